@@ -1,0 +1,333 @@
+"""CPU FP64 oracle for homomorphically compressed XPCS two-time correlation.
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously correct
+reference that the GPU library is checked against.  Only the tests, the smoke
+check and the benchmark's CPU-baseline leg may import it; the library itself
+never does, and this module imports nothing from the library.
+
+Notation (paper: Strempfer et al., "Homomorphic data compression for real
+time photon correlation analysis", arXiv 2407.20356).  The paper writes the
+data as X in R^{N x M}, one flattened image per row (Sec. 2.1, Eq. 2).  Here
+`F` is exactly that array, shape (N, M): frames x pixels.  The pixel-by-frame
+matrix used in the correlation formulas below is X = F^T (M x N).
+
+What is computed, and where it comes from:
+
+* Two-time correlation (Sec. 2.1, Eq. 1): mean over the ROI's pixels of
+  I_t1 * I_t2 divided by the product of the per-frame ROI means.  Written with
+  the integer Gram G_R = X_R^T X_R (Eq. 2 restricted to the ROI's pixels) and
+  the exact per-frame ROI photon sums S_R[t], this is
+  C_R[t1, t2] = |R| * G_R[t1, t2] / (S_R[t1] * S_R[t2]).
+* Compression basis (Sec. 2.1, Eqs. 3 and 6): the leading right singular
+  vectors of the paper's X, i.e. eigenvectors of the pixel Gram ordered by
+  decreasing eigenvalue.  `exact_basis` builds them from the frame Gram
+  F F^T; `randomized_basis` reaches the same subspace approximately with the
+  randomized range finder of Halko, Martinsson & Tropp (SIAM Rev. 2011,
+  Alg. 4.4 subspace iteration + Alg. 5.1 direct SVD).
+* Encoding (Eq. 7): Y_K = X V_K -- here W = F U (N x k), U the pixel basis.
+* Compressed correlation (Eqs. 8-10): the correlation of the decompressed data
+  equals the correlation of the compressed data.  Restricted to an ROI R with
+  the shared basis U, the decompressed ROI data is U_R (U^T X), hence
+  C~_R = |R| * W G_R W^T / (S_R S_R^T) with G_R = U_R^T U_R.
+* g2 (Sec. 3.1, Eq. 12), read as the average of C along its diagonals
+  t2 - t1 = tau over the valid frame pairs.
+* Relaxation fit (Sec. 3.1, Eq. 13): g2(tau) = B + beta * exp(-2 Gamma tau).
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Optional, Tuple
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# ROI bookkeeping (Sec. 2.2: a q-range is a flattened subset of the pixels)
+# ----------------------------------------------------------------------------
+
+
+def roi_pixels(labels: np.ndarray, roi: int) -> np.ndarray:
+    """Indices of the pixels whose label equals `roi`, in increasing order."""
+    return np.flatnonzero(np.asarray(labels) == roi)
+
+
+def roi_pixel_counts(labels: np.ndarray, n_roi: int) -> np.ndarray:
+    """|R| for every ROI (int64)."""
+    lab = np.asarray(labels)
+    return np.array([int(np.count_nonzero(lab == r)) for r in range(n_roi)], dtype=np.int64)
+
+
+def roi_frame_sums(F: np.ndarray, labels: np.ndarray, n_roi: int) -> np.ndarray:
+    """S[r, t] = sum of the counts of frame t over the pixels of ROI r (exact, int64)."""
+    F = np.asarray(F)
+    S = np.zeros((n_roi, F.shape[0]), dtype=np.int64)
+    for r in range(n_roi):
+        px = roi_pixels(labels, r)
+        S[r] = F[:, px].astype(np.int64).sum(axis=1)
+    return S
+
+
+# ----------------------------------------------------------------------------
+# Raw path: exact ROI Gram and its normalisation (Sec. 2.1, Eqs. 1-2)
+# ----------------------------------------------------------------------------
+
+_EXACT_F64 = 2 ** 53
+
+
+def raw_gram(F: np.ndarray, labels: np.ndarray, roi: int, chunk: int = 4096) -> np.ndarray:
+    """G_R = X_R^T X_R as exact int64 (N x N).
+
+    FP64 products of integer-valued arrays are exact while every partial sum
+    stays below 2^53; each pixel chunk is checked against that bound before it
+    is used, then converted to int64 and summed exactly.
+    """
+    F = np.asarray(F)
+    px = roi_pixels(labels, roi)
+    n = F.shape[0]
+    G = np.zeros((n, n), dtype=np.int64)
+    for c0 in range(0, px.size, chunk):
+        sub = F[:, px[c0:c0 + chunk]].astype(np.float64)
+        amax = float(sub.max(initial=0.0))
+        if sub.shape[1] * amax * amax >= _EXACT_F64:
+            raise OverflowError("pixel chunk too large for exact FP64 integer products")
+        G += np.rint(sub @ sub.T).astype(np.int64)
+    return G
+
+
+def normalise_two_time(G: np.ndarray, S: np.ndarray, npix: int) -> np.ndarray:
+    """C[t1, t2] = |R| G[t1, t2] / (S[t1] S[t2]) in FP64 (Eq. 1); NaN where S = 0."""
+    Sd = np.asarray(S, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        C = float(npix) * np.asarray(G, dtype=np.float64) / np.outer(Sd, Sd)
+    bad = Sd == 0.0
+    C[bad, :] = np.nan
+    C[:, bad] = np.nan
+    return C
+
+
+def raw_two_time(F: np.ndarray, labels: np.ndarray, roi: int) -> np.ndarray:
+    """Raw-data two-time correlation of one ROI (Eqs. 1-2), FP64 N x N."""
+    px = roi_pixels(labels, roi)
+    S = np.asarray(F)[:, px].astype(np.int64).sum(axis=1)
+    return normalise_two_time(raw_gram(F, labels, roi), S, px.size)
+
+
+# ----------------------------------------------------------------------------
+# g2 from the two-time matrix (Sec. 3.1, Eq. 12)
+# ----------------------------------------------------------------------------
+
+
+def g2_from_two_time(C: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """g2[tau] = mean of C[t, t + tau] over valid (non-NaN) pairs, tau = 0..N-1.
+
+    Returns (g2, npairs); g2 is NaN where a lag has no valid pair.
+    """
+    C = np.asarray(C, dtype=np.float64)
+    n = C.shape[0]
+    g2 = np.full(n, np.nan)
+    npairs = np.zeros(n, dtype=np.int64)
+    for tau in range(n):
+        d = np.diagonal(C, offset=tau)
+        ok = ~np.isnan(d)
+        npairs[tau] = int(ok.sum())
+        if npairs[tau]:
+            g2[tau] = float(d[ok].sum()) / npairs[tau]
+    return g2, npairs
+
+
+# ----------------------------------------------------------------------------
+# Compression basis (Sec. 2.1, Eqs. 3 and 6)
+# ----------------------------------------------------------------------------
+
+
+def exact_basis(F: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Top-k singular triplets of X = F^T from the exact frame Gram.
+
+    The paper takes the encoding vectors as eigenvectors of the Gram of the
+    data and keeps the K with the largest eigenvalues (Eqs. 3, 6).  The frame
+    Gram F F^T (N x N) is formed exactly, eigendecomposed in FP64, ordered by
+    decreasing eigenvalue, and the pixel-space vectors follow as
+    u_i = X v_i / sigma_i with sigma_i = sqrt(lambda_i).
+
+    Returns U (M x k), sigma (k,), V (N x k) with X ~= U diag(sigma) V^T.
+    """
+    F = np.asarray(F)
+    Fd = F.astype(np.float64)
+    gram = Fd @ Fd.T                      # N x N, exact for integer counts
+    lam, vecs = np.linalg.eigh(gram)      # ascending
+    order = np.argsort(-lam, kind="stable")[:k]
+    lam = np.clip(lam[order], 0.0, None)
+    V = vecs[:, order]
+    sigma = np.sqrt(lam)
+    U = (Fd.T @ V) / sigma
+    return U, sigma, V
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 output for generator state x (Steele, Lea & Flood, OOPSLA 2014).
+
+    One call advances the state by the golden-ratio increment 0x9E3779B97F4A7C15
+    and returns the variant-13 finaliser of the new state.  Arithmetic is
+    modulo 2^64.
+    """
+    with np.errstate(over="ignore"):
+        z = np.asarray(x, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def rademacher_sketch(seed: int, n_frames: int, ell: int) -> np.ndarray:
+    """Omega in {-1, +1}^{N x ell}: sign from the top bit of SplitMix64(seed XOR (i 2^32 + j))."""
+    i = np.arange(n_frames, dtype=np.uint64)[:, None]
+    j = np.arange(ell, dtype=np.uint64)[None, :]
+    ctr = (i << np.uint64(32)) | j
+    h = splitmix64(np.uint64(seed) ^ ctr)
+    top = (h >> np.uint64(63)).astype(np.float64)
+    return 1.0 - 2.0 * top
+
+
+def _orth(A: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the column space of A (Householder QR, LAPACK)."""
+    q, _ = np.linalg.qr(A, mode="reduced")
+    return q
+
+
+def sketch(F: np.ndarray, seed: int, ell: int) -> np.ndarray:
+    """Y0 = X Omega (M x ell), exact for integer counts."""
+    Fd = np.asarray(F).astype(np.float64)
+    return Fd.T @ rademacher_sketch(seed, Fd.shape[0], ell)
+
+
+def randomized_basis(F: np.ndarray, k: int, oversample: int = 16, power_iters: int = 1,
+                     seed: int = 0) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Rank-k basis of X = F^T by randomized subspace iteration, FP64.
+
+    Halko, Martinsson & Tropp (2011): Alg. 4.4 (range finder with q power
+    iterations, re-orthonormalising after every product) followed by Alg. 5.1
+    (SVD of the small projected matrix).  Here the small SVD is taken from the
+    eigendecomposition of W^T W with W = X^T Q, the same Gram-eigenvector
+    construction the paper uses for its full basis (Eq. 3).
+
+    Returns U (M x k), sigma (k,), V (N x k), sigma descending.
+    """
+    Fd = np.asarray(F).astype(np.float64)
+    n, m = Fd.shape
+    ell = k + oversample
+    if ell > min(m, n):
+        raise ValueError("k + oversample must not exceed min(M, N)")
+    X = Fd.T                                          # M x N
+    Q = _orth(X @ rademacher_sketch(seed, n, ell))    # range of X Omega
+    for _ in range(power_iters):
+        Qz = _orth(X.T @ Q)                           # N x ell
+        Q = _orth(X @ Qz)                             # M x ell
+    W = X.T @ Q                                       # N x ell, the projected data
+    lam, P = np.linalg.eigh(W.T @ W)
+    order = np.argsort(-lam, kind="stable")[:k]
+    lam = np.clip(lam[order], 0.0, None)
+    P = P[:, order]
+    sigma = np.sqrt(lam)
+    U = Q @ P
+    V = (W @ P) / sigma
+    return U, sigma, V
+
+
+# ----------------------------------------------------------------------------
+# Compressed-domain correlation (Eqs. 7-10, per ROI)
+# ----------------------------------------------------------------------------
+
+
+def encode(F: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """W = X^T U (N x k), the compressed data of Eq. 7 (paper's Y_K)."""
+    return np.asarray(F).astype(np.float64) @ np.asarray(U, dtype=np.float64)
+
+
+def roi_basis_gram(U: np.ndarray, labels: np.ndarray, roi: int) -> np.ndarray:
+    """G_R = U_R^T U_R (k x k): the basis restricted to the ROI's pixels."""
+    Ur = np.asarray(U, dtype=np.float64)[roi_pixels(labels, roi)]
+    return Ur.T @ Ur
+
+
+def compressed_two_time_from_factors(W: np.ndarray, G_R: np.ndarray, S: np.ndarray,
+                                     npix: int) -> np.ndarray:
+    """C~ = |R| W G_R W^T / (S S^T) in FP64; NaN where S = 0."""
+    W = np.asarray(W, dtype=np.float64)
+    return normalise_two_time(W @ np.asarray(G_R, dtype=np.float64) @ W.T, S, npix)
+
+
+def compressed_two_time(F: np.ndarray, U: np.ndarray, labels: np.ndarray, roi: int) -> np.ndarray:
+    """Compressed two-time correlation of ROI `roi` for the pixel basis U (Eqs. 8-10).
+
+    S is the exact raw ROI photon sum per frame, recorded while encoding.
+    """
+    px = roi_pixels(labels, roi)
+    S = np.asarray(F)[:, px].astype(np.int64).sum(axis=1)
+    W = encode(F, U)
+    return compressed_two_time_from_factors(W, roi_basis_gram(U, labels, roi), S, px.size)
+
+
+def compressed_two_time_explicit(F: np.ndarray, U: np.ndarray, labels: np.ndarray,
+                                 roi: int) -> np.ndarray:
+    """Same quantity through the decompressed data of Eq. 8 (small inputs only).
+
+    X~ = U U^T X is formed explicitly; the ROI rows of X~ then go through the
+    raw formula of Eqs. 1-2 (with the exact raw S), as in Eq. 9.
+    """
+    Fd = np.asarray(F).astype(np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    Fdec = (Fd @ U) @ U.T                 # rows = decompressed frames (N x M)
+    px = roi_pixels(labels, roi)
+    sub = Fdec[:, px]
+    S = np.asarray(F)[:, px].astype(np.int64).sum(axis=1)
+    return normalise_two_time(sub @ sub.T, S, px.size)
+
+
+def g2_fft_from_factors(W: np.ndarray, G_R: np.ndarray, S: np.ndarray,
+                        npix: int) -> Tuple[np.ndarray, np.ndarray]:
+    """g2 of C~ without forming C~, by FFT cross-correlation of the k channels.
+
+    With z_t = sqrt(|R|) W[t] / S[t] (zero where S[t] = 0) and y_t = G_R z_t,
+    sum_t C~[t, t + tau] = sum_j sum_t y_j(t) z_j(t + tau), a cross-correlation
+    of k pairs of length-N sequences.  npairs counts frame pairs with S > 0.
+    """
+    W = np.asarray(W, dtype=np.float64)
+    Sd = np.asarray(S, dtype=np.float64)
+    ok = Sd > 0
+    n = W.shape[0]
+    z = np.zeros_like(W)
+    z[ok] = math.sqrt(npix) * W[ok] / Sd[ok, None]
+    y = z @ np.asarray(G_R, dtype=np.float64)
+    L = 1 << int(math.ceil(math.log2(2 * n)))
+    fy = np.fft.rfft(y, L, axis=0)
+    fz = np.fft.rfft(z, L, axis=0)
+    xc = np.fft.irfft(np.conj(fy) * fz, L, axis=0)[:n].sum(axis=1)   # lag tau >= 0
+    okf = ok.astype(np.float64)
+    cnt = np.fft.irfft(np.conj(np.fft.rfft(okf, L)) * np.fft.rfft(okf, L), L)[:n]
+    npairs = np.rint(cnt).astype(np.int64)
+    g2 = np.full(n, np.nan)
+    nz = npairs > 0
+    g2[nz] = xc[nz] / npairs[nz]
+    return g2, npairs
+
+
+# ----------------------------------------------------------------------------
+# Relaxation fit (Sec. 3.1, Eq. 13)
+# ----------------------------------------------------------------------------
+
+
+def siegert_fit(g2: np.ndarray, taus: np.ndarray,
+                p0: Optional[Tuple[float, float, float]] = None) -> Tuple[float, float, float]:
+    """Least-squares fit of g2(tau) = B + beta * exp(-2 Gamma tau); returns (B, beta, Gamma)."""
+    from scipy.optimize import least_squares
+
+    taus = np.asarray(taus, dtype=np.float64)
+    y = np.asarray(g2, dtype=np.float64)
+    if p0 is None:
+        p0 = (float(y[-1]), float(max(y[0] - y[-1], 1e-3)), 1.0 / max(taus.mean(), 1.0))
+
+    def resid(p):
+        return p[0] + p[1] * np.exp(-2.0 * p[2] * taus) - y
+
+    sol = least_squares(resid, np.asarray(p0, dtype=np.float64), method="lm")
+    B, beta, gamma = sol.x
+    return float(B), float(beta), float(gamma)

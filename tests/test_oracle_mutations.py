@@ -1,0 +1,107 @@
+"""Planted mistakes in the oracle must each be caught by one of its pins.
+
+Every case replaces one oracle function by a plausibly wrong variant (dropped
+factor, wrong ordering, wrong divisor, missing ROI restriction, ...) for the
+duration of the test and asserts that the corresponding pin fails.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import xpcs_oracle as OX
+from tests import test_oracle_pins as pins
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _expect_pin_failure(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_dropped_pixel_count_in_normalisation(monkeypatch, golden):
+    orig = OX.normalise_two_time
+    monkeypatch.setattr(OX, "normalise_two_time", lambda G, S, npix: orig(G, S, 1))
+    _expect_pin_failure(pins.test_hand_worked_two_time, golden)
+
+
+def test_g2_divides_by_frame_count(monkeypatch, golden):
+    def wrong(C):
+        C = np.asarray(C, dtype=np.float64)
+        n = C.shape[0]
+        g2 = np.array([np.nansum(np.diagonal(C, t)) / n for t in range(n)])
+        return g2, np.array([n - t for t in range(n)], dtype=np.int64)
+    monkeypatch.setattr(OX, "g2_from_two_time", wrong)
+    monkeypatch.setattr(O, "g2_from_two_time", wrong)
+    _expect_pin_failure(pins.test_hand_worked_two_time, golden)
+
+
+def test_g2_counts_invalid_pairs(monkeypatch):
+    def wrong(C):
+        C = np.asarray(C, dtype=np.float64)
+        n = C.shape[0]
+        g2 = np.array([np.nanmean(np.diagonal(C, t)) for t in range(n)])
+        return g2, np.array([n - t for t in range(n)], dtype=np.int64)
+    monkeypatch.setattr(O, "g2_from_two_time", wrong)
+    _expect_pin_failure(pins.test_empty_frames_are_nan_and_skipped)
+
+
+def test_basis_keeps_smallest_eigenvalues(monkeypatch):
+    def wrong(F, k):
+        Fd = np.asarray(F).astype(np.float64)
+        lam, vecs = np.linalg.eigh(Fd @ Fd.T)
+        V = vecs[:, :k]
+        sigma = np.sqrt(np.clip(lam[:k], 1e-300, None))
+        return (Fd.T @ V) / sigma, sigma, V
+    monkeypatch.setattr(O, "exact_basis", wrong)
+    _expect_pin_failure(pins.test_exact_basis_matches_library_svd_and_eckart_young)
+
+
+def test_compressed_ignores_roi_restriction(monkeypatch):
+    # Using the full-basis Gram (identity) instead of U_R^T U_R for every ROI.
+    monkeypatch.setattr(OX, "roi_basis_gram",
+                        lambda U, labels, roi: np.eye(np.asarray(U).shape[1]))
+    _expect_pin_failure(pins.test_full_rank_compression_is_lossless)
+
+
+def test_compressed_normalised_by_whole_detector_sum(monkeypatch):
+    orig = OX.compressed_two_time_from_factors
+
+    def wrong(F, U, labels, roi):
+        px = OX.roi_pixels(labels, roi)
+        S_all = np.asarray(F).astype(np.int64).sum(axis=1)
+        return orig(OX.encode(F, U), OX.roi_basis_gram(U, labels, roi), S_all, px.size)
+    monkeypatch.setattr(O, "compressed_two_time", wrong)
+    _expect_pin_failure(pins.test_full_rank_compression_is_lossless)
+
+
+def test_right_vectors_not_divided_by_sigma(monkeypatch):
+    orig = OX.randomized_basis
+
+    def wrong(F, k, oversample=16, power_iters=1, seed=0):
+        U, s, V = orig(F, k, oversample, power_iters, seed)
+        return U, s, V * s
+    monkeypatch.setattr(O, "randomized_basis", wrong)
+    _expect_pin_failure(pins.test_randomized_basis_near_optimal)
+
+
+def test_splitmix64_wrong_shift(monkeypatch):
+    def wrong(x):
+        with np.errstate(over="ignore"):
+            z = np.asarray(x, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+            z = (z ^ (z >> np.uint64(29))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            return z ^ (z >> np.uint64(31))
+    monkeypatch.setattr(O, "splitmix64", wrong)
+    _expect_pin_failure(pins.test_splitmix64_published_outputs)
+
+
+def test_fft_g2_with_reversed_lag(monkeypatch):
+    orig = OX.g2_fft_from_factors
+
+    def wrong(W, G_R, S, npix):
+        g2, n = orig(W, G_R, S, npix)
+        return g2[::-1].copy(), n
+    monkeypatch.setattr(O, "g2_fft_from_factors", wrong)
+    _expect_pin_failure(pins.test_g2_fft_matches_diagonal_mean)
