@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Frames/s of compress + two-time correlation (compressed vs raw) on one MI355X.
+
+One step = compress_frames (basis from the data, randomized subspace
+iteration) + correlate_two_time for every q-ROI with the full C written in
+FP32 and g2 fused into the same pass, on the 512 x 512 px x 10,000-frame,
+36-annulus workload (uint16 counts, k = 64 by default).  The raw path
+(exact int8 Gram of the same frames, same C and g2 outputs) is timed beside
+it.  Inputs are generated on the device before timing; nothing is copied
+from the host inside the timed region.
+
+Prints one JSON line (see the README of the measurement in the design doc).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frames/sec compress+two-time C (compressed vs raw, 1 GPU) at 1e-3 rel err; p99 latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_I8_TOPS = 5000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    i = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[i]
+
+
+def cpu_baseline(frames_host, labels, n_roi, k, seed, n_sample):
+    """Time the FP64 oracle on the first n_sample frames: basis + C~ + g2 for every ROI."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    F = np.ascontiguousarray(frames_host[:n_sample])
+    t0 = time.perf_counter()
+    U, s, V = O.randomized_basis(F, k, 16, 1, seed=seed)
+    W = O.encode(F, U)
+    S = O.roi_frame_sums(F, labels, n_roi)
+    npix = O.roi_pixel_counts(labels, n_roi)
+    for r in range(n_roi):
+        C = O.compressed_two_time_from_factors(W, O.roi_basis_gram(U, labels, r), S[r], int(npix[r]))
+        O.g2_from_two_time(C)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_sample} frames of the same series ({F.shape[1]} px, {n_roi} ROIs, k={k}): "
+                      f"FP64 randomized basis + compressed C and g2 for every ROI, {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="det512_10k_36roi")
+    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--raw-steps", type=int, default=3)
+    ap.add_argument("--no-raw", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-frames", type=int, default=1000)
+    ap.add_argument("--seed", type=int, default=1000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2407_20356_amd import api
+
+    spec = synth.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    M, N, n_roi, k = spec.n_pixels, spec.n_frames, spec.n_roi, args.k
+    labels = synth.workload_labels(spec)
+    tau = synth.workload_tau(spec, labels)
+    log(f"generating {args.workload}: {N} frames x {M} px ({spec.dtype}) on {dev}")
+    t = time.perf_counter()
+    frames = synth.speckle_frames_torch(M, N, spec.mu, spec.beta, tau, spec.dtype, seed=args.seed,
+                                        device=dev, max_count=spec.max_count)
+    labels_d = torch.from_numpy(labels).to(dev)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t:.1f} s")
+
+    ctx = api.Context(0)
+    f = api.Factors.empty(M, N, k, n_roi, dev)
+    C = torch.empty((n_roi, N, N), dtype=torch.float32, device=dev)
+    g2 = torch.empty((n_roi, N), dtype=torch.float64, device=dev)
+    npairs = torch.empty((n_roi, N), dtype=torch.int64, device=dev)
+
+    def step_compressed():
+        api.compress_frames(ctx, frames, labels_d, n_roi, k=k, seed=7, out=f)
+        api.correlate_two_time(ctx, f, C=C, g2=g2, npairs=npairs)
+
+    def step_raw():
+        api.correlate_two_time_raw(ctx, frames, labels_d, n_roi, C=C, g2=g2, npairs=npairs)
+
+    def timed(fn, steps, warmup, name):
+        for i in range(warmup):
+            fn()
+        ctx.sync()
+        torch.cuda.synchronize()
+        ctx.enable_phase_timing(True)
+        stream = torch.cuda.current_stream(dev)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ctx.sync()
+        per = [a.elapsed_time(b) for a, b in evs]
+        phases = ctx.phase_times()
+        ctx.enable_phase_timing(False)
+        log(f"{name}: {steps} steps, mean {sum(per) / len(per):.3f} ms, wall {1e3 * wall / steps:.3f} ms/step")
+        return per, wall, phases
+
+    log("compressed path: warmup + timed steps")
+    per_c, wall_c, ph_c = timed(step_compressed, args.steps, args.warmup, "compressed")
+    ms_c = 1e3 * wall_c / args.steps
+
+    # light parity spot checks on this run (sampled frames; the full checks are in tests/)
+    import oracle as O
+    rng = np.random.default_rng(0)
+    ts = np.sort(rng.choice(N, size=16, replace=False))
+    Fs = frames[torch.from_numpy(ts).to(dev)].cpu().numpy()
+    U = f.U.cpu().numpy().T.astype(np.float64)
+    Ws = Fs.astype(np.float64) @ U
+    Wg = (f.V.cpu().numpy().T.astype(np.float64) * f.sigma.cpu().numpy())[ts]
+    S_ok = bool(np.array_equal(f.roi_sum.cpu().numpy()[:, ts], O.roi_frame_sums(Fs, labels, n_roi)))
+    w_err = float(np.linalg.norm(Wg - Ws) / np.linalg.norm(Ws))
+    orth = float(np.abs(U.T @ U - np.eye(k)).max())
+    Cs = C[:, torch.from_numpy(ts).to(dev)][:, :, torch.from_numpy(ts).to(dev)].cpu().numpy()
+    npix = O.roi_pixel_counts(labels, n_roi)
+    Sg = O.roi_frame_sums(Fs, labels, n_roi).astype(np.float64)
+    c_err = 0.0
+    for r in range(n_roi):
+        Ur = U[labels == r]
+        Cr = npix[r] * (Ws @ (Ur.T @ Ur) @ Ws.T) / np.outer(Sg[r], Sg[r])
+        ok = np.isfinite(Cr)
+        c_err = max(c_err, float(np.max(np.abs(Cs[r][ok] - Cr[ok]) / np.maximum(np.abs(Cr[ok]), 0.1))))
+    parity = {"roi_sum_exact": S_ok, "w_rel_err": w_err, "u_orthonormality": orth,
+              "c_identity_max_rel_err": c_err, "sampled_frames": int(len(ts))}
+    log(f"parity spot checks: {parity}")
+
+    raw = None
+    if not args.no_raw:
+        log("raw path: warmup + timed steps")
+        per_r, wall_r, ph_r = timed(step_raw, args.raw_steps, 1, "raw")
+        ms_r = 1e3 * wall_r / args.raw_steps
+        raw = {"frames_per_s": N / (ms_r / 1e3), "ms_per_step": ms_r, "p50_ms": percentile(per_r, 50),
+               "p99_ms": percentile(per_r, 99), "steps": args.raw_steps,
+               "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_r.items()}}
+
+    # per-kernel achieved rates from the HIP events recorded around each phase
+    esz = 1 if spec.dtype == "u8" else 2
+    x_bytes = N * M * esz
+    kp = (k + 31) // 32 * 32
+    nb = (N + 127) // 128
+    algo = {
+        # bytes each launch must move: the frames it reads / the matrix it writes
+        "proj_frames": (x_bytes, "hbm"),
+        "proj_pixels": (x_bytes, "hbm"),
+        "lowrank_tiles": (n_roi * N * N * 4 + 4 * n_roi * N * kp * 2, "hbm"),
+    }
+    kernels = {}
+    for name, (bytes_per_launch, bound) in algo.items():
+        if name in ph_c:
+            tot_ms, cnt = ph_c[name]
+            avg_ms = tot_ms / cnt
+            kernels[name] = {"avg_ms": avg_ms, "launches_per_step": cnt / args.steps,
+                             "achieved_GBs": bytes_per_launch / (avg_ms / 1e3) / 1e9,
+                             "bytes_per_launch": bytes_per_launch}
+    dom = max(kernels, key=lambda kk: kernels[kk]["avg_ms"] * kernels[kk]["launches_per_step"])
+    dk = kernels[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(dk["achieved_GBs"] / PEAK_HBM_GBS, 4), "traffic": None}
+    if raw is not None and "raw_gram_tiles" in ph_r:
+        tot_ms, cnt = ph_r["raw_gram_tiles"]
+        npix_all = O.roi_pixel_counts(labels, n_roi)
+        ops = 2.0 * N * N * float(npix_all.sum())
+        raw["gram_int8_TOPs"] = ops / (tot_ms / cnt / 1e3) / 1e12
+        raw["gram_frac_of_int8_peak"] = raw["gram_int8_TOPs"] / PEAK_I8_TOPS
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on the first {args.cpu_sample_frames} frames")
+        host = frames[:args.cpu_sample_frames].cpu().numpy()
+        cpu = cpu_baseline(host, labels, n_roi, k, 7, args.cpu_sample_frames)
+        log(f"cpu baseline: {cpu['value']:.1f} frames/s in {cpu['seconds']:.1f} s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": N / (ms_c / 1e3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_c,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "pixels": M, "frames": N, "count_dtype": spec.dtype,
+                   "n_roi": n_roi, "k": k, "oversample": 16, "power_iters": 1, "c_dtype": "f32",
+                   "g2": "fused"},
+        "p50_ms": percentile(per_c, 50),
+        "p99_ms": percentile(per_c, 99),
+        "raw": raw,
+        "speedup_vs_raw": (raw["ms_per_step"] / ms_c) if raw else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * xpcs.h -- C ABI of the MI355X (gfx950) library for homomorphically compressed
+ * XPCS two-time correlation.
+ *
+ * Method: Strempfer et al., "Homomorphic data compression for real time photon
+ * correlation analysis" (arXiv 2407.20356).  The two-time correlation of the
+ * photon counts (Sec. 2.1, Eqs. 1-2) is computed either from the raw frames or
+ * directly from a low-rank compression of them (Sec. 2.1, Eqs. 3-10) without
+ * decompressing, and g2 is taken from its diagonals (Sec. 3.1, Eq. 12).
+ *
+ * Notation.  A series of N frames of M pixels is passed frame-contiguous: frame
+ * t occupies elements [t*M, (t+1)*M) of `frames` (the paper's X, one flattened
+ * image per row).  Read column-major, the same buffer is the pixel-by-frame
+ * matrix X (M x N) of the formulas below.  A q-ROI R is a set of pixels given by
+ * an int32 label per pixel (label r selects ROI r, -1 selects none; Sec. 2.2
+ * compresses and analyses such pixel subsets directly).
+ *
+ * Conventions for every entry point.
+ *  - Array arguments are DEVICE pointers owned by the caller; the library never
+ *    frees, reallocates or retains them after the call returns.  Memory owned by
+ *    the library is the workspace inside an xpcs_ctx (grown on demand, bounded by
+ *    the context's HBM budget, released by xpcs_destroy).
+ *  - Work is enqueued on the context's stream (xpcs_set_stream) and the call
+ *    returns without waiting for the device, except where noted.  Calls on one
+ *    context must be ordered on that stream: they share its workspace.
+ *  - The return value is an xpcs_status.  A negative value means the call was
+ *    rejected on the host and nothing was enqueued; xpcs_last_error() then
+ *    describes the problem.  Conditions only the device can detect (a label
+ *    outside [-1, n_roi), a count too large for the exact integer path, a
+ *    numerically rank-deficient sketch) raise a device flag that the next
+ *    xpcs_sync() reports.
+ *  - Frames whose ROI photon sum is zero have no defined correlation: their rows
+ *    and columns of C are NaN and they are left out of g2 and of its pair counts.
+ */
+#ifndef XPCS_H
+#define XPCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xpcs_status;
+#define XPCS_OK 0
+#define XPCS_EINVAL (-1)        /* bad argument (null pointer, size, label, dtype)      */
+#define XPCS_ENOMEM (-2)        /* device allocation failed                             */
+#define XPCS_ERANGE (-3)        /* a count exceeds what the exact integer path holds    */
+#define XPCS_EBUDGET (-4)       /* the workspace would exceed the context's HBM budget  */
+#define XPCS_EDEVICE (-5)       /* HIP runtime error or a failed device-side step      */
+#define XPCS_EUNSUPPORTED (-6)  /* valid request outside what this build implements    */
+
+/* element type of the frames */
+#define XPCS_U8 1
+#define XPCS_U16 2
+/* element type of a two-time matrix */
+#define XPCS_F32 10
+#define XPCS_F64 11
+/* arithmetic of the compression products (FP32 accumulation in every case) */
+#define XPCS_PREC_BF16 0
+
+/* `roi` argument selecting every ROI in one call */
+#define XPCS_ALL_ROIS (-1)
+
+typedef struct xpcs_ctx xpcs_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * library-owned workspace (0 = no bound).  *out receives the context. */
+xpcs_status xpcs_create(int device, size_t hbm_budget_bytes, xpcs_ctx **out);
+
+/* Destroy a context: waits for its stream, frees its workspace.  NULL is a no-op. */
+void xpcs_destroy(xpcs_ctx *ctx);
+
+/* Bind the stream (a hipStream_t, NULL = the default stream) subsequent calls
+ * enqueue on, e.g. torch.cuda.current_stream().cuda_stream. */
+xpcs_status xpcs_set_stream(xpcs_ctx *ctx, void *hip_stream);
+
+/* Wait for the context's stream, then report and clear device-side flags.
+ * Returns XPCS_OK, XPCS_ERANGE, XPCS_EINVAL or XPCS_EDEVICE. */
+xpcs_status xpcs_sync(xpcs_ctx *ctx);
+
+/* Message for the last error on this context ("" if none).  Owned by the context. */
+const char *xpcs_last_error(const xpcs_ctx *ctx);
+
+/* Bytes of device workspace the context currently holds. */
+size_t xpcs_workspace_bytes(const xpcs_ctx *ctx);
+
+/* Diagnostics: device time per kernel phase.  When enabled (which also clears
+ * earlier records), every entry point records a pair of HIP events on the
+ * context's stream around each of its kernel phases.  xpcs_phase_times waits
+ * for the stream and fills, for up to `cap` distinct phase names, the name
+ * (NUL-terminated, at most 31 characters, in names[i*32]), the summed device
+ * milliseconds and the number of launches since timing was enabled; *n_out
+ * receives the number of phases filled.  names, ms and launches are host
+ * memory of at least cap entries.  Recording costs a few microseconds of host
+ * time per phase; it does not stall the device. */
+xpcs_status xpcs_enable_phase_timing(xpcs_ctx *ctx, int32_t enable);
+xpcs_status xpcs_phase_times(xpcs_ctx *ctx, int32_t cap, char *names, double *ms, int64_t *launches,
+                             int32_t *n_out);
+
+/* Compressed state of one series: X ~= U diag(sigma) V^T plus the per-ROI data
+ * the compressed correlation needs.  All buffers are caller-allocated device
+ * memory of the sizes stated; compress_frames fills them.
+ *   U        M x k floats, column-major (U[j*M + p]): the pixel basis, orthonormal
+ *            columns -- the paper's encoding matrix V_K (Eq. 6).
+ *   sigma    k doubles, descending: singular values (the paper calls the diagonal
+ *            of Sigma its eigenvalues, Sec. 2.1 below Eq. 3).
+ *   V        N x k floats, column-major (V[j*N + t]); W = V diag(sigma) = X^T U is
+ *            the compressed data, the paper's Y_K (Eq. 7).
+ *   roi_npix n_roi int64: pixel count |R| of each ROI.
+ *   roi_sum  n_roi x N int64 (roi_sum[r*N + t]): exact photon sum of frame t over
+ *            ROI r, recorded from the raw counts while encoding.
+ *   roi_gram n_roi x k x k doubles (roi_gram[(r*k + a)*k + b]): G_R = U_R^T U_R,
+ *            the basis restricted to the ROI's pixels. */
+typedef struct {
+    int64_t M, N;
+    int32_t k, n_roi;
+    float *U;
+    double *sigma;
+    float *V;
+    int64_t *roi_npix;
+    int64_t *roi_sum;
+    double *roi_gram;
+} xpcs_factors;
+
+/* Options of compress_frames.
+ *   k            rank kept (the paper's K, Eq. 6), 1 <= k.
+ *   oversample   extra sketch columns p (sketch width l = k + p); 16 by default.
+ *   power_iters  subspace iterations q (0 or 1).
+ *   precision    XPCS_PREC_BF16.
+ *   seed         seed of the Rademacher sketch Omega[t][j] = +-1, sign = top bit of
+ *                SplitMix64(seed XOR (t*2^32 + j)).
+ *   basis        NULL: offline mode, the basis is computed from these frames
+ *                (Sec. 2.2, "offline").  Non-NULL: online mode, an M x k
+ *                column-major device basis generated beforehand (Sec. 2.2,
+ *                "online"); it is copied to out->U and the frames are only
+ *                encoded; sigma_j = |W e_j| and V = W diag(1/sigma). */
+typedef struct {
+    int32_t k;
+    int32_t oversample;
+    int32_t power_iters;
+    int32_t precision;
+    uint64_t seed;
+    const float *basis;
+} xpcs_compress_opts;
+
+/* Compress N frames of M pixels (Sec. 2.1, Eqs. 3-7; Sec. 2.2).
+ * Offline mode: a rank-k basis of X by randomized subspace iteration (Halko,
+ * Martinsson & Tropp 2011, Algs. 4.4 + 5.1): Y = X Omega, orthonormalise,
+ * q x (Z = X^T Q, Y = X Z), orthonormalise, W_l = X^T Q, then the FP64
+ * eigendecomposition of W_l^T W_l ranks the l directions and the top k are
+ * kept.  The products with X run on BF16 MFMA with FP32 accumulation; the final
+ * W = X^T U carries a second (residual) BF16 term so that W is accurate to FP32
+ * level; Gram, Cholesky and eigen steps are FP64.
+ * frames: device, dtype XPCS_U8 or XPCS_U16, N*M elements, frame-contiguous.
+ * roi_label: device int32[M], values in [-1, n_roi).
+ * out: caller-allocated factors with out->M == M, out->N == N, out->k == opts->k,
+ *      out->n_roi == n_roi.
+ * Errors: EINVAL (null, sizes, k + oversample > min(M, N) offline), EUNSUPPORTED
+ * (k + oversample > 192 offline), EBUDGET, ENOMEM. */
+xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M,
+                            int64_t N, const int32_t *roi_label, int32_t n_roi,
+                            const xpcs_compress_opts *opts, xpcs_factors *out);
+
+/* Two-time correlation on the compressed data (Sec. 2.1, Eqs. 8-10 per ROI):
+ *   C~_R[t1][t2] = |R| * (W G_R W^T)[t1][t2] / (S_R[t1] S_R[t2]),  W = V diag(sigma),
+ * for frames t1, t2 in the window [t0, t1) and ROI `roi` (or every ROI).
+ * C: device, (t1-t0) x (t1-t0) elements of c_dtype with row stride ldc; for
+ *    XPCS_ALL_ROIS, n_roi such matrices, ROI r at C + r*(t1-t0)*ldc elements.
+ *    May be NULL (g2 only, no matrix is written).  C is exactly symmetric.
+ * g2, npairs: device, (t1-t0) entries per ROI (ROI-major for XPCS_ALL_ROIS), or
+ *    NULL.  g2[tau] = mean of C[t][t+tau] over the valid pairs in the window
+ *    (Sec. 3.1, Eq. 12 read as the mean along C's diagonals), fused into the
+ *    tile pass; npairs[tau] = number of those pairs.
+ * Arithmetic: split-BF16 MFMA products (three terms) with FP32 accumulation.
+ * Errors: EINVAL (null factors, window, ldc, roi), EBUDGET, ENOMEM. */
+xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0,
+                               int64_t t1, void *C, int32_t c_dtype, int64_t ldc, double *g2,
+                               int64_t *npairs);
+
+/* Two-time correlation from the raw frames (Sec. 2.1, Eqs. 1-2 per ROI), the path
+ * the compressed correlation replaces:
+ *   C_R[t1][t2] = |R| * G_R[t1][t2] / (S_R[t1] S_R[t2]),  G_R = X_R^T X_R exact.
+ * The ROI pixels are gathered once into int8 and G_R runs on int8 MFMA with
+ * int32 accumulation (int64 across pixel chunks), so G_R is exact; this needs
+ * every count <= 127, otherwise the device flag XPCS_ERANGE is raised.
+ * Arguments as correlate_two_time; gram_out (device int64, same layout as C with
+ * row stride t1-t0, or NULL) receives the exact G_R. */
+xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M,
+                                   int64_t N, const int32_t *roi_label, int32_t n_roi,
+                                   int32_t roi, int64_t t0, int64_t t1, void *C, int32_t c_dtype,
+                                   int64_t ldc, double *g2, int64_t *npairs, int64_t *gram_out);
+
+/* g2 from a two-time matrix already in device memory (Sec. 3.1, Eq. 12):
+ * g2[tau] = mean of C[t][t+tau] over the non-NaN entries, tau = 0..n-1, and
+ * npairs[tau] their number (g2 is NaN where npairs is 0).  Only the upper
+ * triangle of C is read.  C: device, n x n of c_dtype, row stride ldc. */
+xpcs_status g2_from_two_time(xpcs_ctx *ctx, const void *C, int32_t c_dtype, int64_t n,
+                             int64_t ldc, double *g2, int64_t *npairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XPCS_H */

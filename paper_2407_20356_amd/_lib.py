@@ -1,0 +1,91 @@
+"""ctypes declarations of the C ABI in include/xpcs.h (libxpcs.so, built in-tree).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libxpcs.so")
+
+XPCS_OK = 0
+XPCS_EINVAL = -1
+XPCS_ENOMEM = -2
+XPCS_ERANGE = -3
+XPCS_EBUDGET = -4
+XPCS_EDEVICE = -5
+XPCS_EUNSUPPORTED = -6
+STATUS_NAMES = {0: "XPCS_OK", -1: "XPCS_EINVAL", -2: "XPCS_ENOMEM", -3: "XPCS_ERANGE",
+                -4: "XPCS_EBUDGET", -5: "XPCS_EDEVICE", -6: "XPCS_EUNSUPPORTED"}
+
+XPCS_U8 = 1
+XPCS_U16 = 2
+XPCS_F32 = 10
+XPCS_F64 = 11
+XPCS_PREC_BF16 = 0
+XPCS_ALL_ROIS = -1
+
+
+class XpcsFactors(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int64), ("N", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("n_roi", ctypes.c_int32),
+        ("U", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("V", ctypes.c_void_p),
+        ("roi_npix", ctypes.c_void_p), ("roi_sum", ctypes.c_void_p), ("roi_gram", ctypes.c_void_p),
+    ]
+
+
+class XpcsCompressOpts(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32), ("oversample", ctypes.c_int32),
+        ("power_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("basis", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_ST = ctypes.c_int32
+
+SIGNATURES = {
+    "xpcs_create": (_ST, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "xpcs_destroy": (None, [_P]),
+    "xpcs_set_stream": (_ST, [_P, _P]),
+    "xpcs_sync": (_ST, [_P]),
+    "xpcs_last_error": (ctypes.c_char_p, [_P]),
+    "xpcs_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "compress_frames": (_ST, [_P, _P, _I32, _I64, _I64, _P, _I32,
+                              ctypes.POINTER(XpcsCompressOpts), ctypes.POINTER(XpcsFactors)]),
+    "correlate_two_time": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _I32, _I64,
+                                 _P, _P]),
+    "correlate_two_time_raw": (_ST, [_P, _P, _I32, _I64, _I64, _P, _I32, _I32, _I64, _I64, _P, _I32,
+                                     _I64, _P, _P, _P]),
+    "g2_from_two_time": (_ST, [_P, _P, _I32, _I64, _I64, _P, _P]),
+    "xpcs_enable_phase_timing": (_ST, [_P, _I32]),
+    "xpcs_phase_times": (_ST, [_P, _I32, _P, _P, _P, ctypes.POINTER(_I32)]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libxpcs.so once; raise ImportError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2407_20356_amd.build` "
+            "(the library has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

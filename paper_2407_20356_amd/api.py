@@ -1,0 +1,231 @@
+"""Python binding of the C ABI (include/xpcs.h): argument marshalling only.
+
+torch supplies device memory and the HIP stream; every step of the
+computation runs in libxpcs.so.  Function names follow the C entry points.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+class XpcsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _frame_dtype(frames: torch.Tensor) -> int:
+    if frames.dtype == torch.uint8:
+        return L.XPCS_U8
+    if frames.dtype == torch.uint16:
+        return L.XPCS_U16
+    raise TypeError("frames must be uint8 or uint16")
+
+
+def _check_device(t: torch.Tensor, name: str, device: torch.device):
+    if t.device != device:
+        raise ValueError(f"{name} must live on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """Owns an xpcs_ctx (workspace + device flags) on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.lib.xpcs_create(device, hbm_budget_bytes, ctypes.byref(h))
+        if st != L.XPCS_OK:
+            raise XpcsError(st, "xpcs_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.xpcs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def bind_stream(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.check(self.lib.xpcs_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream)))
+
+    def check(self, status: int):
+        if status != L.XPCS_OK:
+            msg = self.lib.xpcs_last_error(self.handle)
+            raise XpcsError(status, msg.decode() if msg else "")
+
+    def sync(self):
+        self.check(self.lib.xpcs_sync(self.handle))
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.xpcs_workspace_bytes(self.handle))
+
+    def enable_phase_timing(self, enable: bool = True):
+        """Record HIP events around every kernel phase (also clears earlier records)."""
+        self.check(self.lib.xpcs_enable_phase_timing(self.handle, 1 if enable else 0))
+
+    def phase_times(self, cap: int = 64):
+        """{phase: (total_ms, launches)} since timing was enabled (waits for the stream)."""
+        names = ctypes.create_string_buffer(32 * cap)
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        self.check(self.lib.xpcs_phase_times(self.handle, cap, names, ms, cnt, ctypes.byref(n)))
+        out = {}
+        for i in range(n.value):
+            nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[i], cnt[i])
+        return out
+
+
+@dataclass
+class Factors:
+    """Compressed state (xpcs_factors): torch device tensors plus sizes."""
+
+    M: int
+    N: int
+    k: int
+    n_roi: int
+    U: torch.Tensor          # (k, M) float32: row j = basis column j (column-major M x k)
+    sigma: torch.Tensor      # (k,) float64
+    V: torch.Tensor          # (k, N) float32: row j = right vector j (column-major N x k)
+    roi_npix: torch.Tensor   # (n_roi,) int64
+    roi_sum: torch.Tensor    # (n_roi, N) int64
+    roi_gram: torch.Tensor   # (n_roi, k, k) float64
+
+    @staticmethod
+    def empty(M: int, N: int, k: int, n_roi: int, device) -> "Factors":
+        return Factors(
+            M, N, k, n_roi,
+            torch.empty((k, M), dtype=torch.float32, device=device),
+            torch.empty((k,), dtype=torch.float64, device=device),
+            torch.empty((k, N), dtype=torch.float32, device=device),
+            torch.empty((n_roi,), dtype=torch.int64, device=device),
+            torch.empty((n_roi, N), dtype=torch.int64, device=device),
+            torch.empty((n_roi, k, k), dtype=torch.float64, device=device),
+        )
+
+    def struct(self) -> L.XpcsFactors:
+        return L.XpcsFactors(self.M, self.N, self.k, self.n_roi,
+                             self.U.data_ptr(), self.sigma.data_ptr(), self.V.data_ptr(),
+                             self.roi_npix.data_ptr(), self.roi_sum.data_ptr(), self.roi_gram.data_ptr())
+
+
+def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int, k: int,
+                    oversample: int = 16, power_iters: int = 1, seed: int = 0,
+                    basis: Optional[torch.Tensor] = None, out: Optional[Factors] = None) -> Factors:
+    """frames: (N, M) uint8/uint16 device tensor; roi_label: (M,) int32; basis: optional (k, M) float32."""
+    _check_device(frames, "frames", ctx.device)
+    _check_device(roi_label, "roi_label", ctx.device)
+    if roi_label.dtype != torch.int32:
+        raise TypeError("roi_label must be int32")
+    N, M = frames.shape
+    if basis is not None:
+        _check_device(basis, "basis", ctx.device)
+        if basis.dtype != torch.float32 or tuple(basis.shape) != (k, M):
+            raise ValueError("basis must be a (k, M) float32 tensor")
+    f = out if out is not None else Factors.empty(M, N, k, n_roi, ctx.device)
+    opts = L.XpcsCompressOpts(k, oversample, power_iters, L.XPCS_PREC_BF16, seed & (2 ** 64 - 1),
+                              basis.data_ptr() if basis is not None else None)
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.compress_frames(ctx.handle, _ptr(frames), _frame_dtype(frames), M, N, _ptr(roi_label),
+                                      n_roi, ctypes.byref(opts), ctypes.byref(fs)))
+    return f
+
+
+def _alloc_outputs(device, nr, nw, want_c, c_dtype, want_g2):
+    C = torch.empty((nr, nw, nw), dtype=c_dtype, device=device) if want_c else None
+    g2 = torch.empty((nr, nw), dtype=torch.float64, device=device) if want_g2 else None
+    npairs = torch.empty((nr, nw), dtype=torch.int64, device=device) if want_g2 else None
+    return C, g2, npairs
+
+
+def _c_code(c_dtype) -> int:
+    if c_dtype == torch.float32:
+        return L.XPCS_F32
+    if c_dtype == torch.float64:
+        return L.XPCS_F64
+    raise TypeError("C must be float32 or float64")
+
+
+def correlate_two_time(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: int = 0,
+                       t1: Optional[int] = None, want_c: bool = True, c_dtype=torch.float32,
+                       want_g2: bool = True, C: Optional[torch.Tensor] = None,
+                       g2: Optional[torch.Tensor] = None, npairs: Optional[torch.Tensor] = None):
+    """Compressed-domain two-time correlation (and fused g2) of one ROI or all ROIs.
+
+    Returns (C, g2, npairs) with leading ROI dimension (1 for a single ROI).
+    Preallocated outputs may be passed (C: (nr, nw, nw), g2/npairs: (nr, nw)).
+    """
+    t1 = f.N if t1 is None else t1
+    nw = t1 - t0
+    nr = f.n_roi if roi == L.XPCS_ALL_ROIS else 1
+    if C is None and g2 is None:
+        C, g2, npairs = _alloc_outputs(ctx.device, nr, nw, want_c, c_dtype, want_g2)
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.correlate_two_time(ctx.handle, ctypes.byref(fs), roi, t0, t1, _ptr(C),
+                                         _c_code(C.dtype) if C is not None else L.XPCS_F32,
+                                         C.shape[-1] if C is not None else nw, _ptr(g2), _ptr(npairs)))
+    return C, g2, npairs
+
+
+def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int,
+                           roi: int = L.XPCS_ALL_ROIS, t0: int = 0, t1: Optional[int] = None,
+                           want_c: bool = True, c_dtype=torch.float32, want_g2: bool = True,
+                           want_gram: bool = False, C: Optional[torch.Tensor] = None,
+                           g2: Optional[torch.Tensor] = None, npairs: Optional[torch.Tensor] = None):
+    """Raw-data two-time correlation (exact int8 Gram). Returns (C, g2, npairs, gram)."""
+    _check_device(frames, "frames", ctx.device)
+    _check_device(roi_label, "roi_label", ctx.device)
+    N, M = frames.shape
+    t1 = N if t1 is None else t1
+    nw = t1 - t0
+    nr = n_roi if roi == L.XPCS_ALL_ROIS else 1
+    if C is None and g2 is None:
+        C, g2, npairs = _alloc_outputs(ctx.device, nr, nw, want_c, c_dtype, want_g2)
+    gram = torch.empty((nr, nw, nw), dtype=torch.int64, device=ctx.device) if want_gram else None
+    ctx.bind_stream()
+    ctx.check(ctx.lib.correlate_two_time_raw(
+        ctx.handle, _ptr(frames), _frame_dtype(frames), M, N, _ptr(roi_label), n_roi, roi, t0, t1, _ptr(C),
+        _c_code(C.dtype) if C is not None else L.XPCS_F32, C.shape[-1] if C is not None else nw,
+        _ptr(g2), _ptr(npairs), _ptr(gram)))
+    return C, g2, npairs, gram
+
+
+def g2_from_two_time(ctx: Context, C: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+    """g2 and pair counts from an (n, n) (row stride may exceed n) device matrix."""
+    if C.dim() != 2 or C.stride(1) != 1:
+        raise ValueError("C must be a 2-D matrix with unit column stride")
+    n = C.shape[0]
+    g2 = torch.empty((n,), dtype=torch.float64, device=C.device)
+    npairs = torch.empty((n,), dtype=torch.int64, device=C.device)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.g2_from_two_time(ctx.handle, _ptr(C), _c_code(C.dtype), n, C.stride(0), _ptr(g2),
+                                       _ptr(npairs)))
+    return g2, npairs

@@ -1,0 +1,198 @@
+// ROI bookkeeping and the int8 gather of the raw path.
+//
+// A q-ROI is an arbitrary pixel subset (Sec. 2.2: the analysis runs on the
+// flattened pixels of a q range).  The raw path gathers each ROI's pixels once
+// into a dense int8 matrix xs[t][q] (frames x ROI-sorted pixels) so that the
+// Gram X_R^T X_R (Sec. 2.1, Eq. 2) reads contiguous K ranges on the int8 MFMA,
+// and records the exact per-frame ROI photon sums S_R[t] used to normalise it
+// (Eq. 1).
+#include "internal.hpp"
+
+namespace xpcs {
+namespace {
+
+constexpr int kMaxRoiLds = 4096;
+
+__global__ void fill_i64_kernel(int64_t *p, int64_t n, int64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Histogram of labels into roi_npix; flags labels outside [-1, n_roi).
+__global__ __launch_bounds__(256) void roi_count_kernel(const int32_t *__restrict__ labels, int64_t M,
+                                                        int n_roi, unsigned long long *roi_npix,
+                                                        int *flags) {
+    __shared__ int hist[kMaxRoiLds];
+    for (int r = threadIdx.x; r < n_roi; r += blockDim.x) hist[r] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < M;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int l = labels[p];
+        if (l >= 0 && l < n_roi)
+            atomicAdd(&hist[l], 1);
+        else if (l != -1)
+            bad = true;
+    }
+    if (bad) atomicOr(&flags[kFlagLabel], 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n_roi; r += blockDim.x)
+        if (hist[r]) atomicAdd(&roi_npix[r], (unsigned long long)hist[r]);
+}
+
+// One block per ROI: stable compaction of the ROI's pixel indices.
+__global__ __launch_bounds__(1024) void roi_order_kernel(const int32_t *__restrict__ labels, int64_t M,
+                                                         int n_roi, const int64_t *__restrict__ roi_npix,
+                                                         int pad, int64_t *off, int32_t *perm,
+                                                         int32_t *qroi) {
+    const int r = blockIdx.x;
+    __shared__ int wave_tot[16];
+    __shared__ int64_t s_start;
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int i = 0; i < r; ++i) s += (roi_npix[i] + pad - 1) / pad * pad;
+        s_start = s;
+        off[r] = s;
+        if (r == n_roi - 1) off[n_roi] = s + (roi_npix[r] + pad - 1) / pad * pad;
+    }
+    __syncthreads();
+    const int64_t start = s_start;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < M; c0 += blockDim.x) {
+        int64_t p = c0 + threadIdx.x;
+        bool hit = p < M && labels[p] == r;
+        unsigned long long m = __ballot(hit);
+        int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wid] = __popcll(m);
+        __syncthreads();
+        int wbase = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            if (w < wid) wbase += wave_tot[w];
+            tot += wave_tot[w];
+        }
+        if (hit) {
+            int64_t q = start + base + wbase + pre;
+            perm[q] = (int32_t)p;
+            qroi[q] = r;
+        }
+        base += tot;
+        __syncthreads();
+    }
+    const int64_t padded = (roi_npix[r] + pad - 1) / pad * pad;
+    for (int64_t q = roi_npix[r] + threadIdx.x; q < padded; q += blockDim.x) {
+        perm[start + q] = -1;
+        qroi[start + q] = r;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ frames, int64_t M, int64_t t0,
+                                                        int64_t nw, const int32_t *__restrict__ perm,
+                                                        const int32_t *__restrict__ qroi,
+                                                        const int64_t *__restrict__ off, int n_roi,
+                                                        int64_t ldx, int8_t *__restrict__ xs,
+                                                        int64_t *__restrict__ S, int *amax, int *flags) {
+    __shared__ int s_sum[kMaxRoiLds];
+    const int64_t total = off[n_roi];
+    int vmax = 0;
+    bool over = false;
+    for (int r = threadIdx.x; r < n_roi; r += blockDim.x) s_sum[r] = 0;
+    __syncthreads();
+    for (int64_t tl = blockIdx.x; tl < nw; tl += gridDim.x) {
+        const T *fr = frames + (t0 + tl) * M;
+        int cur = -1, acc = 0;
+        for (int64_t q = (int64_t)threadIdx.x * 16; q < total; q += (int64_t)blockDim.x * 16) {
+            int vals[16];
+            int sum = 0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                int p = perm[q + e];
+                int v = p >= 0 ? (int)fr[p] : 0;
+                vmax = v > vmax ? v : vmax;
+                if (v > 127) {
+                    over = true;
+                    v = 127;
+                }
+                vals[e] = v;
+                sum += v;
+            }
+            i32x4 packed;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                packed[w] = (vals[4 * w] & 0xff) | ((vals[4 * w + 1] & 0xff) << 8) |
+                            ((vals[4 * w + 2] & 0xff) << 16) | ((vals[4 * w + 3] & 0xff) << 24);
+            *reinterpret_cast<i32x4 *>(xs + tl * ldx + q) = packed;
+            // ROI starts are multiples of 64, so a 16-pixel group lies in one ROI.
+            int r = qroi[q];
+            if (r != cur) {
+                if (cur >= 0 && acc) atomicAdd(&s_sum[cur], acc);
+                cur = r;
+                acc = 0;
+            }
+            acc += sum;
+        }
+        if (cur >= 0 && acc) atomicAdd(&s_sum[cur], acc);
+        __syncthreads();
+        for (int r = threadIdx.x; r < n_roi; r += blockDim.x) {
+            S[(int64_t)r * nw + tl] = s_sum[r];
+            s_sum[r] = 0;
+        }
+        __syncthreads();
+    }
+    if (over) atomicOr(&flags[kFlagRange], 1);
+    // wave max then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        int v = __shfl_xor(vmax, o);
+        vmax = v > vmax ? v : vmax;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, vmax);
+}
+
+}  // namespace
+
+xpcs_status launch_roi_count(xpcs_ctx *ctx, const int32_t *labels, int64_t M, int n_roi,
+                             int64_t *roi_npix) {
+    Phase phase_(ctx, "roi_count");
+    if (n_roi > kMaxRoiLds) return fail(ctx, XPCS_EUNSUPPORTED, "more than 4096 ROIs");
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(1), dim3(256), 0, ctx->stream, roi_npix, (int64_t)n_roi,
+                       (int64_t)0);
+    int grid = (int)((M + 255) / 256);
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(roi_count_kernel, dim3(grid), dim3(256), 0, ctx->stream, labels, M, n_roi,
+                       reinterpret_cast<unsigned long long *>(roi_npix), ctx->flags);
+    XPCS_LAUNCH_CHECK(ctx, "roi_count");
+    return XPCS_OK;
+}
+
+xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, int n_roi,
+                             const int64_t *roi_npix, int pad, int64_t *off, int32_t *perm,
+                             int32_t *qroi, int64_t total_cap) {
+    Phase phase_(ctx, "roi_order");
+    (void)total_cap;
+    hipLaunchKernelGGL(roi_order_kernel, dim3(n_roi), dim3(1024), 0, ctx->stream, labels, M, n_roi,
+                       roi_npix, pad, off, perm, qroi);
+    XPCS_LAUNCH_CHECK(ctx, "roi_order");
+    return XPCS_OK;
+}
+
+xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t t0,
+                             int64_t nw, const int32_t *perm, const int32_t *qroi, const int64_t *off,
+                             int n_roi, int64_t ldx, int8_t *xs, int64_t *S, int *amax) {
+    Phase phase_(ctx, "gather_i8");
+    if (ldx % 16) return fail(ctx, XPCS_EINVAL, "internal: gather row stride not a multiple of 16");
+    int grid = nw < 4096 ? (int)nw : 4096;
+    if (dtype == XPCS_U8)
+        hipLaunchKernelGGL(gather_i8_kernel<uint8_t>, dim3(grid), dim3(256), 0, ctx->stream,
+                           static_cast<const uint8_t *>(frames), M, t0, nw, perm, qroi, off, n_roi,
+                           ldx, xs, S, amax, ctx->flags);
+    else
+        hipLaunchKernelGGL(gather_i8_kernel<uint16_t>, dim3(grid), dim3(256), 0, ctx->stream,
+                           static_cast<const uint16_t *>(frames), M, t0, nw, perm, qroi, off, n_roi,
+                           ldx, xs, S, amax, ctx->flags);
+    XPCS_LAUNCH_CHECK(ctx, "gather_i8");
+    return XPCS_OK;
+}
+
+}  // namespace xpcs

@@ -1,0 +1,255 @@
+// Internal declarations of the gfx950 XPCS library: context, workspace, MFMA
+// operand types and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "xpcs.h"
+
+namespace xpcs {
+
+// ---------------------------------------------------------------- MFMA operand types
+// v_mfma_f32_16x16x32_bf16: A/B operands are 8 bf16 per lane, C/D 4 floats.
+// v_mfma_i32_16x16x64_i8:   A/B operands are 16 int8 per lane, C/D 4 int32.
+// Lane l of a 64-wide wave holds operand row/column (l % 16) and the K group
+// (l / 16); the accumulator holds rows 4*(l/16) + i, i = 0..3, of column l % 16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Round-to-nearest-even float -> bf16 bit pattern (NaN stays a quiet NaN).
+__device__ __forceinline__ unsigned short f32_to_bf16_bits(float x) {
+    unsigned int u = __builtin_bit_cast(unsigned int, x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(unsigned short b) {
+    return __builtin_bit_cast(float, ((unsigned int)b) << 16);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(const u16x8 &a, const u16x8 &b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ i32x4 mfma_i8(const i32x4 &a, const i32x4 &b, i32x4 c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- device flags
+enum : int {
+    kFlagRange = 0,     // a count above 127 reached the int8 path
+    kFlagLabel = 1,     // a label outside [-1, n_roi)
+    kFlagNumeric = 2,   // a numerically singular step (all sketch pivots dropped, no convergence)
+    kNumFlags = 4,
+};
+
+// ---------------------------------------------------------------- context
+struct Workspace {
+    char *base = nullptr;
+    size_t capacity = 0;
+    size_t used = 0;
+};
+
+struct PhaseRecord {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+}  // namespace xpcs
+
+struct xpcs_ctx {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    xpcs::Workspace ws;          // per-call buffers (bump allocated, reset by every entry point)
+    xpcs::Workspace scratch;     // launcher-private temporaries, reused launch after launch
+    int *flags = nullptr;        // device int[kNumFlags]
+    std::string last_error;
+    bool timing = false;                         // phase timing enabled
+    std::vector<xpcs::PhaseRecord> phases;       // recorded, not yet read
+    std::vector<hipEvent_t> event_pool;          // reusable events
+};
+
+namespace xpcs {
+
+// Records an error message on the context and returns `st`.
+xpcs_status fail(xpcs_ctx *ctx, xpcs_status st, const std::string &msg);
+// Converts a HIP error into XPCS_EDEVICE with a message; XPCS_OK otherwise.
+xpcs_status check_hip(xpcs_ctx *ctx, hipError_t err, const char *what);
+
+// Workspace: `ws_begin` resets the bump pointer; `ws_reserve` makes sure
+// `bytes` more can be carved (growing the arena -- after waiting for the stream
+// -- when needed, subject to the budget); `ws_take` carves 256-byte aligned
+// pieces and never fails after a successful reserve of the total.
+void ws_begin(xpcs_ctx *ctx);
+xpcs_status ws_reserve(xpcs_ctx *ctx, size_t total_bytes);
+void *ws_take(xpcs_ctx *ctx, size_t bytes);
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+// Scratch: one arena shared by consecutive launchers.  Work on the context's
+// stream runs in order, so a launcher may reuse what an earlier launcher's
+// kernels used.  Returns NULL (with the status set) when it cannot grow.
+void *scratch_get(xpcs_ctx *ctx, size_t bytes, xpcs_status *st);
+// Zero `bytes` of device memory with a kernel (safe inside captured graphs).
+xpcs_status launch_zero(xpcs_ctx *ctx, void *p, size_t bytes);
+
+// Records the device time of the enclosed launches under `name` when phase
+// timing is enabled (no-op otherwise).  `name` must be a string literal.
+class Phase {
+  public:
+    Phase(xpcs_ctx *ctx, const char *name);
+    ~Phase();
+
+  private:
+    xpcs_ctx *ctx_;
+    int idx_ = -1;
+};
+
+#define XPCS_LAUNCH_CHECK(ctx, what)                                         \
+    do {                                                                      \
+        hipError_t e_ = hipGetLastError();                                    \
+        if (e_ != hipSuccess) return ::xpcs::check_hip((ctx), e_, (what));    \
+    } while (0)
+
+// ---------------------------------------------------------------- ROI bookkeeping (ingest.hip)
+// roi_npix[r] (int64) and label validation.
+xpcs_status launch_roi_count(xpcs_ctx *ctx, const int32_t *labels, int64_t M, int n_roi,
+                             int64_t *roi_npix);
+// Stable ROI-sorted pixel order: off[r] = start of ROI r (ROI lengths padded to
+// `pad`), perm[q] = pixel at sorted position q (-1 in padding), qroi[q] = ROI.
+// `total_cap` is the capacity of perm/qroi (M + n_roi*pad is always enough).
+xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, int n_roi,
+                             const int64_t *roi_npix, int pad, int64_t *off, int32_t *perm,
+                             int32_t *qroi, int64_t total_cap);
+// Gather the ROI pixels of frames [t0, t0+nw) to int8 rows xs[t][q] (row stride
+// ldx >= total), with exact ROI sums S[r*nw + t] and the int8-range flag.
+xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M,
+                             int64_t t0, int64_t nw, const int32_t *perm, const int32_t *qroi,
+                             const int64_t *off, int n_roi, int64_t ldx, int8_t *xs, int64_t *S,
+                             int *amax);
+
+// ---------------------------------------------------------------- tile pass (tiles.hip)
+struct TileOut {
+    void *C = nullptr;          // output matrix base (NULL: none)
+    int c_dtype = XPCS_F32;
+    int64_t ldc = 0;
+    int64_t c_roi_stride = 0;   // elements between consecutive ROIs' matrices
+    int64_t *gram_out = nullptr;      // raw path only
+    int64_t gram_roi_stride = 0;
+    double *g2_part = nullptr;  // [roi][tile][255] partial diagonal sums (NULL: no g2)
+    int *g2_cnt = nullptr;      // [roi][tile][255] partial pair counts
+};
+constexpr int kTile = 128;
+constexpr int kDiag = 2 * kTile - 1;
+
+inline int64_t n_tiles_upper(int64_t nw) {
+    int64_t nb = (nw + kTile - 1) / kTile;
+    return nb * (nb + 1) / 2;
+}
+
+// Raw ROI Gram on int8 MFMA + normalisation epilogue, for ROIs [r0, r0+nr).
+xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx,
+                                  const int64_t *off, const int64_t *roi_npix, const int64_t *S,
+                                  int64_t nw, int r0, int nr, const int *amax, int64_t max_roi_pixels,
+                                  const TileOut &out);
+// Low-rank tiles C = A' W'^T for ROIs [0, nr) from split-bf16 operands laid out
+// [r][t][kp] (hi and lo), with the frame validity mask valid[r*nw + t].
+xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *a_hi,
+                                 const unsigned short *a_lo, const unsigned short *w_hi,
+                                 const unsigned short *w_lo, int kp, const unsigned char *valid,
+                                 int64_t nw, int nr, const TileOut &out);
+// Partial diagonal sums of an existing matrix (upper triangle only).
+xpcs_status launch_matrix_diag_tiles(xpcs_ctx *ctx, const void *C, int c_dtype, int64_t n,
+                                     int64_t ldc, double *g2_part, int *g2_cnt);
+// g2[r][tau] = sum / count over the tiles covering lag tau.
+xpcs_status launch_g2_reduce(xpcs_ctx *ctx, const double *g2_part, const int *g2_cnt, int64_t nw,
+                             int nr, double *g2, int64_t *npairs);
+
+// ---------------------------------------------------------------- projections (project.hip)
+// Rademacher sketch as bf16 rows om[j][t] (row stride ldt >= N padded to 32, zero padded).
+xpcs_status launch_sketch_omega(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell,
+                                int64_t ldt, unsigned short *om);
+// Pixel-space product Y[j][p] = sum_t X[p][t] B[j][t] (B bf16 rows of stride ldb, L
+// columns, L multiple of 16); Y fp32 column-major with stride M.
+xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
+                               const unsigned short *B, int64_t ldb, int L, float *Y);
+// Frame-space partial products P[c][t][j] = sum_{p in chunk c} X[p][t] Q[j][p] for
+// j < L (bf16 hi, optional lo) and, when n_ind > 0, the indicator columns
+// j = L + r (label == r).  Q rows have stride ldq (>= M padded to 32, zero padded).
+struct FrameProj {
+    int64_t nchunks = 0;
+    int64_t chunk = 0;      // pixels per chunk (multiple of 32)
+    int ncols = 0;          // L + indicator columns rounded to 16
+};
+FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind);
+xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
+                               const unsigned short *q_hi, const unsigned short *q_lo, int64_t ldq,
+                               int L, const int32_t *labels, int n_ind, const FrameProj &plan,
+                               float *part);
+// Sum the chunk partials: Z[j*ldz + t] (fp64, column-major) for j < L, and the
+// indicator columns into S[r*N + t] (int64) when S != NULL.
+xpcs_status launch_proj_frames_reduce(xpcs_ctx *ctx, const float *part, const FrameProj &plan,
+                                      int64_t N, int L, int n_ind, double *Z, int64_t ldz,
+                                      int64_t *S);
+
+// ---------------------------------------------------------------- small dense FP64 steps (smallmat.hip)
+// Gram of a tall column-major matrix A (rows x ncols, column stride lda; fp32 or
+// fp64): G = A^T A (ncols x ncols, fp64).  With seg_off (segments of a gathered
+// row list row_idx; -1 entries skipped) one Gram per segment: G[s].
+xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda,
+                          int ncols, const int32_t *row_idx, const int64_t *seg_off, int nseg,
+                          double *G);
+// Cholesky of G (n x n) with pivots below rel_tol*max(diag) dropped, and the
+// inverse of the factor: A * Rinv has orthonormal (or zero) columns.  Rinv is
+// upper triangular, column-major n x n.  Optionally Rinv <- Rprev * Rinv.
+xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol,
+                           const double *Rprev, double *Rinv);
+// out[:, j] = sum_i A[:, i] T[i][j] (A column-major rows x n, fp32 or fp64; T
+// column-major n x m fp64, optionally scaled per output column by colscale[j]).
+// Writes any of: fp32 out32 (stride ld32), fp64 out64 (stride ld64), bf16 hi/lo
+// rows (stride ldh) padded with zeros up to Lpad columns and rows_pad rows.
+struct TsOut {
+    float *out32 = nullptr; int64_t ld32 = 0;
+    double *out64 = nullptr; int64_t ld64 = 0;
+    unsigned short *hi = nullptr; unsigned short *lo = nullptr; int64_t ldh = 0;
+    int Lpad = 0; int64_t rows_pad = 0;
+};
+xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
+                         const double *T, int m, const double *colscale, const TsOut &out);
+// Symmetric eigendecomposition of B (n x n, n even, n <= 192) by parallel-order
+// cyclic Jacobi: eigenvalues lam[n] (unsorted), eigenvectors P (row-major n x n,
+// column j = vector j).  `rot` holds the rotation log (see workspace sizing).
+size_t jacobi_rot_bytes(int n);
+xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *rot);
+// Order by decreasing eigenvalue, pick the first k, fix signs and build the
+// column transforms: T_u[i][r] = P[i][perm[r]] * sign_r, scale_v[r] = 1 /
+// sigma_r (0 when sigma_r == 0), sigma[r] = sqrt(max(lam, 0)).  The sign makes
+// the largest-magnitude entry of W_l P[:, perm[r]] positive.
+xpcs_status launch_select_basis(xpcs_ctx *ctx, const double *lam, const double *P, int n, int k,
+                                const double *Wl, int64_t N, int64_t ldw, double *T_u,
+                                double *scale_v, double *sigma);
+// Online mode: sigma[j] = |W[:, j]|, scale[j] = 1 / sigma[j] (0 if sigma is 0).
+xpcs_status launch_column_norms(xpcs_ctx *ctx, const double *W, int64_t N, int64_t ldw, int k,
+                                double *sigma, double *scale);
+// Copy / convert a basis: U fp32 column-major -> bf16 hi/lo rows (stride ldq).
+xpcs_status launch_basis_to_bf16(xpcs_ctx *ctx, const float *U, int64_t M, int k, int64_t ldq,
+                                 int Lpad, unsigned short *hi, unsigned short *lo);
+// Diagonal identity: T[i][j] = (i == j) for an n x n column-major matrix.
+xpcs_status launch_identity(xpcs_ctx *ctx, double *T, int n);
+
+// ---------------------------------------------------------------- compressed TTC prep (lowrank.hip)
+// Per ROI r and frame t of the window: w = V[t, :] * sigma / S_r[t];
+// W'[r][t] = w, A'[r][t] = |R| * w G_R; both split to bf16 hi/lo rows of kp.
+xpcs_status launch_lowrank_prep(xpcs_ctx *ctx, const xpcs_factors *f, int r0, int nr, int64_t t0,
+                                int64_t nw, int kp, unsigned short *a_hi, unsigned short *a_lo,
+                                unsigned short *w_hi, unsigned short *w_lo, unsigned char *valid);
+
+}  // namespace xpcs

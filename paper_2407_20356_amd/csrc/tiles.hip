@@ -1,0 +1,498 @@
+// The N x N tile pass shared by the raw and the compressed two-time correlation.
+//
+// C is symmetric (Sec. 2.1, Eq. 2: G = X X^T), so only the tiles on and above
+// the block diagonal are computed; each is written at (i, j) and mirrored at
+// (j, i) from the same value, which makes C exactly symmetric.  The g2 lag
+// average (Sec. 3.1, Eq. 12) is fused into the same pass: every tile leaves the
+// sums of its 255 diagonals t2 - t1 = const in a partial buffer, and a second,
+// fixed-order pass adds them per lag (no float atomics, deterministic).
+//
+// Block shape: 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning a
+// 64 x 64 quarter of the 128 x 128 tile as 4 x 4 MFMA 16 x 16 blocks.  The
+// epilogue stages one 64-row half of the tile in LDS at a time so that both the
+// direct and the mirrored writes go out as contiguous rows.
+#include <math.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace xpcs {
+namespace {
+
+constexpr int kPitch = kTile + 1;   // odd LDS pitch: column reads are conflict-free
+constexpr int kHalf = kTile / 2;
+
+// Tiles of one ROI in diagonal-major order: id = sum_{d<D} (nb - d) + bi with D = bj - bi.
+__device__ __forceinline__ void tile_coords(int64_t id, int nb, int &bi, int &bj) {
+    int D = 0;
+    while (id >= nb - D) {
+        id -= nb - D;
+        ++D;
+    }
+    bi = (int)id;
+    bj = bi + D;
+}
+
+template <typename OutT>
+__device__ __forceinline__ void nt_store(OutT *p, OutT v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+template <typename OutT>
+__device__ __forceinline__ void store4(OutT *dst, const OutT (&v)[4], const bool (&ok)[4], bool vec) {
+    if (vec && ok[0] && ok[1] && ok[2] && ok[3]) {
+        if constexpr (sizeof(OutT) == 4) {
+            f32x4 x = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            __builtin_nontemporal_store(x, reinterpret_cast<f32x4 *>(dst));
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (ok[e]) nt_store(dst + e, v[e]);
+}
+
+// One 64-row half h of a staged tile: direct rows, mirrored columns, diagonal partials.
+// All 256 threads call it; st holds rows [64h, 64h + 64) of the tile at pitch kPitch.
+template <typename StageT, typename OutT>
+__device__ __forceinline__ void epilogue_half(const StageT *st, int h, int64_t i0, int64_t j0, bool diag,
+                                              int64_t nw, OutT *C, int64_t ldc, bool vec, double &dsum,
+                                              int &dcnt) {
+    const int tid = threadIdx.x;
+    if (C) {
+        // Direct rows: 32 threads x 4 columns per row, 8 rows per pass.
+#pragma unroll 1
+        for (int pass = 0; pass < kHalf / 8; ++pass) {
+            const int rl = pass * 8 + tid / 32;
+            const int c = (tid % 32) * 4;
+            const int r = kHalf * h + rl;
+            const int64_t i = i0 + r;
+            if (i < nw) {
+                OutT v[4];
+                bool ok[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ok[e] = (j0 + c + e < nw) && (!diag || c + e >= r);
+                    v[e] = (OutT)st[rl * kPitch + c + e];
+                }
+                store4(C + i * ldc + j0 + c, v, ok, vec);
+            }
+        }
+        // Mirrored columns: 16 threads x 4 rows per column, 16 columns per pass.
+#pragma unroll 1
+        for (int pass = 0; pass < kTile / 16; ++pass) {
+            const int c = pass * 16 + tid / 16;
+            const int rq = tid % 16;
+            const int64_t j = j0 + c;
+            if (j < nw) {
+                OutT v[4];
+                bool ok[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rl = 4 * rq + e;
+                    const int r = kHalf * h + rl;
+                    ok[e] = (i0 + r < nw) && (!diag || c > r);
+                    v[e] = (OutT)st[rl * kPitch + c];
+                }
+                store4(C + j * ldc + i0 + kHalf * h + 4 * rq, v, ok, vec);
+            }
+        }
+    }
+    // Diagonal partials: thread d handles t2 - t1 offset d - 127 inside the tile.
+    if (tid < kDiag) {
+        const int d = tid - (kTile - 1);
+        if (!diag || d >= 0) {
+#pragma unroll 4
+            for (int rl = 0; rl < kHalf; ++rl) {
+                const int r = kHalf * h + rl;
+                const int c = r + d;
+                if (c < 0 || c >= kTile) continue;
+                if (i0 + r >= nw || j0 + c >= nw) continue;
+                const StageT v = st[rl * kPitch + c];
+                if (v == v) {
+                    dsum += (double)v;
+                    dcnt += 1;
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void write_diag_partials(double *g2_part, int *g2_cnt, int64_t slot, double dsum,
+                                                    int dcnt) {
+    if (g2_part && threadIdx.x < kDiag) {
+        g2_part[slot * kDiag + threadIdx.x] = dsum;
+        g2_cnt[slot * kDiag + threadIdx.x] = dcnt;
+    }
+}
+
+// ---------------------------------------------------------------- raw Gram (int8 MFMA)
+// WIDE = false handles the ROIs whose pixel count fits one int32 accumulation
+// chunk (every realistic case: with counts <= 40 a chunk holds 1.3 M pixels);
+// WIDE = true the others, folding int32 chunk sums into int64.  Both are
+// launched; each block leaves at once when its ROI belongs to the other.
+template <typename OutT, bool WIDE>
+__global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
+    const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
+    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
+    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    __shared__ double stage[kHalf * kPitch];
+    const int slot = blockIdx.y;
+    const int roi = r0 + slot;
+    int bi, bj;
+    tile_coords(blockIdx.x, nb, bi, bj);
+    const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
+    const bool diag = bi == bj;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    const bool skip = diag && wr > wc;     // strictly below the diagonal: never used
+
+    const int64_t q0 = off[roi], qlen = off[roi + 1] - off[roi];
+    const int am = *amax;
+    // int32 accumulation is exact while (pixels per chunk) * amax^2 < 2^31.
+    int64_t kc = am > 0 ? (int64_t)2147483647 / ((int64_t)am * am) : qlen;
+    kc = kc / 64 * 64;
+    if (kc < 64) kc = 64;
+    if ((qlen > kc) != WIDE) return;
+
+    const int8_t *arow[4], *brow[4];
+    bool aok[4], bok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        int64_t ta = i0 + 64 * wr + 16 * b + lr, tb = j0 + 64 * wc + 16 * b + lr;
+        aok[b] = ta < nw;
+        bok[b] = tb < nw;
+        arow[b] = xs + (aok[b] ? ta : 0) * ldx + q0 + 16 * lg;
+        brow[b] = xs + (bok[b] ? tb : 0) * ldx + q0 + 16 * lg;
+    }
+    // int32 MFMA accumulators; the wide variant folds them into int64 per chunk.
+    i32x4 acc[4][4];
+    int64_t wide[WIDE ? 4 : 1][WIDE ? 4 : 1][WIDE ? 4 : 1];
+    if constexpr (WIDE) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) wide[a][b][e] = 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (i32x4){0, 0, 0, 0};
+
+    if (!skip) {
+        for (int64_t c0 = 0; c0 < qlen; c0 += kc) {
+            const int64_t c1 = c0 + kc < qlen ? c0 + kc : qlen;
+            for (int64_t k = c0; k < c1; k += 64) {
+                i32x4 av[4], bv[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    av[b] = aok[b] ? *reinterpret_cast<const i32x4 *>(arow[b] + k) : (i32x4){0, 0, 0, 0};
+                    bv[b] = bok[b] ? *reinterpret_cast<const i32x4 *>(brow[b] + k) : (i32x4){0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = mfma_i8(av[a], bv[b], acc[a][b]);
+            }
+            if constexpr (WIDE) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) wide[a][b][e] += acc[a][b][e];
+                        acc[a][b] = (i32x4){0, 0, 0, 0};
+                    }
+            }
+        }
+    }
+    auto gval = [&](int a, int b, int e) -> int64_t {
+        if constexpr (WIDE)
+            return wide[a][b][e];
+        else
+            return (int64_t)acc[a][b][e];
+    };
+
+    const double npix = (double)roi_npix[roi];
+    const int64_t *Sr = S + (int64_t)roi * nw;
+    OutT *Cr = C ? C + (int64_t)slot * c_roi_stride : nullptr;
+    int64_t *Gr = gram_out ? gram_out + (int64_t)slot * gram_roi_stride : nullptr;
+
+    // Exact Gram straight from the registers (a debugging/verification output).
+    if (Gr && !skip) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t i = i0 + 64 * wr + 16 * a + 4 * lg + e;
+                    const int64_t j = j0 + 64 * wc + 16 * b + lr;
+                    if (i < nw && j < nw && j >= i) {
+                        Gr[i * nw + j] = gval(a, b, e);
+                        Gr[j * nw + i] = gval(a, b, e);
+                    }
+                }
+    }
+
+    double dsum = 0.0;
+    int dcnt = 0;
+    for (int h = 0; h < 2; ++h) {
+        if (wr == h) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = 64 * wc + 16 * b + lr;
+                const int64_t j = j0 + c;
+                const double sj = j < nw ? (double)Sr[j] : 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int rl = 16 * a + 4 * lg + e;
+                        const int64_t i = i0 + kHalf * h + rl;
+                        const double si = i < nw ? (double)Sr[i] : 0.0;
+                        double v;
+                        if (si > 0.0 && sj > 0.0)
+                            v = (npix * (double)gval(a, b, e)) / (si * sj);
+                        else
+                            v = __builtin_nan("");
+                        stage[rl * kPitch + c] = v;
+                    }
+            }
+        }
+        __syncthreads();
+        epilogue_half<double, OutT>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, dsum, dcnt);
+        __syncthreads();
+    }
+    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + blockIdx.x, dsum, dcnt);
+}
+
+// ---------------------------------------------------------------- low-rank tiles (split-bf16 MFMA)
+// C~[i][j] = A'[i] . W'[j] with A' = |R| W G_R / S and W' = W / S, each carried as
+// bf16 hi + lo; the three products hi.hi + hi.lo + lo.hi are accumulated in FP32.
+template <typename OutT>
+__global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
+    const unsigned short *__restrict__ a_hi, const unsigned short *__restrict__ a_lo,
+    const unsigned short *__restrict__ w_hi, const unsigned short *__restrict__ w_lo, int kp,
+    const unsigned char *__restrict__ valid, int64_t nw, int nb, OutT *C, int64_t ldc,
+    int64_t c_roi_stride, bool vec, double *g2_part, int *g2_cnt) {
+    __shared__ float stage[kHalf * kPitch];
+    const int slot = blockIdx.y;
+    int bi, bj;
+    tile_coords(blockIdx.x, nb, bi, bj);
+    const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
+    const bool diag = bi == bj;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    const bool skip = diag && wr > wc;
+    const int64_t base = (int64_t)slot * nw * kp;
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    if (!skip) {
+        int64_t aoff[4], boff[4];
+        bool aok[4], bok[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int64_t ta = i0 + 64 * wr + 16 * b + lr, tb = j0 + 64 * wc + 16 * b + lr;
+            aok[b] = ta < nw;
+            bok[b] = tb < nw;
+            aoff[b] = base + (aok[b] ? ta : 0) * kp + 8 * lg;
+            boff[b] = base + (bok[b] ? tb : 0) * kp + 8 * lg;
+        }
+        const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < kp; k += 32) {
+            u16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                ah[b] = aok[b] ? *reinterpret_cast<const u16x8 *>(a_hi + aoff[b] + k) : z;
+                al[b] = aok[b] ? *reinterpret_cast<const u16x8 *>(a_lo + aoff[b] + k) : z;
+                bh[b] = bok[b] ? *reinterpret_cast<const u16x8 *>(w_hi + boff[b] + k) : z;
+                bl[b] = bok[b] ? *reinterpret_cast<const u16x8 *>(w_lo + boff[b] + k) : z;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b] = mfma_bf16(al[a], bh[b], acc[a][b]);
+                    acc[a][b] = mfma_bf16(ah[a], bl[b], acc[a][b]);
+                    acc[a][b] = mfma_bf16(ah[a], bh[b], acc[a][b]);
+                }
+        }
+    }
+
+    const unsigned char *vr = valid + (int64_t)slot * nw;
+    OutT *Cr = C ? C + (int64_t)slot * c_roi_stride : nullptr;
+    double dsum = 0.0;
+    int dcnt = 0;
+    for (int h = 0; h < 2; ++h) {
+        if (wr == h) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = 64 * wc + 16 * b + lr;
+                const int64_t j = j0 + c;
+                const bool vj = j < nw && vr[j];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int rl = 16 * a + 4 * lg + e;
+                        const int64_t i = i0 + kHalf * h + rl;
+                        const bool vi = i < nw && vr[i];
+                        stage[rl * kPitch + c] = (vi && vj) ? acc[a][b][e] : __builtin_nanf("");
+                    }
+            }
+        }
+        __syncthreads();
+        epilogue_half<float, OutT>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, dsum, dcnt);
+        __syncthreads();
+    }
+    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + blockIdx.x, dsum, dcnt);
+}
+
+// ---------------------------------------------------------------- diagonals of a given matrix
+template <typename InT>
+__global__ __launch_bounds__(256) void matrix_diag_tile_kernel(const InT *__restrict__ C, int64_t n,
+                                                               int64_t ldc, int nb, double *g2_part,
+                                                               int *g2_cnt) {
+    __shared__ InT stage[kHalf * kPitch];
+    int bi, bj;
+    tile_coords(blockIdx.x, nb, bi, bj);
+    const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
+    const bool diag = bi == bj;
+    double dsum = 0.0;
+    int dcnt = 0;
+    for (int h = 0; h < 2; ++h) {
+        for (int idx = threadIdx.x; idx < kHalf * kTile; idx += blockDim.x) {
+            const int rl = idx / kTile, c = idx % kTile;
+            const int64_t i = i0 + kHalf * h + rl, j = j0 + c;
+            stage[rl * kPitch + c] = (i < n && j < n) ? C[i * ldc + j] : (InT)0;
+        }
+        __syncthreads();
+        epilogue_half<InT, InT>(stage, h, i0, j0, diag, n, (InT *)nullptr, 0, false, dsum, dcnt);
+        __syncthreads();
+    }
+    write_diag_partials(g2_part, g2_cnt, blockIdx.x, dsum, dcnt);
+}
+
+// ---------------------------------------------------------------- lag reduction
+__global__ __launch_bounds__(256) void g2_reduce_kernel(const double *__restrict__ part,
+                                                        const int *__restrict__ cnt, int64_t nw, int nb,
+                                                        int64_t ntiles, double *g2, int64_t *npairs) {
+    const int slot = blockIdx.y;
+    const int64_t tau = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tau >= nw) return;
+    const double *P = part + (int64_t)slot * ntiles * kDiag;
+    const int *K = cnt + (int64_t)slot * ntiles * kDiag;
+    double s = 0.0;
+    int64_t c = 0;
+    const int64_t D0 = tau / kTile;
+    for (int64_t D = D0; D <= D0 + 1 && D < nb; ++D) {
+        const int64_t d = tau - D * kTile;          // offset inside the tile
+        if (d < -(kTile - 1)) continue;
+        if (D == 0 && d < 0) continue;
+        const int64_t first = D * nb - D * (D - 1) / 2;
+        for (int64_t bi = 0; bi < nb - D; ++bi) {
+            const int64_t id = first + bi;
+            s += P[id * kDiag + d + kTile - 1];
+            c += K[id * kDiag + d + kTile - 1];
+        }
+    }
+    g2[(int64_t)slot * nw + tau] = c ? s / (double)c : __builtin_nan("");
+    if (npairs) npairs[(int64_t)slot * nw + tau] = c;
+}
+
+}  // namespace
+
+xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx, const int64_t *off,
+                                  const int64_t *roi_npix, const int64_t *S, int64_t nw, int r0, int nr,
+                                  const int *amax, int64_t max_roi_pixels, const TileOut &o) {
+    Phase phase_(ctx, "raw_gram_tiles");
+    const int nb = (int)((nw + kTile - 1) / kTile);
+    const int64_t nt = n_tiles_upper(nw);
+    if (nt > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "window too large");
+    dim3 grid((unsigned)nt, (unsigned)nr);
+    const bool vec = o.C && o.c_dtype == XPCS_F32 && (o.ldc % 4 == 0) &&
+                     ((uintptr_t)o.C % 16 == 0) && (o.c_roi_stride % 4 == 0);
+    // The wide variant is only needed when some ROI can exceed the smallest int32 chunk
+    // (counts <= 127: 133,120 pixels); M bounds every ROI.
+    const bool maybe_wide = max_roi_pixels > 133120;
+    if (o.C == nullptr || o.c_dtype == XPCS_F32) {
+        hipLaunchKernelGGL((raw_gram_tile_kernel<float, false>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
+                           o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
+        if (maybe_wide)
+            hipLaunchKernelGGL((raw_gram_tile_kernel<float, true>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                               roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
+                               o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    } else {
+        hipLaunchKernelGGL((raw_gram_tile_kernel<double, false>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
+                           o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
+        if (maybe_wide)
+            hipLaunchKernelGGL((raw_gram_tile_kernel<double, true>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                               roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
+                               o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    }
+    XPCS_LAUNCH_CHECK(ctx, "raw_gram_tiles");
+    return XPCS_OK;
+}
+
+xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *a_hi, const unsigned short *a_lo,
+                                 const unsigned short *w_hi, const unsigned short *w_lo, int kp,
+                                 const unsigned char *valid, int64_t nw, int nr, const TileOut &o) {
+    Phase phase_(ctx, "lowrank_tiles");
+    const int nb = (int)((nw + kTile - 1) / kTile);
+    const int64_t nt = n_tiles_upper(nw);
+    if (nt > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "window too large");
+    if (kp % 32) return fail(ctx, XPCS_EINVAL, "internal: kp must be a multiple of 32");
+    dim3 grid((unsigned)nt, (unsigned)nr);
+    const bool vec = o.C && o.c_dtype == XPCS_F32 && (o.ldc % 4 == 0) &&
+                     ((uintptr_t)o.C % 16 == 0) && (o.c_roi_stride % 4 == 0);
+    if (o.C == nullptr || o.c_dtype == XPCS_F32)
+        hipLaunchKernelGGL(lowrank_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, a_hi, a_lo, w_hi,
+                           w_lo, kp, valid, nw, nb, static_cast<float *>(o.C), o.ldc, o.c_roi_stride,
+                           vec, o.g2_part, o.g2_cnt);
+    else
+        hipLaunchKernelGGL(lowrank_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, a_hi, a_lo, w_hi,
+                           w_lo, kp, valid, nw, nb, static_cast<double *>(o.C), o.ldc, o.c_roi_stride,
+                           false, o.g2_part, o.g2_cnt);
+    XPCS_LAUNCH_CHECK(ctx, "lowrank_tiles");
+    return XPCS_OK;
+}
+
+xpcs_status launch_matrix_diag_tiles(xpcs_ctx *ctx, const void *C, int c_dtype, int64_t n, int64_t ldc,
+                                     double *g2_part, int *g2_cnt) {
+    Phase phase_(ctx, "matrix_diag_tiles");
+    const int nb = (int)((n + kTile - 1) / kTile);
+    const int64_t nt = n_tiles_upper(n);
+    if (c_dtype == XPCS_F32)
+        hipLaunchKernelGGL(matrix_diag_tile_kernel<float>, dim3((unsigned)nt), dim3(256), 0, ctx->stream,
+                           static_cast<const float *>(C), n, ldc, nb, g2_part, g2_cnt);
+    else
+        hipLaunchKernelGGL(matrix_diag_tile_kernel<double>, dim3((unsigned)nt), dim3(256), 0, ctx->stream,
+                           static_cast<const double *>(C), n, ldc, nb, g2_part, g2_cnt);
+    XPCS_LAUNCH_CHECK(ctx, "matrix_diag_tiles");
+    return XPCS_OK;
+}
+
+xpcs_status launch_g2_reduce(xpcs_ctx *ctx, const double *g2_part, const int *g2_cnt, int64_t nw, int nr,
+                             double *g2, int64_t *npairs) {
+    Phase phase_(ctx, "g2_reduce");
+    const int nb = (int)((nw + kTile - 1) / kTile);
+    dim3 grid((unsigned)((nw + 255) / 256), (unsigned)nr);
+    hipLaunchKernelGGL(g2_reduce_kernel, grid, dim3(256), 0, ctx->stream, g2_part, g2_cnt, nw, nb,
+                       n_tiles_upper(nw), g2, npairs);
+    XPCS_LAUNCH_CHECK(ctx, "g2_reduce");
+    return XPCS_OK;
+}
+
+}  // namespace xpcs

@@ -152,7 +152,7 @@ def speckle_frames_torch(n_pixels: int, n_frames: int, mu: float, beta: float,
     """Same model generated with torch's RNG on `device` (for inputs too large for NumPy).
 
     The random stream differs from the NumPy generator; the distribution is the
-    same.  Returns a (n_frames, n_pixels) uint8/int16-viewed-as-uint16 tensor.
+    same.  Returns a (n_frames, n_pixels) uint8 or uint16 tensor.
     """
     import torch
 
@@ -163,12 +163,13 @@ def speckle_frames_torch(n_pixels: int, n_frames: int, mu: float, beta: float,
     a = torch.from_numpy(np.ascontiguousarray(a_np)).to(dev)
     b = torch.sqrt(torch.clamp(1.0 - a * a, min=0.0))
     sb = math.sqrt(beta)
-    tdt = {"u8": torch.uint8, "u16": torch.uint16}[dtype]
+    # 16-bit counts are built as int16 (counts stay far below 2^15) and viewed as uint16
+    tdt = {"u8": torch.uint8, "u16": torch.int16}[dtype]
     out = torch.empty((n_frames, n_pixels), dtype=tdt, device=dev)
     inv_sqrt2 = 1.0 / math.sqrt(2.0)
     er = torch.randn(n_pixels, generator=gen, device=dev) * inv_sqrt2
     ei = torch.randn(n_pixels, generator=gen, device=dev) * inv_sqrt2
-    cap = 255 if dtype == "u8" else 65535
+    cap = 255 if dtype == "u8" else 32767
     if max_count is not None:
         cap = min(cap, max_count)
     lam_blk = torch.empty((block, n_pixels), dtype=torch.float32, device=dev)
@@ -185,7 +186,7 @@ def speckle_frames_torch(n_pixels: int, n_frames: int, mu: float, beta: float,
         if float(n.max()) > cap:
             raise ValueError(f"count {float(n.max())} exceeds the cap {cap} in frames {t0}..{t0 + nb}")
         out[t0:t0 + nb] = n.to(torch.int32).to(tdt)
-    return out
+    return out.view(torch.uint16) if dtype == "u16" else out
 
 
 def low_rank_frames_numpy(n_pixels: int, n_frames: int, rank: int, seed: int = 0,

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU tests (inputs, tolerance checks)."""
+
+import sys
+
+import numpy as np
+
+
+def say(msg):
+    """Name the case before each GPU step, flushed, so a failing run shows where it was."""
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, device="cuda:0"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_two_time_close(C, Cref, rtol=1e-3, small=0.1, what="C"):
+    """Tolerance of the compressed path: entries with |C*| >= small within rtol
+    relative; the remaining entries within rtol in relative Frobenius norm.  NaN
+    patterns (frames without photons) must agree exactly."""
+    C = np.asarray(C, dtype=np.float64)
+    Cref = np.asarray(Cref, dtype=np.float64)
+    assert C.shape == Cref.shape, (C.shape, Cref.shape)
+    nan_ref = np.isnan(Cref)
+    assert np.array_equal(np.isnan(C), nan_ref), f"{what}: NaN pattern differs"
+    ok = ~nan_ref
+    big = ok & (np.abs(Cref) >= small)
+    rel = np.abs(C[big] - Cref[big]) / np.abs(Cref[big])
+    worst = float(rel.max(initial=0.0))
+    assert worst <= rtol, f"{what}: max rel err {worst:.3e} > {rtol:.1e}"
+    rest = ok & ~big
+    if rest.any():
+        num = np.linalg.norm(C[rest] - Cref[rest])
+        den = np.linalg.norm(Cref[rest])
+        if den > 0:
+            assert num / den <= rtol, f"{what}: small-entry Frobenius rel err {num / den:.3e}"
+    return worst

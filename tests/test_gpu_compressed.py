@@ -1,0 +1,228 @@
+"""GPU parity of the compressed path (compress_frames + correlate_two_time)
+through the C ABI.
+
+Elementwise parity against the CPU FP64 oracle uses inputs the oracle sees
+unchanged: the frames, the labels and -- in online mode -- a basis the oracle
+computed itself (Sec. 2.2: the encoding matrix is generated beforehand).  The
+offline pipeline (basis from the data) is compared with the oracle where the
+answer does not depend on the basis: at full rank and on low-rank data the
+compressed correlation equals the raw one (Eq. 11).  The GPU's own lossy
+basis is checked through properties that any correct rank-k basis has
+(orthonormality, singular-value interlacing, Eckart-Young optimality within
+5%, W = X^T U, G_R = U_R^T U_R, and the Eqs. 8-10 identity), written with
+plain NumPy in this file.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.gpu_util import assert_two_time_close, say, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2407_20356_amd import api
+    assert torch.cuda.is_available()
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _factors_np(f):
+    return dict(U=to_np(f.U).T.astype(np.float64), sigma=to_np(f.sigma), V=to_np(f.V).T.astype(np.float64),
+                npix=to_np(f.roi_npix), S=to_np(f.roi_sum), G=to_np(f.roi_gram))
+
+
+def _oracle_compressed(F, U, labels, n_roi, t0=0, t1=None):
+    t1 = F.shape[0] if t1 is None else t1
+    return [O.compressed_two_time(F[t0:t1], U, labels, r) for r in range(n_roi)]
+
+
+def _gpu_correlate(ctx, f, **kw):
+    from paper_2407_20356_amd import api
+    say(f"correlate N={f.N} k={f.k} n_roi={f.n_roi} {kw}")
+    C, g2, npairs = api.correlate_two_time(ctx, f, **kw)
+    ctx.sync()
+    return (to_np(C) if C is not None else None), to_np(g2), to_np(npairs)
+
+
+def _assert_parity(C, g2, npairs, Crefs):
+    for r, Cref in enumerate(Crefs):
+        assert_two_time_close(C[r], Cref, what=f"C roi {r}")
+        assert np.array_equal(np.nan_to_num(C[r]), np.nan_to_num(C[r].T))
+        gref, nref = O.g2_from_two_time(Cref)
+        np.testing.assert_array_equal(npairs[r], nref)
+        ok = nref > 0
+        np.testing.assert_allclose(g2[r][ok], gref[ok], rtol=1e-3)
+
+
+# --------------------------------------------------------------------------- parity with oracle inputs only
+
+@pytest.mark.parametrize("dtype,related", [("u8", False), ("u16", True)])
+def test_online_basis_parity(ctx, dtype, related):
+    """Basis generated beforehand by the oracle (the data's own, or a related series')."""
+    from paper_2407_20356_amd import api
+    H, W, n_roi, k = 50, 50, 4, 24
+    labels = synth.annular_labels(H, W, n_roi, r_in=2.0)
+    F = synth.speckle_frames_numpy(H * W, 500, 0.2, 0.2, 20.0, dtype, seed=6)
+    F[33] = 0                                            # a frame without photons
+    src = synth.speckle_frames_numpy(H * W, 300, 0.2, 0.2, 20.0, dtype, seed=60) if related else F
+    U0, _, _ = O.exact_basis(src, k)
+    U0 = U0.astype(np.float32).astype(np.float64)        # the library takes an fp32 basis
+    say(f"online basis {dtype} related={related}")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), n_roi, k=k,
+                            basis=to_dev(U0.T.astype(np.float32)))
+    ctx.sync()
+    fn = _factors_np(f)
+    np.testing.assert_array_equal(fn["U"], U0)
+    np.testing.assert_array_equal(fn["npix"], O.roi_pixel_counts(labels, n_roi))
+    np.testing.assert_array_equal(fn["S"], O.roi_frame_sums(F, labels, n_roi))
+    Wref = O.encode(F, U0)
+    np.testing.assert_allclose(fn["sigma"], np.linalg.norm(Wref, axis=0), rtol=1e-6)
+    assert np.linalg.norm(fn["V"] * fn["sigma"] - Wref) <= 1e-5 * np.linalg.norm(Wref)
+    for r in range(n_roi):
+        np.testing.assert_allclose(fn["G"][r], O.roi_basis_gram(U0, labels, r), rtol=1e-9, atol=1e-12)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, _oracle_compressed(F, U0, labels, n_roi))
+    # a window of one ROI, and g2 without writing C
+    t0, t1 = 129, 461
+    C1, g21, n1 = _gpu_correlate(ctx, f, roi=1, t0=t0, t1=t1)
+    _, g2b, nb = _gpu_correlate(ctx, f, roi=1, t0=t0, t1=t1, want_c=False)
+    Cw = O.compressed_two_time_from_factors(Wref[t0:t1], O.roi_basis_gram(U0, labels, 1),
+                                            O.roi_frame_sums(F, labels, n_roi)[1][t0:t1],
+                                            int(O.roi_pixel_counts(labels, n_roi)[1]))
+    _assert_parity(C1, g21, n1, [Cw])
+    np.testing.assert_array_equal(g21, g2b)
+    np.testing.assert_array_equal(n1, nb)
+    np.testing.assert_array_equal(C1[0], C[1][t0:t1, t0:t1])
+
+
+def test_offline_full_rank_is_lossless(ctx):
+    """Eq. 11: a basis of rank N spans every frame, so C~ is the raw C."""
+    from paper_2407_20356_amd import api
+    H = W = 64
+    labels = synth.annular_labels(H, W, 3, r_in=4.0)
+    F = synth.speckle_frames_numpy(H * W, 64, 0.3, 0.2, 20.0, "u8", seed=21)
+    say("offline full rank k = N = 64")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 3, k=64, oversample=0, seed=1)
+    ctx.sync()
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, [O.raw_two_time(F, labels, r) for r in range(3)])
+
+
+def test_offline_low_rank_data_is_lossless(ctx):
+    from paper_2407_20356_amd import api
+    F = synth.low_rank_frames_numpy(3000, 400, rank=6, seed=4)
+    labels = synth.annular_labels(50, 60, 3, r_in=2.0)
+    say("offline low-rank data k=8")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 3, k=8, oversample=8, seed=5)
+    ctx.sync()
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, [O.raw_two_time(F, labels, r) for r in range(3)])
+
+
+# --------------------------------------------------------------------------- properties of the GPU's own basis
+
+def _check_basis_properties(F, labels, n_roi, fn, k, ey_factor=1.05):
+    X = F.astype(np.float64).T
+    U, s = fn["U"], fn["sigma"]
+    np.testing.assert_array_equal(fn["npix"], O.roi_pixel_counts(labels, n_roi))
+    np.testing.assert_array_equal(fn["S"], O.roi_frame_sums(F, labels, n_roi))
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-5
+    assert np.all(np.diff(s) <= 0) and np.all(s >= 0)
+    s_exact = O.exact_basis(F, min(F.shape))[1]
+    # interlacing: the singular values of a projection of X cannot exceed those of X
+    assert np.all(s <= s_exact[:k] * (1 + 1e-5) + 1e-9)
+    assert abs(s[0] - s_exact[0]) <= 1e-3 * s_exact[0]
+    resid = np.linalg.norm(X - U @ (U.T @ X)) ** 2
+    assert resid <= ey_factor * np.sum(s_exact[k:] ** 2)
+    # the factors are consistent: W = X^T U, G_R = U_R^T U_R
+    W = X.T @ U
+    assert np.linalg.norm(fn["V"] * s - W) <= 1e-5 * np.linalg.norm(W)
+    for r in range(n_roi):
+        Ur = U[labels == r]
+        np.testing.assert_allclose(fn["G"][r], Ur.T @ Ur, rtol=1e-9, atol=1e-12)
+    return W
+
+
+def _check_homomorphic_identity(C, F, labels, n_roi, U):
+    """C~ equals the two-time correlation of the decompressed data U U^T X (Eqs. 8-10)."""
+    Xd = U @ (U.T @ F.astype(np.float64).T)              # decompressed, pixels x frames
+    for r in range(n_roi):
+        m = labels == r
+        S = F[:, m].astype(np.int64).sum(axis=1).astype(np.float64)
+        G = Xd[m].T @ Xd[m]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Cd = m.sum() * G / np.outer(S, S)
+        Cd[S == 0, :] = np.nan
+        Cd[:, S == 0] = np.nan
+        assert_two_time_close(C[r], Cd, what=f"identity roi {r}")
+
+
+@pytest.mark.parametrize("power_iters", [1, 0])
+def test_offline_basis_single_roi(ctx, power_iters):
+    from paper_2407_20356_amd import api
+    F = synth.speckle_frames_numpy(4096, 600, 0.05, 0.2, 50.0, "u8", seed=1)
+    F[17] = 0
+    labels = np.zeros(4096, dtype=np.int32)
+    k = 32
+    say(f"offline tiny 4096 px x 600 frames k=32 q={power_iters}")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 1, k=k, seed=7, power_iters=power_iters)
+    ctx.sync()
+    fn = _factors_np(f)
+    _check_basis_properties(F, labels, 1, fn, k, ey_factor=1.05 if power_iters else 1.15)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _check_homomorphic_identity(C, F, labels, 1, fn["U"])
+
+
+def test_offline_basis_multi_roi_u16(ctx):
+    from paper_2407_20356_amd import api
+    H = W = 96
+    labels = synth.annular_labels(H, W, 8)
+    tau = synth.split_tau_map(labels, 8, 100.0, 10.0)
+    F = synth.speckle_frames_numpy(H * W, 700, 0.1, 0.2, tau, "u16", seed=2)
+    k = 48
+    say("offline multi-ROI u16 96x96 x 700 k=48")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 8, k=k, seed=3)
+    ctx.sync()
+    fn = _factors_np(f)
+    _check_basis_properties(F, labels, 8, fn, k)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _check_homomorphic_identity(C, F, labels, 8, fn["U"])
+
+
+def test_large_counts_split_exactly(ctx):
+    """u16 counts above 256 are carried as bf16 hi + lo: W still equals X^T U."""
+    from paper_2407_20356_amd import api
+    rng = np.random.default_rng(9)
+    F = rng.integers(0, 5000, size=(200, 2048)).astype(np.uint16)
+    labels = np.zeros(2048, dtype=np.int32)
+    say("offline u16 counts up to 5000")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 1, k=16, seed=1)
+    ctx.sync()
+    fn = _factors_np(f)
+    X = F.astype(np.float64).T
+    assert np.abs(fn["U"].T @ fn["U"] - np.eye(16)).max() <= 1e-5
+    W = X.T @ fn["U"]
+    assert np.linalg.norm(fn["V"] * fn["sigma"] - W) <= 1e-5 * np.linalg.norm(W)
+    np.testing.assert_array_equal(fn["S"], O.roi_frame_sums(F, labels, 1))
+
+
+def test_deterministic(ctx):
+    from paper_2407_20356_amd import api
+    F = synth.speckle_frames_numpy(2048, 300, 0.1, 0.2, 20.0, "u8", seed=12)
+    labels = synth.annular_labels(32, 64, 2, r_in=2.0)
+    outs = []
+    for rep in range(2):
+        say(f"determinism rep {rep}")
+        f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 2, k=16, seed=4)
+        C, g2, _ = api.correlate_two_time(ctx, f)
+        ctx.sync()
+        outs.append((to_np(f.U), to_np(f.V), to_np(C), to_np(g2)))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)

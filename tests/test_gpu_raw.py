@@ -1,0 +1,142 @@
+"""GPU parity of the raw path (exact int8 Gram + normalisation + fused g2) and
+of g2_from_two_time, against the CPU FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.gpu_util import say, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2407_20356_amd import api
+    assert torch.cuda.is_available()
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _case(n_px_side, n_frames, n_roi, seed, dtype="u8", mu=0.3, zero_frames=()):
+    H = W = n_px_side
+    labels = (synth.annular_labels(H, W, n_roi, r_in=1.0) if n_roi > 1
+              else np.zeros(H * W, dtype=np.int32))
+    F = synth.speckle_frames_numpy(H * W, n_frames, mu, 0.2, 10.0, dtype, seed=seed, max_count=127)
+    for t in zero_frames:
+        F[t] = 0
+    return F, labels
+
+
+@pytest.mark.parametrize("n_frames,n_roi,dtype", [(300, 1, "u8"), (257, 3, "u16"), (130, 2, "u8")])
+def test_raw_gram_exact_and_c_f64(ctx, n_frames, n_roi, dtype):
+    from paper_2407_20356_amd import api
+    F, labels = _case(32, n_frames, n_roi, seed=n_frames, dtype=dtype, zero_frames=(5,))
+    say(f"raw f64 N={n_frames} n_roi={n_roi} {dtype}")
+    C, g2, npairs, gram = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), n_roi,
+                                                     c_dtype=__import__("torch").float64, want_gram=True)
+    ctx.sync()
+    C, g2, npairs, gram = to_np(C), to_np(g2), to_np(npairs), to_np(gram)
+    for r in range(n_roi):
+        G = O.raw_gram(F, labels, r)
+        np.testing.assert_array_equal(gram[r], G)
+        Cref = O.raw_two_time(F, labels, r)
+        # identical FP64 operations in the same order: identical values
+        np.testing.assert_array_equal(np.isnan(C[r]), np.isnan(Cref))
+        np.testing.assert_allclose(C[r], Cref, rtol=1e-15, atol=0, equal_nan=True)
+        assert np.array_equal(np.nan_to_num(C[r]), np.nan_to_num(C[r].T))
+        gref, nref = O.g2_from_two_time(Cref)
+        np.testing.assert_array_equal(npairs[r], nref)
+        np.testing.assert_allclose(g2[r], gref, rtol=1e-12, equal_nan=True)
+
+
+def test_raw_f32_window_and_single_roi(ctx):
+    import torch
+    from paper_2407_20356_amd import api
+    F, labels = _case(40, 400, 4, seed=11)
+    t0, t1 = 37, 311
+    for roi in (2, -1):
+        say(f"raw f32 window [{t0},{t1}) roi={roi}")
+        C, g2, npairs, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 4, roi=roi, t0=t0, t1=t1)
+        ctx.sync()
+        C, g2, npairs = to_np(C), to_np(g2), to_np(npairs)
+        rois = [roi] if roi >= 0 else list(range(4))
+        for i, r in enumerate(rois):
+            Cref = O.raw_two_time(F[t0:t1], labels, r)
+            np.testing.assert_allclose(C[i], Cref.astype(np.float32), rtol=0, atol=0, equal_nan=True)
+            gref, nref = O.g2_from_two_time(Cref)
+            np.testing.assert_array_equal(npairs[i], nref)
+            # g2 sums the fp32 entries in fp64
+            np.testing.assert_allclose(g2[i], O.g2_from_two_time(Cref.astype(np.float32))[0], rtol=1e-12)
+
+
+def test_raw_g2_only_matches_with_c(ctx):
+    from paper_2407_20356_amd import api
+    F, labels = _case(24, 500, 2, seed=3)
+    say("raw g2-only vs with-C")
+    _, g2a, na, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 2, want_c=False)
+    _, g2b, nb, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 2, want_c=True)
+    ctx.sync()
+    np.testing.assert_array_equal(to_np(g2a), to_np(g2b))
+    np.testing.assert_array_equal(to_np(na), to_np(nb))
+
+
+def test_raw_rejects_counts_above_127(ctx):
+    from paper_2407_20356_amd import api
+    F = np.full((20, 64), 3, dtype=np.uint16)
+    F[7, 5] = 300
+    labels = np.zeros(64, dtype=np.int32)
+    say("raw count > 127 raises ERANGE at sync")
+    api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 1)
+    with pytest.raises(api.XpcsError) as ei:
+        ctx.sync()
+    assert ei.value.status == -3
+    ctx.sync()   # the flag is cleared
+
+
+def test_bad_label_is_reported(ctx):
+    from paper_2407_20356_amd import api
+    F = np.ones((16, 32), dtype=np.uint8)
+    labels = np.zeros(32, dtype=np.int32)
+    labels[3] = 9
+    say("label outside [-1, n_roi)")
+    api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 2)
+    with pytest.raises(api.XpcsError) as ei:
+        ctx.sync()
+    assert ei.value.status == -1
+
+
+def test_host_argument_errors(ctx):
+    import torch
+    from paper_2407_20356_amd import api
+    F = to_dev(np.ones((16, 32), dtype=np.uint8))
+    labels = to_dev(np.zeros(32, dtype=np.int32))
+    say("host-side argument errors")
+    with pytest.raises(api.XpcsError):
+        api.correlate_two_time_raw(ctx, F, labels, 1, t0=10, t1=5)
+    with pytest.raises(api.XpcsError):
+        api.correlate_two_time_raw(ctx, F, labels, 1, roi=3)
+    with pytest.raises(api.XpcsError):
+        api.compress_frames(ctx, F, labels, 1, k=30)      # k + oversample > min(M, N)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_g2_from_two_time(ctx, dtype):
+    import torch
+    from paper_2407_20356_amd import api
+    F, labels = _case(20, 333, 1, seed=5, zero_frames=(0, 100))
+    Cref = O.raw_two_time(F, labels, 0)
+    npdt = np.float32 if dtype == "f32" else np.float64
+    # a padded row stride exercises ldc > n
+    buf = np.full((333, 340), 7.0, dtype=npdt)
+    buf[:, :333] = Cref.astype(npdt)
+    dev = to_dev(buf)[:, :333]
+    say(f"g2_from_two_time {dtype}")
+    g2, npairs = api.g2_from_two_time(ctx, dev)
+    ctx.sync()
+    gref, nref = O.g2_from_two_time(Cref.astype(npdt))
+    np.testing.assert_array_equal(to_np(npairs), nref)
+    np.testing.assert_allclose(to_np(g2), gref, rtol=1e-12, equal_nan=True)
