@@ -144,12 +144,18 @@ def main():
     log("compressed path: warmup + timed steps")
     per_c, wall_c, ph_c = timed(step_compressed, args.steps, args.warmup, "compressed")
     ms_c = 1e3 * wall_c / args.steps
+    log("compressed phases (ms per launch x launches per step): " + ", ".join(
+        f"{kk} {v[0] / v[1]:.3f}x{v[1] // args.steps}" for kk, v in sorted(ph_c.items(), key=lambda kv: -kv[1][0])))
 
     # light parity spot checks on this run (sampled frames; the full checks are in tests/)
     import oracle as O
     rng = np.random.default_rng(0)
     ts = np.sort(rng.choice(N, size=16, replace=False))
-    Fs = frames[torch.from_numpy(ts).to(dev)].cpu().numpy()
+    idx = torch.from_numpy(ts).to(dev)
+    if spec.dtype == "u16":      # torch has no uint16 gather on the device: gather the int16 view
+        Fs = frames.view(torch.int16)[idx].cpu().numpy().view(np.uint16)
+    else:
+        Fs = frames[idx].cpu().numpy()
     U = f.U.cpu().numpy().T.astype(np.float64)
     Ws = Fs.astype(np.float64) @ U
     Wg = (f.V.cpu().numpy().T.astype(np.float64) * f.sigma.cpu().numpy())[ts]
@@ -174,6 +180,8 @@ def main():
         log("raw path: warmup + timed steps")
         per_r, wall_r, ph_r = timed(step_raw, args.raw_steps, 1, "raw")
         ms_r = 1e3 * wall_r / args.raw_steps
+        log("raw phases (ms per launch x launches per step): " + ", ".join(
+            f"{kk} {v[0] / v[1]:.3f}x{v[1] // args.raw_steps}" for kk, v in sorted(ph_r.items(), key=lambda kv: -kv[1][0])))
         raw = {"frames_per_s": N / (ms_r / 1e3), "ms_per_step": ms_r, "p50_ms": percentile(per_r, 50),
                "p99_ms": percentile(per_r, 99), "steps": args.raw_steps,
                "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_r.items()}}

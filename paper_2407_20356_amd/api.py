@@ -159,6 +159,8 @@ def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor,
 
 
 def _alloc_outputs(device, nr, nw, want_c, c_dtype, want_g2):
+    if nw <= 0:
+        return None, None, None       # the library rejects the window itself
     C = torch.empty((nr, nw, nw), dtype=c_dtype, device=device) if want_c else None
     g2 = torch.empty((nr, nw), dtype=torch.float64, device=device) if want_g2 else None
     npairs = torch.empty((nr, nw), dtype=torch.int64, device=device) if want_g2 else None
@@ -209,7 +211,7 @@ def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.
     nr = n_roi if roi == L.XPCS_ALL_ROIS else 1
     if C is None and g2 is None:
         C, g2, npairs = _alloc_outputs(ctx.device, nr, nw, want_c, c_dtype, want_g2)
-    gram = torch.empty((nr, nw, nw), dtype=torch.int64, device=ctx.device) if want_gram else None
+    gram = torch.empty((nr, nw, nw), dtype=torch.int64, device=ctx.device) if want_gram and nw > 0 else None
     ctx.bind_stream()
     ctx.check(ctx.lib.correlate_two_time_raw(
         ctx.handle, _ptr(frames), _frame_dtype(frames), M, N, _ptr(roi_label), n_roi, roi, t0, t1, _ptr(C),

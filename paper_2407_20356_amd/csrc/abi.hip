@@ -3,6 +3,7 @@
 // library; the host only validates and enqueues.
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "internal.hpp"
@@ -46,14 +47,17 @@ size_t g2_part_bytes(int64_t nw, int nr) {
 size_t g2_cnt_bytes(int64_t nw, int nr) { return (size_t)n_tiles_upper(nw) * nr * kDiag * sizeof(int); }
 
 struct Orth {
-    // orthonormalise the first `ell` columns of a tall column-major matrix
-    // (CholeskyQR twice, FP64 Gram and factor).
+    // Orthonormalise the first `ell` columns of a tall column-major matrix with
+    // Cholesky QR (FP64 Gram and factor): once when the result only feeds a bf16
+    // product (the subspace passes), twice when it is the final basis.
     static xpcs_status run(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ell,
-                           void *tmp, bool tmp_f64, double *G, double *R1, double *R2, const TsOut &final_out) {
+                           void *tmp, bool tmp_f64, double *G, double *R1, double *R2, const TsOut &final_out,
+                           int passes = 2) {
         xpcs_status st = launch_tsgram(ctx, A, a_f64, rows, lda, ell, nullptr, nullptr, 1, G);
         if (st) return st;
         st = launch_cholinv(ctx, G, ell, 1e-13, nullptr, R1);
         if (st) return st;
+        if (passes == 1) return launch_tsmul(ctx, A, a_f64, rows, lda, ell, R1, ell, nullptr, final_out);
         TsOut o1;
         if (tmp_f64) {
             o1.out64 = static_cast<double *>(tmp);
@@ -109,12 +113,14 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     const int cols = online ? k : ell;
     const int L = (int)up(cols, 16);
     const int64_t ldt = up(N, 32), ldq = up(M, 32);
-    const FrameProj plan = plan_proj_frames(M, N, L, n_roi);
+    const FrameProj plan = plan_proj_frames(M, N, L, n_roi, true);       // final pass: hi + lo + ROI sums
+    const FrameProj plan_q = plan_proj_frames(M, N, L, 0, false);        // power pass: hi only
     // workspace layout
     size_t need = 0;
     auto add = [&](size_t b) { need += align_up(b, 256) + 256; };
     const size_t b_om = (size_t)L * ldt * 2, b_y = (size_t)L * M * 4, b_q16 = (size_t)L * ldq * 2;
-    const size_t b_z = (size_t)L * N * 8, b_part = (size_t)plan.nchunks * N * plan.ncols * 4;
+    const size_t b_z = (size_t)L * N * 8;
+    const size_t b_part = (size_t)std::max(plan.nchunks * plan.ncols, plan_q.nchunks * plan_q.ncols) * N * 4;
     const size_t b_small = (size_t)kMaxEll * kMaxEll * 8;
     add(b_om); add(b_y); add(b_y); add(b_q16); add(b_q16); add(b_z); add(b_z); add(b_part);
     for (int i = 0; i < 6; ++i) add(b_small);
@@ -170,16 +176,16 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
             o.ldh = ldq;
             o.Lpad = L;
             o.rows_pad = ldq;
-            if ((st = Orth::run(ctx, Ya, false, M, M, ell, Yb, false, G, R1, R2, o))) return st;
-            if ((st = launch_proj_frames(ctx, frames, dtype, M, N, qhi, nullptr, ldq, L, roi_label, 0, plan, part)))
+            if ((st = Orth::run(ctx, Ya, false, M, M, ell, Yb, false, G, R1, R2, o, 1))) return st;
+            if ((st = launch_proj_frames(ctx, frames, dtype, M, N, qhi, nullptr, ldq, L, roi_label, 0, plan_q, part)))
                 return st;
-            if ((st = launch_proj_frames_reduce(ctx, part, plan, N, L, 0, Za, N, nullptr))) return st;
+            if ((st = launch_proj_frames_reduce(ctx, part, plan_q, N, L, 0, Za, N, nullptr))) return st;
             TsOut oz;
             oz.hi = om;                                 // reuse the sketch buffer for Qz
             oz.ldh = ldt;
             oz.Lpad = L;
             oz.rows_pad = ldt;
-            if ((st = Orth::run(ctx, Za, true, N, N, ell, Zb, true, G, R1, R2, oz))) return st;
+            if ((st = Orth::run(ctx, Za, true, N, N, ell, Zb, true, G, R1, R2, oz, 1))) return st;
             if ((st = launch_proj_pixels(ctx, frames, dtype, M, N, om, ldt, L, Ya))) return st;
         }
         // 3. Q = orth(Y) in fp32 + bf16 hi/lo
@@ -313,7 +319,7 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
     if ((st = launch_roi_count(ctx, roi_label, M, n_roi, npix))) return st;
     if ((st = launch_roi_order(ctx, roi_label, M, n_roi, npix, kRawPad, off, perm, qroi, cap))) return st;
     if ((st = launch_zero(ctx, amax, 256))) return st;
-    if ((st = launch_gather_i8(ctx, frames, dtype, M, t0, nw, perm, qroi, off, n_roi, ldx, xs, S, amax))) return st;
+    if ((st = launch_gather_i8(ctx, frames, dtype, M, t0, nw, perm, qroi, off, n_roi, ldx, xs, S, amax, cap))) return st;
     if ((st = launch_raw_gram_tiles(ctx, xs, ldx, off, npix, S, nw, r0, nr, amax, M, o))) return st;
     if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, nw, nr, g2, npairs))) return st;
     return XPCS_OK;

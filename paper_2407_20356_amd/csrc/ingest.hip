@@ -87,62 +87,84 @@ __global__ __launch_bounds__(1024) void roi_order_kernel(const int32_t *__restri
     }
 }
 
+// Block = (4096 ROI-sorted positions) x (32 frames).  A thread owns 4 consecutive
+// positions (never split between ROIs: ROI starts are multiples of 64), keeps
+// their pixel indices in registers for all 32 frames, and writes one packed
+// 4-byte word per frame, so both the gathered loads and the stores are
+// contiguous across the wave.  ROI sums go through LDS (int, exact) and then one
+// exact 64-bit atomic per (frame, ROI) and block.
+constexpr int kGatherQ = 4096;
+constexpr int kGatherT = 32;
+constexpr int kGatherSlots = 64;
+
 template <typename T>
 __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ frames, int64_t M, int64_t t0,
                                                         int64_t nw, const int32_t *__restrict__ perm,
                                                         const int32_t *__restrict__ qroi,
                                                         const int64_t *__restrict__ off, int n_roi,
                                                         int64_t ldx, int8_t *__restrict__ xs,
-                                                        int64_t *__restrict__ S, int *amax, int *flags) {
-    __shared__ int s_sum[kMaxRoiLds];
+                                                        unsigned long long *__restrict__ S, int *amax, int *flags) {
+    __shared__ int s_sum[kGatherT][kGatherSlots];
     const int64_t total = off[n_roi];
+    const int64_t qb = (int64_t)blockIdx.x * kGatherQ;
+    if (qb >= total) return;
+    const int64_t tb = (int64_t)blockIdx.y * kGatherT;
+    const int r_first = qroi[qb];
+    for (int idx = threadIdx.x; idx < kGatherT * kGatherSlots; idx += blockDim.x) (&s_sum[0][0])[idx] = 0;
+    __syncthreads();
     int vmax = 0;
     bool over = false;
-    for (int r = threadIdx.x; r < n_roi; r += blockDim.x) s_sum[r] = 0;
-    __syncthreads();
-    for (int64_t tl = blockIdx.x; tl < nw; tl += gridDim.x) {
+    constexpr int kPasses = kGatherQ / (4 * 256);
+    int px[kPasses][4];
+    int roi[kPasses];
+    bool live[kPasses];
+#pragma unroll
+    for (int ps = 0; ps < kPasses; ++ps) {
+        const int64_t q = qb + 4 * (threadIdx.x + 256 * ps);
+        live[ps] = q < total;
+        roi[ps] = live[ps] ? qroi[q] : -1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) px[ps][e] = live[ps] ? perm[q + e] : -1;
+    }
+    const int64_t tend = tb + kGatherT < nw ? tb + kGatherT : nw;
+    for (int64_t tl = tb; tl < tend; ++tl) {
         const T *fr = frames + (t0 + tl) * M;
-        int cur = -1, acc = 0;
-        for (int64_t q = (int64_t)threadIdx.x * 16; q < total; q += (int64_t)blockDim.x * 16) {
-            int vals[16];
+#pragma unroll
+        for (int ps = 0; ps < kPasses; ++ps) {
+            if (!live[ps]) continue;
+            int v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = px[ps][e] >= 0 ? (int)fr[px[ps][e]] : 0;
             int sum = 0;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                int p = perm[q + e];
-                int v = p >= 0 ? (int)fr[p] : 0;
-                vmax = v > vmax ? v : vmax;
-                if (v > 127) {
+            for (int e = 0; e < 4; ++e) {
+                vmax = v[e] > vmax ? v[e] : vmax;
+                if (v[e] > 127) {
                     over = true;
-                    v = 127;
+                    v[e] = 127;
                 }
-                vals[e] = v;
-                sum += v;
+                sum += v[e];
             }
-            i32x4 packed;
-#pragma unroll
-            for (int w = 0; w < 4; ++w)
-                packed[w] = (vals[4 * w] & 0xff) | ((vals[4 * w + 1] & 0xff) << 8) |
-                            ((vals[4 * w + 2] & 0xff) << 16) | ((vals[4 * w + 3] & 0xff) << 24);
-            *reinterpret_cast<i32x4 *>(xs + tl * ldx + q) = packed;
-            // ROI starts are multiples of 64, so a 16-pixel group lies in one ROI.
-            int r = qroi[q];
-            if (r != cur) {
-                if (cur >= 0 && acc) atomicAdd(&s_sum[cur], acc);
-                cur = r;
-                acc = 0;
+            const int word = (v[0] & 0xff) | ((v[1] & 0xff) << 8) | ((v[2] & 0xff) << 16) | ((v[3] & 0xff) << 24);
+            const int64_t q = qb + 4 * (threadIdx.x + 256 * ps);
+            *reinterpret_cast<int *>(xs + tl * ldx + q) = word;
+            if (sum) {
+                const int slot = roi[ps] - r_first;
+                if (slot < kGatherSlots)
+                    atomicAdd(&s_sum[tl - tb][slot], sum);
+                else
+                    atomicAdd(&S[(int64_t)roi[ps] * nw + tl], (unsigned long long)sum);
             }
-            acc += sum;
         }
-        if (cur >= 0 && acc) atomicAdd(&s_sum[cur], acc);
-        __syncthreads();
-        for (int r = threadIdx.x; r < n_roi; r += blockDim.x) {
-            S[(int64_t)r * nw + tl] = s_sum[r];
-            s_sum[r] = 0;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kGatherT * kGatherSlots; idx += blockDim.x) {
+        const int tt = idx / kGatherSlots, slot = idx % kGatherSlots;
+        const int v = s_sum[tt][slot];
+        if (v && r_first + slot < n_roi && tb + tt < nw)
+            atomicAdd(&S[(int64_t)(r_first + slot) * nw + tb + tt], (unsigned long long)v);
     }
     if (over) atomicOr(&flags[kFlagRange], 1);
-    // wave max then one atomic per wave
     for (int o = 32; o > 0; o >>= 1) {
         int v = __shfl_xor(vmax, o);
         vmax = v > vmax ? v : vmax;
@@ -177,20 +199,23 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
     return XPCS_OK;
 }
 
-xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t t0,
-                             int64_t nw, const int32_t *perm, const int32_t *qroi, const int64_t *off,
-                             int n_roi, int64_t ldx, int8_t *xs, int64_t *S, int *amax) {
+xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t t0, int64_t nw,
+                             const int32_t *perm, const int32_t *qroi, const int64_t *off, int n_roi, int64_t ldx,
+                             int8_t *xs, int64_t *S, int *amax, int64_t total_cap) {
     Phase phase_(ctx, "gather_i8");
     if (ldx % 16) return fail(ctx, XPCS_EINVAL, "internal: gather row stride not a multiple of 16");
-    int grid = nw < 4096 ? (int)nw : 4096;
+    // the sums are accumulated with atomics: start from zero
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(256), dim3(256), 0, ctx->stream, S, (int64_t)n_roi * nw, (int64_t)0);
+    dim3 grid((unsigned)((total_cap + kGatherQ - 1) / kGatherQ), (unsigned)((nw + kGatherT - 1) / kGatherT));
+    auto *Su = reinterpret_cast<unsigned long long *>(S);
     if (dtype == XPCS_U8)
-        hipLaunchKernelGGL(gather_i8_kernel<uint8_t>, dim3(grid), dim3(256), 0, ctx->stream,
-                           static_cast<const uint8_t *>(frames), M, t0, nw, perm, qroi, off, n_roi,
-                           ldx, xs, S, amax, ctx->flags);
+        hipLaunchKernelGGL(gather_i8_kernel<uint8_t>, grid, dim3(256), 0, ctx->stream,
+                           static_cast<const uint8_t *>(frames), M, t0, nw, perm, qroi, off, n_roi, ldx, xs, Su,
+                           amax, ctx->flags);
     else
-        hipLaunchKernelGGL(gather_i8_kernel<uint16_t>, dim3(grid), dim3(256), 0, ctx->stream,
-                           static_cast<const uint16_t *>(frames), M, t0, nw, perm, qroi, off, n_roi,
-                           ldx, xs, S, amax, ctx->flags);
+        hipLaunchKernelGGL(gather_i8_kernel<uint16_t>, grid, dim3(256), 0, ctx->stream,
+                           static_cast<const uint16_t *>(frames), M, t0, nw, perm, qroi, off, n_roi, ldx, xs, Su,
+                           amax, ctx->flags);
     XPCS_LAUNCH_CHECK(ctx, "gather_i8");
     return XPCS_OK;
 }

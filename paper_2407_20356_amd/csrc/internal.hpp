@@ -74,6 +74,7 @@ struct xpcs_ctx {
     xpcs::Workspace scratch;     // launcher-private temporaries, reused launch after launch
     int *flags = nullptr;        // device int[kNumFlags]
     std::string last_error;
+    void *tr_buf = nullptr;                      // small row-major copy of a tall x small product's T
     bool timing = false;                         // phase timing enabled
     std::vector<xpcs::PhaseRecord> phases;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;          // reusable events
@@ -134,7 +135,7 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
 xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M,
                              int64_t t0, int64_t nw, const int32_t *perm, const int32_t *qroi,
                              const int64_t *off, int n_roi, int64_t ldx, int8_t *xs, int64_t *S,
-                             int *amax);
+                             int *amax, int64_t total_cap);
 
 // ---------------------------------------------------------------- tile pass (tiles.hip)
 struct TileOut {
@@ -188,8 +189,10 @@ struct FrameProj {
     int64_t nchunks = 0;
     int64_t chunk = 0;      // pixels per chunk (multiple of 32)
     int ncols = 0;          // L + indicator columns rounded to 16
+    int frames_per_block = 0;
 };
-FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind);
+// Plan for a pass with (lo = true) or without the residual term of Q.
+FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo);
 xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
                                const unsigned short *q_hi, const unsigned short *q_lo, int64_t ldq,
                                int L, const int32_t *labels, int n_ind, const FrameProj &plan,

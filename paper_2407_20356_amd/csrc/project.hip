@@ -57,44 +57,151 @@ __device__ __forceinline__ unsigned short count_lo_bits(unsigned v) {
     const float hi = bf16_bits_to_f32(count_hi_bits(v));
     return (unsigned short)(__builtin_bit_cast(unsigned, (float)v - hi) >> 16);
 }
+// Two counts -> two packed bf16 (hi parts).
+__device__ __forceinline__ unsigned pack_hi2(unsigned a, unsigned b) {
+    const unsigned fa = __builtin_bit_cast(unsigned, (float)a), fb = __builtin_bit_cast(unsigned, (float)b);
+    return (fb & 0xffff0000u) | (fa >> 16);
+}
 
-template <typename T, int RB>
-struct PixVec;
+// 8 counts (one MFMA K group) held packed: 16 bytes for u16, 8 bytes for u8.
+template <typename T>
+struct Pack8;
 template <>
-struct PixVec<uint16_t, 4> { typedef unsigned long long type; };
-template <>
-struct PixVec<uint16_t, 2> { typedef unsigned type; };
-template <>
-struct PixVec<uint8_t, 4> { typedef unsigned type; };
-template <>
-struct PixVec<uint8_t, 2> { typedef unsigned short type; };
-
-template <typename T, int RB>
-__device__ __forceinline__ void load_pixels(const T *__restrict__ src, bool vec, int nvalid,
-                                            unsigned (&v)[RB]) {
-    if (vec && nvalid >= RB) {
-        typedef typename PixVec<T, RB>::type V;
-        const V x = *reinterpret_cast<const V *>(src);
-#pragma unroll
-        for (int s = 0; s < RB; ++s) v[s] = (unsigned)((x >> (8 * sizeof(T) * s)) & ((1u << (8 * sizeof(T))) - 1u));
-    } else {
-#pragma unroll
-        for (int s = 0; s < RB; ++s) v[s] = s < nvalid ? (unsigned)src[s] : 0u;
+struct Pack8<uint16_t> {
+    typedef i32x4 type;
+    static __device__ __forceinline__ unsigned get(const type &x, int e) {
+        return (unsigned)(x[e >> 1] >> (16 * (e & 1))) & 0xffffu;
     }
+    static __device__ __forceinline__ bool any_ge256(const type &x) {
+        return ((x[0] | x[1] | x[2] | x[3]) & 0xff00ff00) != 0;
+    }
+};
+template <>
+struct Pack8<uint8_t> {
+    typedef int2 type;
+    static __device__ __forceinline__ unsigned get(const type &x, int e) {
+        return (unsigned)((e < 4 ? x.x : x.y) >> (8 * (e & 3))) & 0xffu;
+    }
+    static __device__ __forceinline__ bool any_ge256(const type &) { return false; }
+};
+
+template <typename T>
+__device__ __forceinline__ u16x8 pack8_to_bf16(const typename Pack8<T>::type &x) {
+    i32x4 r;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) r[w] = (int)pack_hi2(Pack8<T>::get(x, 2 * w), Pack8<T>::get(x, 2 * w + 1));
+    return __builtin_bit_cast(u16x8, r);
+}
+template <typename T>
+__device__ __forceinline__ u16x8 pack8_to_bf16_lo(const typename Pack8<T>::type &x) {
+    u16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = count_lo_bits(Pack8<T>::get(x, e));
+    return r;
+}
+
+// Load 8 consecutive counts src[0..8) (nv of them valid) as one packed K group.
+template <typename T>
+__device__ __forceinline__ typename Pack8<T>::type load8(const T *__restrict__ src, int nv, bool vec) {
+    typedef typename Pack8<T>::type V;
+    if (vec && nv == 8) return *reinterpret_cast<const V *>(src);
+    unsigned v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = e < nv ? (unsigned)src[e] : 0u;
+    V x;
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) x[w] = (int)(v[2 * w] | (v[2 * w + 1] << 16));
+    } else {
+        x.x = (int)(v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24));
+        x.y = (int)(v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24));
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------- LDS staging of the thin operand
+// One 32-wide K step of a bf16 row-major operand (rows j < 16*NCB, K contiguous),
+// staged as rows of kQp u16 (32 + 8 padding against bank conflicts).
+constexpr int kQp = 40;
+
+template <int NCB>
+struct Stage16 {
+    static constexpr int kUnits = NCB * 16 * 4;           // 16-byte units per K step
+    static constexpr int kPer = (kUnits + 255) / 256;
+    i32x4 r[kPer];
+    // global rows src[j*ld + k0 + 8*part], j < 16*NCB
+    __device__ __forceinline__ void load(const unsigned short *__restrict__ src, int64_t ld, int64_t k0) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int u = threadIdx.x + 256 * i;
+            if (u < kUnits) r[i] = *reinterpret_cast<const i32x4 *>(src + (int64_t)(u >> 2) * ld + k0 + 8 * (u & 3));
+        }
+    }
+    __device__ __forceinline__ void store(unsigned short *dst) const {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int u = threadIdx.x + 256 * i;
+            if (u < kUnits) *reinterpret_cast<i32x4 *>(dst + (u >> 2) * kQp + 8 * (u & 3)) = r[i];
+        }
+    }
+};
+
+__device__ __forceinline__ u16x8 lds_frag(const unsigned short *base, int row, int lg) {
+    return *reinterpret_cast<const u16x8 *>(base + row * kQp + 8 * lg);
 }
 
 // ---------------------------------------------------------------- pixel-space product
-// Y[j][p] = sum_t X[t][p] * B[j][t], j < 16*NCB (+ column-group offset).
+// Y[j][p] = sum_t X[t][p] * B[j][t], j in this block's column group (16*NCB columns).
+// A wave owns 16*RB pixels as RB interleaved MFMA row blocks (pixel = base + RB*row
+// + s); a lane loads RB adjacent pixels of 8 frames.  B's K step is staged in LDS.
+template <typename T, int RB>
+struct PixPack;
+template <>
+struct PixPack<uint16_t, 4> { typedef int2 type; };
+template <>
+struct PixPack<uint16_t, 2> { typedef int type; };
+template <>
+struct PixPack<uint8_t, 4> { typedef int type; };
+template <>
+struct PixPack<uint8_t, 2> { typedef unsigned short type; };
+
+template <typename T, int RB>
+__device__ __forceinline__ unsigned pix_get(const typename PixPack<T, RB>::type &x, int s) {
+    if constexpr (sizeof(T) == 2 && RB == 4) return (unsigned)(((s < 2 ? x.x : x.y) >> (16 * (s & 1))) & 0xffff);
+    else return (unsigned)((((unsigned long long)(unsigned)x) >> (8 * sizeof(T) * s)) & ((1u << (8 * sizeof(T))) - 1u));
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ typename PixPack<T, RB>::type load_pix(const T *__restrict__ src, int nvalid, bool vec) {
+    typedef typename PixPack<T, RB>::type V;
+    if (vec && nvalid == RB) return *reinterpret_cast<const V *>(src);
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int s = 0; s < RB; ++s)
+        if (s < nvalid) acc |= (unsigned long long)src[s] << (8 * sizeof(T) * s);
+    if constexpr (sizeof(T) == 2 && RB == 4) {
+        int2 r;
+        r.x = (int)(acc & 0xffffffffull);
+        r.y = (int)(acc >> 32);
+        return r;
+    } else {
+        return (V)acc;
+    }
+}
+
 template <typename T, int RB, int NCB>
 __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ Y, bool vec) {
+    typedef typename PixPack<T, RB>::type PV;
+    __shared__ unsigned short sb[2][NCB * 16 * kQp];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const int jg = blockIdx.y * 16 * NCB;                  // column-group offset
     const int64_t pb = ((int64_t)blockIdx.x * 4 + wv) * (16 * RB);
     const int64_t pl = pb + RB * lr;                       // this lane's first pixel
     const int nvalid = pl >= M ? 0 : (M - pl >= RB ? RB : (int)(M - pl));
+    const unsigned short *Bg = B + (int64_t)jg * ldb;
 
     f32x4 acc[RB][NCB];
 #pragma unroll
@@ -102,46 +209,63 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[s][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    const unsigned short *brow[NCB];
+    const int nsteps = (int)((N + 31) / 32);
+    Stage16<NCB> st;
+    st.load(Bg, ldb, 0);
+    st.store(sb[0]);
+    PV xn[8];
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) brow[c] = B + (int64_t)(jg + 16 * c + lr) * ldb + 8 * lg;
-
-    for (int64_t tk = 0; tk < N; tk += 32) {
-        unsigned v[8][RB];
-        bool big = false;
+    for (int e = 0; e < 8; ++e) {
+        const int64_t t = 8 * lg + e;
+        xn[e] = (t < N && nvalid > 0) ? load_pix<T, RB>(X + t * M + pl, nvalid, vec) : PV{};
+    }
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        const int64_t tk = (int64_t)step * 32;
+        PV xc[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t t = tk + 8 * lg + e;
-            if (t < N && nvalid > 0) {
-                load_pixels<T, RB>(X + t * M + pl, vec, nvalid, v[e]);
-            } else {
+        for (int e = 0; e < 8; ++e) xc[e] = xn[e];
+        const bool more = step + 1 < nsteps;
+        if (more) {
+            st.load(Bg, ldb, tk + 32);
 #pragma unroll
-                for (int s = 0; s < RB; ++s) v[e][s] = 0u;
+            for (int e = 0; e < 8; ++e) {
+                const int64_t t = tk + 32 + 8 * lg + e;
+                xn[e] = (t < N && nvalid > 0) ? load_pix<T, RB>(X + t * M + pl, nvalid, vec) : PV{};
             }
-#pragma unroll
-            for (int s = 0; s < RB; ++s) big |= v[e][s] > 256u;
         }
-        u16x8 bf[NCB];
+        const unsigned short *cur = sb[step & 1];
+        bool big = false;
+        if constexpr (sizeof(T) > 1) {
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) bf[c] = *reinterpret_cast<const u16x8 *>(brow[c] + tk);
+            for (int e = 0; e < 8; ++e)
 #pragma unroll
-        for (int s = 0; s < RB; ++s) {
-            u16x8 a;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a[e] = count_hi_bits(v[e][s]);
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) acc[s][c] = mfma_bf16(a, bf[c], acc[s][c]);
+                for (int s = 0; s < RB; ++s) big |= pix_get<T, RB>(xc[e], s) > 255u;
         }
-        if (sizeof(T) > 1 && __ballot(big)) {
+        // plane 0: bf16 of every count (exact below 256); plane 1, only when some
+        // count of this K step is >= 256: the exact bf16 remainders.
+#pragma unroll 1
+        for (int plane = 0; plane < 2; ++plane) {
+            if (plane == 1 && (sizeof(T) == 1 || !__ballot(big))) break;
 #pragma unroll
             for (int s = 0; s < RB; ++s) {
                 u16x8 a;
+                if (plane == 0) {
+                    i32x4 aw;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) a[e] = count_lo_bits(v[e][s]);
+                    for (int w = 0; w < 4; ++w)
+                        aw[w] = (int)pack_hi2(pix_get<T, RB>(xc[2 * w], s), pix_get<T, RB>(xc[2 * w + 1], s));
+                    a = __builtin_bit_cast(u16x8, aw);
+                } else {
 #pragma unroll
-                for (int c = 0; c < NCB; ++c) acc[s][c] = mfma_bf16(a, bf[c], acc[s][c]);
+                    for (int e = 0; e < 8; ++e) a[e] = count_lo_bits(pix_get<T, RB>(xc[e], s));
+                }
+#pragma unroll
+                for (int c = 0; c < NCB; ++c) acc[s][c] = mfma_bf16(a, lds_frag(cur, 16 * c + lr, lg), acc[s][c]);
             }
         }
+        if (more) st.store(sb[(step + 1) & 1]);
+        __syncthreads();
     }
     // acc[s][c][i] = Y[j = jg + 16c + lr][p = pb + RB*(4*lg + i) + s]
 #pragma unroll
@@ -161,6 +285,8 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
 // ---------------------------------------------------------------- frame-space product
 // part[chunk][t][j] = sum_{p in chunk} X[t][p] * Q[j][p] for j < 16*NCB (hi [+ lo]),
 // and for j = 16*NCB + i < 16*(NCB + NIB) the indicator (label[p] == i).
+// Q's K step (and the labels) are staged in LDS; the next step's counts are
+// loaded while the current step runs.
 template <typename T, int RB, int NCB, int NIB, bool LO>
 __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ qh,
@@ -168,7 +294,11 @@ __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ 
                                                           int64_t ldq, const int32_t *__restrict__ labels,
                                                           int64_t chunk, int nfb, int ncols,
                                                           float *__restrict__ part, bool vec) {
+    typedef typename Pack8<T>::type PK;
     constexpr int FB = RB * 16 * 4;       // frames per block
+    __shared__ unsigned short sqh[2][NCB * 16 * kQp];
+    __shared__ unsigned short sql[LO ? 2 : 1][LO ? NCB * 16 * kQp : 1];
+    __shared__ int slab[2][32];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     // XCD-aware placement: consecutive blocks on one XCD walk the frame blocks of one chunk.
@@ -184,96 +314,83 @@ __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ 
 #pragma unroll
         for (int c = 0; c < NCB + NIB; ++c) acc[s][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    const T *xrow[RB];
+    // lane row offsets (frames tb + 16s + lr) relative to the wave's first frame row
+    const T *Xw = X + (tb < N ? tb : 0) * M;
+    int xo[RB];
     bool rok[RB];
 #pragma unroll
     for (int s = 0; s < RB; ++s) {
-        const int64_t t = tb + 16 * s + lr;
-        rok[s] = t < N;
-        xrow[s] = X + (rok[s] ? t : 0) * M + 8 * lg;
+        rok[s] = tb + 16 * s + lr < N;
+        xo[s] = rok[s] ? (16 * s + lr) * (int)M + 8 * lg : 0;
     }
-    const unsigned short *qhr[NCB], *qlr[NCB];
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-        qhr[c] = qh + (int64_t)(16 * c + lr) * ldq + 8 * lg;
-        qlr[c] = LO ? ql + (int64_t)(16 * c + lr) * ldq + 8 * lg : nullptr;
-    }
-
-    for (int64_t p0 = p_begin; p0 < p_end; p0 += 32) {
+    const int nsteps = p_end > p_begin ? (int)((p_end - p_begin + 31) / 32) : 0;
+    Stage16<NCB> sth, stl;
+    int labv = -1;
+    auto stage_load = [&](int64_t p0) {
+        sth.load(qh, ldq, p0);
+        if constexpr (LO) stl.load(ql, ldq, p0);
+        if constexpr (NIB > 0) {
+            if (threadIdx.x < 32) labv = p0 + threadIdx.x < p_end ? labels[p0 + threadIdx.x] : -1;
+        }
+    };
+    auto stage_store = [&](int b) {
+        sth.store(sqh[b]);
+        if constexpr (LO) stl.store(sql[b]);
+        if constexpr (NIB > 0) {
+            if (threadIdx.x < 32) slab[b][threadIdx.x] = labv;
+        }
+    };
+    auto load_x = [&](int64_t p0, PK (&x)[RB]) {
         const int64_t pl = p0 + 8 * lg;
         const int nv = pl >= p_end ? 0 : (p_end - pl >= 8 ? 8 : (int)(p_end - pl));
-        unsigned v[RB][8];
+#pragma unroll
+        for (int s = 0; s < RB; ++s) x[s] = (rok[s] && nv > 0) ? load8<T>(Xw + xo[s] + p0, nv, vec) : PK{};
+    };
+
+    PK xn[RB];
+    if (nsteps > 0) {
+        stage_load(p_begin);
+        stage_store(0);
+        load_x(p_begin, xn);
+    }
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        const int64_t p0 = p_begin + (int64_t)step * 32;
+        PK xc[RB];
+#pragma unroll
+        for (int s = 0; s < RB; ++s) xc[s] = xn[s];
+        const bool more = step + 1 < nsteps;
+        if (more) {
+            stage_load(p0 + 32);
+            load_x(p0 + 32, xn);
+        }
+        const int b = step & 1;
         bool big = false;
 #pragma unroll
-        for (int s = 0; s < RB; ++s) {
-            if (rok[s] && nv == 8 && vec) {
-                if constexpr (sizeof(T) == 2) {
-                    const u16x8 x = *reinterpret_cast<const u16x8 *>(xrow[s] + p0);
+        for (int s = 0; s < RB; ++s) big |= Pack8<T>::any_ge256(xc[s]);
+        // plane 0: bf16 of every count (exact below 256); plane 1, only when some
+        // count of this K step is >= 256: the exact bf16 remainders.
+#pragma unroll 1
+        for (int plane = 0; plane < 2; ++plane) {
+            if (plane == 1 && (sizeof(T) == 1 || !__ballot(big))) break;
+            u16x8 a[RB];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) v[s][e] = x[e];
-                } else {
-                    const unsigned long long x = *reinterpret_cast<const unsigned long long *>(xrow[s] + p0);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) v[s][e] = (unsigned)((x >> (8 * e)) & 0xffull);
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[s][e] = (rok[s] && e < nv) ? (unsigned)xrow[s][p0 + e] : 0u;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) big |= v[s][e] > 256u;
-        }
-        u16x8 a[RB];
-#pragma unroll
-        for (int s = 0; s < RB; ++s)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a[s][e] = count_hi_bits(v[s][e]);
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-            const u16x8 bh = *reinterpret_cast<const u16x8 *>(qhr[c] + p0);
-#pragma unroll
-            for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(a[s], bh, acc[s][c]);
-            if constexpr (LO) {
-                const u16x8 bl = *reinterpret_cast<const u16x8 *>(qlr[c] + p0);
-#pragma unroll
-                for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(a[s], bl, acc[s][c]);
-            }
-        }
-        if constexpr (NIB > 0) {
-            int lab[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) lab[e] = e < nv ? labels[pl + e] : -1;
-#pragma unroll
-            for (int ib = 0; ib < NIB; ++ib) {
-                u16x8 ind;
-                const int want = 16 * ib + lr;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) ind[e] = lab[e] == want ? kBfOne : (unsigned short)0;
-#pragma unroll
-                for (int s = 0; s < RB; ++s) acc[s][NCB + ib] = mfma_bf16(a[s], ind, acc[s][NCB + ib]);
-            }
-        }
-        if (sizeof(T) > 1 && __ballot(big)) {
-            u16x8 al[RB];
-#pragma unroll
-            for (int s = 0; s < RB; ++s)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) al[s][e] = count_lo_bits(v[s][e]);
+            for (int s = 0; s < RB; ++s) a[s] = plane == 0 ? pack8_to_bf16<T>(xc[s]) : pack8_to_bf16_lo<T>(xc[s]);
 #pragma unroll
             for (int c = 0; c < NCB; ++c) {
-                const u16x8 bh = *reinterpret_cast<const u16x8 *>(qhr[c] + p0);
+                const u16x8 bh = lds_frag(sqh[b], 16 * c + lr, lg);
 #pragma unroll
-                for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(al[s], bh, acc[s][c]);
+                for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(a[s], bh, acc[s][c]);
                 if constexpr (LO) {
-                    const u16x8 bl = *reinterpret_cast<const u16x8 *>(qlr[c] + p0);
+                    const u16x8 bl = lds_frag(sql[b], 16 * c + lr, lg);
 #pragma unroll
-                    for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(al[s], bl, acc[s][c]);
+                    for (int s = 0; s < RB; ++s) acc[s][c] = mfma_bf16(a[s], bl, acc[s][c]);
                 }
             }
             if constexpr (NIB > 0) {
                 int lab[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) lab[e] = e < nv ? labels[pl + e] : -1;
+                for (int e = 0; e < 8; ++e) lab[e] = slab[b][8 * lg + e];
 #pragma unroll
                 for (int ib = 0; ib < NIB; ++ib) {
                     u16x8 ind;
@@ -281,10 +398,12 @@ __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ 
 #pragma unroll
                     for (int e = 0; e < 8; ++e) ind[e] = lab[e] == want ? kBfOne : (unsigned short)0;
 #pragma unroll
-                    for (int s = 0; s < RB; ++s) acc[s][NCB + ib] = mfma_bf16(al[s], ind, acc[s][NCB + ib]);
+                    for (int s = 0; s < RB; ++s) acc[s][NCB + ib] = mfma_bf16(a[s], ind, acc[s][NCB + ib]);
                 }
             }
         }
+        if (more) stage_store(b ^ 1);
+        __syncthreads();
     }
     // acc[s][c][i] = part[ch][t = tb + 16s + 4lg + i][j = 16c + lr]
     float *pc = part + (int64_t)ch * N * ncols;
@@ -364,8 +483,9 @@ void launch_pf(int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
                        static_cast<const T *>(X), M, N, qh, ql, ldq, labels, chunk, nfb, ncols, part, vec);
 }
 
-// Frames per block as a function of the accumulator columns (NCB + NIB).
-inline int pf_rb(int ncb, int nib) { return ncb + nib <= 8 ? 4 : 2; }
+// Row blocks per wave (frames per wave / 16) as a function of the accumulator
+// columns: four when the accumulators stay small, else two (register budget).
+inline int pf_rb(int ncb, int nib, bool lo) { return (lo ? 2 * ncb : ncb) + nib <= 8 ? 4 : 2; }
 
 template <typename T, int NIB, bool LO>
 bool dispatch_pf_ncb(int ncb, int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
@@ -374,7 +494,7 @@ bool dispatch_pf_ncb(int ncb, int nblocks, hipStream_t st, const void *X, int64_
     switch (ncb) {
 #define XPCS_PF(n)                                                                                     \
     case n:                                                                                            \
-        if (n + NIB <= 8)                                                                              \
+        if (pf_rb(n, NIB, LO) == 4)                                                                    \
             launch_pf<T, 4, n, NIB, LO>(nblocks, st, X, M, N, qh, ql, ldq, labels, chunk, nfb, ncols,   \
                                         part, vec);                                                    \
         else                                                                                           \
@@ -439,11 +559,11 @@ xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int
     return XPCS_OK;
 }
 
-FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind) {
+FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
     FrameProj p;
     const int nib = (n_ind + 15) / 16;
     p.ncols = L + 16 * nib;
-    const int rb = pf_rb(L / 16, nib);
+    const int rb = pf_rb(L / 16, nib, lo);
     const int64_t fbf = (int64_t)rb * 64;
     const int64_t nfb = (N + fbf - 1) / fbf;
     int64_t want = (2048 + nfb - 1) / nfb;                 // blocks ~ 2048
@@ -455,6 +575,7 @@ FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind) {
     nch = (nch + 7) / 8 * 8;
     p.nchunks = nch;
     p.chunk = chunk;
+    p.frames_per_block = (int)fbf;
     return p;
 }
 
@@ -465,7 +586,9 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
     const int ncb = L / 16, nib = (n_ind + 15) / 16;
     if (nib > 4) return fail(ctx, XPCS_EUNSUPPORTED, "more than 64 ROIs in the fused ROI sums");
-    const int rb = pf_rb(ncb, nib);
+    const int rb = pf_rb(ncb, nib, q_lo != nullptr);
+    if (rb * 64 != plan.frames_per_block)
+        return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
     const int64_t fbf = (int64_t)rb * 64;
     const int nfb = (int)((N + fbf - 1) / fbf);
     const int64_t nblocks = (int64_t)nfb * plan.nchunks;

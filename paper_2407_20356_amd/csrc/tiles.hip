@@ -55,10 +55,10 @@ __device__ __forceinline__ void store4(OutT *dst, const OutT (&v)[4], const bool
 
 // One 64-row half h of a staged tile: direct rows, mirrored columns, diagonal partials.
 // All 256 threads call it; st holds rows [64h, 64h + 64) of the tile at pitch kPitch.
-template <typename StageT, typename OutT>
+template <typename StageT, typename OutT, typename SumT>
 __device__ __forceinline__ void epilogue_half(const StageT *st, int h, int64_t i0, int64_t j0, bool diag,
-                                              int64_t nw, OutT *C, int64_t ldc, bool vec, double &dsum,
-                                              int &dcnt) {
+                                              int64_t nw, OutT *C, int64_t ldc, bool vec, bool any_nan,
+                                              double &dsum, int &dcnt) {
     const int tid = threadIdx.x;
     if (C) {
         // Direct rows: 32 threads x 4 columns per row, 8 rows per pass.
@@ -99,22 +99,35 @@ __device__ __forceinline__ void epilogue_half(const StageT *st, int h, int64_t i
             }
         }
     }
-    // Diagonal partials: thread d handles t2 - t1 offset d - 127 inside the tile.
+    // Diagonal partials: thread d handles the in-tile offset c - r = d - 127 over the
+    // rows of this half where the diagonal exists (exact bounds, no idle iterations).
+    // Partial sums within the half (at most 64 terms) are kept in SumT.
     if (tid < kDiag) {
         const int d = tid - (kTile - 1);
         if (!diag || d >= 0) {
-#pragma unroll 4
-            for (int rl = 0; rl < kHalf; ++rl) {
-                const int r = kHalf * h + rl;
-                const int c = r + d;
-                if (c < 0 || c >= kTile) continue;
-                if (i0 + r >= nw || j0 + c >= nw) continue;
-                const StageT v = st[rl * kPitch + c];
-                if (v == v) {
-                    dsum += (double)v;
-                    dcnt += 1;
+            int r_lo = kHalf * h, r_hi = kHalf * h + kHalf;          // rows [r_lo, r_hi)
+            if (d < 0 && r_lo < -d) r_lo = -d;                       // c = r + d >= 0
+            if (d > 0 && r_hi > kTile - d) r_hi = kTile - d;         // c = r + d < kTile
+            if (i0 + r_hi > nw) r_hi = (int)(nw - i0);               // rows inside the window
+            const int64_t c_lim = nw - j0 - d;                       // and columns: r < nw - j0 - d
+            if (r_hi > c_lim) r_hi = (int)c_lim;
+            SumT sum = 0;
+            int cnt = 0;
+            if (any_nan) {
+                for (int r = r_lo; r < r_hi; ++r) {
+                    const StageT v = st[(r - kHalf * h) * kPitch + r + d];
+                    if (v == v) {
+                        sum += (SumT)v;
+                        cnt += 1;
+                    }
                 }
+            } else {
+#pragma unroll 8
+                for (int r = r_lo; r < r_hi; ++r) sum += (SumT)st[(r - kHalf * h) * kPitch + r + d];
+                cnt = r_hi > r_lo ? r_hi - r_lo : 0;
             }
+            dsum += (double)sum;
+            dcnt += cnt;
         }
     }
 }
@@ -132,17 +145,22 @@ __device__ __forceinline__ void write_diag_partials(double *g2_part, int *g2_cnt
 // chunk (every realistic case: with counts <= 40 a chunk holds 1.3 M pixels);
 // WIDE = true the others, folding int32 chunk sums into int64.  Both are
 // launched; each block leaves at once when its ROI belongs to the other.
+__device__ __forceinline__ int64_t raw_chunk_pixels(const int *__restrict__ amax, int64_t qlen) {
+    const int am = *amax;
+    // int32 accumulation is exact while (pixels per chunk) * amax^2 < 2^31.
+    int64_t kc = am > 0 ? (int64_t)2147483647 / ((int64_t)am * am) : qlen;
+    kc = kc / 64 * 64;
+    return kc < 64 ? 64 : kc;
+}
+
 template <typename OutT, bool WIDE>
-__global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
-    const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
-    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
-    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+__device__ __forceinline__ void raw_gram_tile(
+    int bi, int bj, int64_t tile_id, const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int slot,
+    int64_t ntiles, int64_t kc, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
+    int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
     __shared__ double stage[kHalf * kPitch];
-    const int slot = blockIdx.y;
     const int roi = r0 + slot;
-    int bi, bj;
-    tile_coords(blockIdx.x, nb, bi, bj);
     const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
     const bool diag = bi == bj;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -150,12 +168,6 @@ __global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
     const bool skip = diag && wr > wc;     // strictly below the diagonal: never used
 
     const int64_t q0 = off[roi], qlen = off[roi + 1] - off[roi];
-    const int am = *amax;
-    // int32 accumulation is exact while (pixels per chunk) * amax^2 < 2^31.
-    int64_t kc = am > 0 ? (int64_t)2147483647 / ((int64_t)am * am) : qlen;
-    kc = kc / 64 * 64;
-    if (kc < 64) kc = 64;
-    if ((qlen > kc) != WIDE) return;
 
     const int8_t *arow[4], *brow[4];
     bool aok[4], bok[4];
@@ -265,10 +277,50 @@ __global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
             }
         }
         __syncthreads();
-        epilogue_half<double, OutT>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, dsum, dcnt);
+        epilogue_half<double, OutT, double>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, true, dsum, dcnt);
         __syncthreads();
     }
-    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + blockIdx.x, dsum, dcnt);
+    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * ntiles + tile_id, dsum, dcnt);
+}
+
+// One block per tile; ROIs that need more than one int32 chunk are left to the wide kernel.
+template <typename OutT>
+__global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
+    const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
+    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
+    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    const int slot = blockIdx.y, roi = r0 + slot;
+    const int64_t qlen = off[roi + 1] - off[roi];
+    const int64_t kc = raw_chunk_pixels(amax, qlen);
+    if (qlen > kc) return;
+    int bi, bj;
+    tile_coords(blockIdx.x, nb, bi, bj);
+    raw_gram_tile<OutT, false>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x, kc, C, ldc,
+                               c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
+}
+
+// One block per (tile row, ROI), looping over the row's tiles, for the ROIs whose
+// pixel count needs several int32 chunks (int64 between chunks).  Blocks of other
+// ROIs leave at once; the grid is small, so the launch costs little when unused.
+template <typename OutT>
+__global__ __launch_bounds__(256, 2) void raw_gram_wide_kernel(
+    const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
+    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
+    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    const int slot = blockIdx.y, roi = r0 + slot;
+    const int64_t qlen = off[roi + 1] - off[roi];
+    const int64_t kc = raw_chunk_pixels(amax, qlen);
+    if (qlen <= kc) return;
+    const int bi = blockIdx.x;
+    const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
+    for (int bj = bi; bj < nb; ++bj) {
+        const int64_t D = bj - bi;
+        const int64_t tile_id = D * nb - D * (D - 1) / 2 + bi;
+        raw_gram_tile<OutT, true>(bi, bj, tile_id, xs, ldx, off, roi_npix, S, nw, r0, slot, ntiles, kc, C, ldc,
+                                  c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
+    }
 }
 
 // ---------------------------------------------------------------- low-rank tiles (split-bf16 MFMA)
@@ -333,6 +385,17 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
     OutT *Cr = C ? C + (int64_t)slot * c_roi_stride : nullptr;
     double dsum = 0.0;
     int dcnt = 0;
+    // does the tile touch a frame without photons (NaN entries)?
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    {
+        const int e = threadIdx.x;                 // 256 threads: 128 rows + 128 columns
+        const int64_t t = e < kTile ? i0 + e : j0 + (e - kTile);
+        if (t < nw && !vr[t]) s_bad = 1;
+    }
+    __syncthreads();
+    const bool any_nan = s_bad != 0;
     for (int h = 0; h < 2; ++h) {
         if (wr == h) {
 #pragma unroll
@@ -352,7 +415,7 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
             }
         }
         __syncthreads();
-        epilogue_half<float, OutT>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, dsum, dcnt);
+        epilogue_half<float, OutT, float>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, any_nan, dsum, dcnt);
         __syncthreads();
     }
     write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + blockIdx.x, dsum, dcnt);
@@ -377,7 +440,7 @@ __global__ __launch_bounds__(256) void matrix_diag_tile_kernel(const InT *__rest
             stage[rl * kPitch + c] = (i < n && j < n) ? C[i * ldc + j] : (InT)0;
         }
         __syncthreads();
-        epilogue_half<InT, InT>(stage, h, i0, j0, diag, n, (InT *)nullptr, 0, false, dsum, dcnt);
+        epilogue_half<InT, InT, double>(stage, h, i0, j0, diag, n, (InT *)nullptr, 0, false, true, dsum, dcnt);
         __syncthreads();
     }
     write_diag_partials(g2_part, g2_cnt, blockIdx.x, dsum, dcnt);
@@ -425,20 +488,21 @@ xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx, 
     // The wide variant is only needed when some ROI can exceed the smallest int32 chunk
     // (counts <= 127: 133,120 pixels); M bounds every ROI.
     const bool maybe_wide = max_roi_pixels > 133120;
+    dim3 wgrid((unsigned)nb, (unsigned)nr);
     if (o.C == nullptr || o.c_dtype == XPCS_F32) {
-        hipLaunchKernelGGL((raw_gram_tile_kernel<float, false>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+        hipLaunchKernelGGL(raw_gram_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, xs, ldx, off,
                            roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
                            o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
         if (maybe_wide)
-            hipLaunchKernelGGL((raw_gram_tile_kernel<float, true>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+            hipLaunchKernelGGL(raw_gram_wide_kernel<float>, wgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
                                roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
                                o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
     } else {
-        hipLaunchKernelGGL((raw_gram_tile_kernel<double, false>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+        hipLaunchKernelGGL(raw_gram_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, xs, ldx, off,
                            roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
                            o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
         if (maybe_wide)
-            hipLaunchKernelGGL((raw_gram_tile_kernel<double, true>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+            hipLaunchKernelGGL(raw_gram_wide_kernel<double>, wgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
                                roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
                                o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
     }

@@ -128,7 +128,7 @@ def test_offline_low_rank_data_is_lossless(ctx):
 
 # --------------------------------------------------------------------------- properties of the GPU's own basis
 
-def _check_basis_properties(F, labels, n_roi, fn, k, ey_factor=1.05):
+def _check_basis_properties(F, labels, n_roi, fn, k, ey_factor=1.05, sigma1_rtol=1e-3):
     X = F.astype(np.float64).T
     U, s = fn["U"], fn["sigma"]
     np.testing.assert_array_equal(fn["npix"], O.roi_pixel_counts(labels, n_roi))
@@ -138,7 +138,8 @@ def _check_basis_properties(F, labels, n_roi, fn, k, ey_factor=1.05):
     s_exact = O.exact_basis(F, min(F.shape))[1]
     # interlacing: the singular values of a projection of X cannot exceed those of X
     assert np.all(s <= s_exact[:k] * (1 + 1e-5) + 1e-9)
-    assert abs(s[0] - s_exact[0]) <= 1e-3 * s_exact[0]
+    if sigma1_rtol is not None:
+        assert abs(s[0] - s_exact[0]) <= sigma1_rtol * s_exact[0]
     resid = np.linalg.norm(X - U @ (U.T @ X)) ** 2
     assert resid <= ey_factor * np.sum(s_exact[k:] ** 2)
     # the factors are consistent: W = X^T U, G_R = U_R^T U_R
@@ -175,9 +176,40 @@ def test_offline_basis_single_roi(ctx, power_iters):
     f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 1, k=k, seed=7, power_iters=power_iters)
     ctx.sync()
     fn = _factors_np(f)
-    _check_basis_properties(F, labels, 1, fn, k, ey_factor=1.05 if power_iters else 1.15)
+    # without a power iteration the range finder is visibly worse on a flat noise
+    # spectrum (the FP64 oracle gives the same numbers, see the parity test below)
+    _check_basis_properties(F, labels, 1, fn, k, ey_factor=1.05 if power_iters else 1.10,
+                            sigma1_rtol=1e-3 if power_iters else None)
     C, g2, npairs = _gpu_correlate(ctx, f)
     _check_homomorphic_identity(C, F, labels, 1, fn["U"])
+    # how far the bf16 power pass moves the result from the FP64 pipeline (reported)
+    Uo, so, _ = O.randomized_basis(F, k, 16, power_iters, seed=7)
+    Co = O.compressed_two_time(F, Uo, labels, 0)
+    ok = ~np.isnan(Co)
+    rel = np.abs(C[0][ok] - Co[ok]) / np.maximum(np.abs(Co[ok]), 0.1)
+    print(f"[report] q={power_iters}: sigma rel dev {np.max(np.abs(fn['sigma'] - so) / so):.2e}, "
+          f"C~ vs FP64 pipeline max {rel.max():.2e} p99.9 {np.quantile(rel, 0.999):.2e}", flush=True)
+
+
+def test_offline_pipeline_parity_without_power_iteration(ctx):
+    """Same frames, same seed: with q = 0 the GPU pipeline and the oracle's FP64
+    randomized basis take the same steps (exact integer sketch, orthonormalise,
+    W_l = X^T Q, eigen ranking); only FP32/bf16 hi-lo rounding differs, so the
+    singular values and the compressed correlation must agree elementwise."""
+    from paper_2407_20356_amd import api
+    H = W = 64
+    labels = synth.annular_labels(H, W, 4, r_in=3.0)
+    F = synth.speckle_frames_numpy(H * W, 600, 0.1, 0.2, 30.0, "u8", seed=31)
+    F[100] = 0
+    k, seed = 24, 12345
+    say("offline q=0 parity with the oracle's randomized basis")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 4, k=k, seed=seed, power_iters=0)
+    ctx.sync()
+    fn = _factors_np(f)
+    Uo, so, Vo = O.randomized_basis(F, k, 16, 0, seed=seed)
+    np.testing.assert_allclose(fn["sigma"], so, rtol=1e-5)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, _oracle_compressed(F, Uo, labels, 4))
 
 
 def test_offline_basis_multi_roi_u16(ctx):

@@ -69,8 +69,8 @@ def test_raw_f32_window_and_single_roi(ctx):
             np.testing.assert_allclose(C[i], Cref.astype(np.float32), rtol=0, atol=0, equal_nan=True)
             gref, nref = O.g2_from_two_time(Cref)
             np.testing.assert_array_equal(npairs[i], nref)
-            # g2 sums the fp32 entries in fp64
-            np.testing.assert_allclose(g2[i], O.g2_from_two_time(Cref.astype(np.float32))[0], rtol=1e-12)
+            # the fused g2 averages the FP64 values before they are rounded for the FP32 store
+            np.testing.assert_allclose(g2[i], gref, rtol=1e-12)
 
 
 def test_raw_g2_only_matches_with_c(ctx):
@@ -140,3 +140,25 @@ def test_g2_from_two_time(ctx, dtype):
     gref, nref = O.g2_from_two_time(Cref.astype(npdt))
     np.testing.assert_array_equal(to_np(npairs), nref)
     np.testing.assert_allclose(to_np(g2), gref, rtol=1e-12, equal_nan=True)
+
+
+def test_raw_wide_accumulation_path(ctx):
+    """An ROI with more pixels than one int32 chunk holds at count 127 (133,120)
+    goes through the int64-between-chunks kernel; the Gram must stay exact."""
+    import torch
+    from paper_2407_20356_amd import api
+    rng = np.random.default_rng(17)
+    M, N = 140_000, 40
+    F = rng.poisson(0.3, size=(N, M)).astype(np.uint8)
+    F[3, 1000] = 127                      # the largest count sets the chunk length
+    F[5, 99_000] = 127
+    labels = np.zeros(M, dtype=np.int32)
+    labels[:500] = 1                      # a small second ROI on the narrow path
+    say("raw wide path: 140k-pixel ROI with counts up to 127")
+    C, g2, npairs, gram = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 2,
+                                                     c_dtype=torch.float64, want_gram=True)
+    ctx.sync()
+    gram, C = to_np(gram), to_np(C)
+    for r in range(2):
+        np.testing.assert_array_equal(gram[r], O.raw_gram(F, labels, r))
+        np.testing.assert_allclose(C[r], O.raw_two_time(F, labels, r), rtol=1e-15, atol=0, equal_nan=True)
