@@ -195,7 +195,7 @@ def main():
         # bytes each launch must move: the frames it reads / the matrix it writes
         "proj_frames": (x_bytes, "hbm"),
         "proj_pixels": (x_bytes, "hbm"),
-        "lowrank_tiles": (n_roi * N * N * 4 + 4 * n_roi * N * kp * 2, "hbm"),
+        "lowrank_tiles": (n_roi * N * N * 4 + 2 * n_roi * N * kp * 2, "hbm"),
     }
     kernels = {}
     for name, (bytes_per_launch, bound) in algo.items():

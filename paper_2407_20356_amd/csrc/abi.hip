@@ -253,13 +253,13 @@ xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi
     const int nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
     const int kp = (int)up(f->k, 32);
     const size_t b_op = (size_t)nr * nw * kp * 2;
-    size_t need = 4 * (align_up(b_op, 256) + 256) + align_up((size_t)nr * nw, 256) + 256;
+    const size_t b_l = (size_t)nr * f->k * f->k * sizeof(double);
+    size_t need = 2 * (align_up(b_op, 256) + 256) + align_up(b_l, 256) + 256 + align_up((size_t)nr * nw, 256) + 256;
     if (g2) need += align_up(g2_part_bytes(nw, nr), 256) + align_up(g2_cnt_bytes(nw, nr), 256) + 512;
     if ((st = ws_reserve(ctx, need))) return st;
-    auto *a_hi = static_cast<unsigned short *>(ws_take(ctx, b_op));
-    auto *a_lo = static_cast<unsigned short *>(ws_take(ctx, b_op));
-    auto *w_hi = static_cast<unsigned short *>(ws_take(ctx, b_op));
-    auto *w_lo = static_cast<unsigned short *>(ws_take(ctx, b_op));
+    auto *z_hi = static_cast<unsigned short *>(ws_take(ctx, b_op));
+    auto *z_lo = static_cast<unsigned short *>(ws_take(ctx, b_op));
+    auto *Lr = static_cast<double *>(ws_take(ctx, b_l));
     auto *valid = static_cast<unsigned char *>(ws_take(ctx, (size_t)nr * nw));
     TileOut o;
     o.C = C;
@@ -270,8 +270,10 @@ xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi
         o.g2_part = static_cast<double *>(ws_take(ctx, g2_part_bytes(nw, nr)));
         o.g2_cnt = static_cast<int *>(ws_take(ctx, g2_cnt_bytes(nw, nr)));
     }
-    if ((st = launch_lowrank_prep(ctx, f, r0, nr, t0, nw, kp, a_hi, a_lo, w_hi, w_lo, valid))) return st;
-    if ((st = launch_lowrank_tiles(ctx, a_hi, a_lo, w_hi, w_lo, kp, valid, nw, nr, o))) return st;
+    // G_R = L_R L_R^T for the ROIs of this call, then Z and the tiles
+    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * f->k * f->k, f->k, nr, Lr))) return st;
+    if ((st = launch_lowrank_prep(ctx, f, Lr, r0, nr, t0, nw, kp, z_hi, z_lo, valid))) return st;
+    if ((st = launch_lowrank_tiles(ctx, z_hi, z_lo, kp, valid, nw, nr, o))) return st;
     if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, nw, nr, g2, npairs))) return st;
     return XPCS_OK;
 }

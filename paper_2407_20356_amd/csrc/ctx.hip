@@ -148,7 +148,8 @@ xpcs_status xpcs_create(int device, size_t hbm_budget_bytes, xpcs_ctx **out) {
         return XPCS_ENOMEM;
     }
     if (hipMemset(ctx->flags, 0, kNumFlags * sizeof(int)) != hipSuccess) {
-        hipFree(p);
+        (void)hipFree(ctx->tr_buf);
+        (void)hipFree(p);
         delete ctx;
         return XPCS_EDEVICE;
     }

@@ -161,12 +161,10 @@ xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx,
                                   const int64_t *off, const int64_t *roi_npix, const int64_t *S,
                                   int64_t nw, int r0, int nr, const int *amax, int64_t max_roi_pixels,
                                   const TileOut &out);
-// Low-rank tiles C = A' W'^T for ROIs [0, nr) from split-bf16 operands laid out
+// Low-rank tiles C = Z Z^T for ROIs [0, nr) from split-bf16 rows laid out
 // [r][t][kp] (hi and lo), with the frame validity mask valid[r*nw + t].
-xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *a_hi,
-                                 const unsigned short *a_lo, const unsigned short *w_hi,
-                                 const unsigned short *w_lo, int kp, const unsigned char *valid,
-                                 int64_t nw, int nr, const TileOut &out);
+xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *z_hi, const unsigned short *z_lo, int kp,
+                                 const unsigned char *valid, int64_t nw, int nr, const TileOut &out);
 // Partial diagonal sums of an existing matrix (upper triangle only).
 xpcs_status launch_matrix_diag_tiles(xpcs_ctx *ctx, const void *C, int c_dtype, int64_t n,
                                      int64_t ldc, double *g2_part, int *g2_cnt);
@@ -215,6 +213,9 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
 // upper triangular, column-major n x n.  Optionally Rinv <- Rprev * Rinv.
 xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol,
                            const double *Rprev, double *Rinv);
+// Cholesky factors of nb symmetric PSD n x n matrices (row-major lower L, dropped
+// pivots give zero columns): G[b] ~= L[b] L[b]^T.
+xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L);
 // out[:, j] = sum_i A[:, i] T[i][j] (A column-major rows x n, fp32 or fp64; T
 // column-major n x m fp64, optionally scaled per output column by colscale[j]).
 // Writes any of: fp32 out32 (stride ld32), fp64 out64 (stride ld64), bf16 hi/lo
@@ -249,10 +250,11 @@ xpcs_status launch_basis_to_bf16(xpcs_ctx *ctx, const float *U, int64_t M, int k
 xpcs_status launch_identity(xpcs_ctx *ctx, double *T, int n);
 
 // ---------------------------------------------------------------- compressed TTC prep (lowrank.hip)
-// Per ROI r and frame t of the window: w = V[t, :] * sigma / S_r[t];
-// W'[r][t] = w, A'[r][t] = |R| * w G_R; both split to bf16 hi/lo rows of kp.
-xpcs_status launch_lowrank_prep(xpcs_ctx *ctx, const xpcs_factors *f, int r0, int nr, int64_t t0,
-                                int64_t nw, int kp, unsigned short *a_hi, unsigned short *a_lo,
-                                unsigned short *w_hi, unsigned short *w_lo, unsigned char *valid);
+// Per ROI r (Lr = Cholesky factor of G_R, row-major lower, nr x k x k) and frame t of
+// the window: z = sqrt(|R|) * (V[t, :] * sigma / S_r[t]) Lr, split to bf16 hi/lo rows
+// of kp (zero padded); valid[r][t] = S_r[t] > 0.  Then C~_R = Z Z^T.
+xpcs_status launch_lowrank_prep(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nr,
+                                int64_t t0, int64_t nw, int kp, unsigned short *z_hi, unsigned short *z_lo,
+                                unsigned char *valid);
 
 }  // namespace xpcs

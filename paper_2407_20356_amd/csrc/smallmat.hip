@@ -226,6 +226,47 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict_
     }
 }
 
+// Batched Cholesky factor: one block per matrix G[bch] (n x n, symmetric PSD),
+// L[bch] row-major lower triangular (upper part zero), pivots below
+// rel_tol * max(diag) dropped (their column of L is zero).
+__global__ __launch_bounds__(1024) void chol_batched_kernel(const double *__restrict__ Gb, int n, double rel_tol,
+                                                            double *__restrict__ Lb) {
+    __shared__ double L[kPacked];
+    __shared__ double s_piv, s_max;
+    const double *G = Gb + (int64_t)blockIdx.x * n * n;
+    double *Lo = Lb + (int64_t)blockIdx.x * n * n;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    for (int i = ty; i < n; i += 32)
+        for (int j = tx; j <= i; j += 32) L[pidx_lower(i, j)] = 0.5 * (G[(int64_t)i * n + j] + G[(int64_t)j * n + i]);
+    if (tid == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, G[(int64_t)i * n + i]);
+        s_max = m;
+    }
+    __syncthreads();
+    const double thresh = rel_tol * s_max;
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double d = L[pidx_lower(j, j)];
+            s_piv = (d > thresh && d > 0.0) ? sqrt(d) : 0.0;
+        }
+        __syncthreads();
+        const double piv = s_piv;
+        const double rp = piv > 0.0 ? 1.0 / piv : 0.0;
+        for (int i = j + 1 + tid; i < n; i += blockDim.x) L[pidx_lower(i, j)] *= rp;
+        if (tid == 0) L[pidx_lower(j, j)] = piv;
+        __syncthreads();
+        for (int r = j + 1 + ty; r < n; r += 32) {
+            const double lrj = L[pidx_lower(r, j)];
+            if (lrj == 0.0) continue;
+            for (int c = j + 1 + tx; c <= r; c += 32) L[pidx_lower(r, c)] -= lrj * L[pidx_lower(c, j)];
+        }
+        __syncthreads();
+    }
+    for (int i = ty; i < n; i += 32)
+        for (int j = tx; j < n; j += 32) Lo[(int64_t)i * n + j] = j <= i ? L[pidx_lower(i, j)] : 0.0;
+}
+
 // C = A B for small column-major n x n matrices (one block).
 __global__ __launch_bounds__(256) void small_matmul_kernel(const double *__restrict__ A, const double *__restrict__ B,
                                                            int n, double *__restrict__ C) {
@@ -684,6 +725,14 @@ xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol
         hipLaunchKernelGGL(small_matmul_kernel, dim3(1), dim3(256), 0, ctx->stream, Rprev, dst, n, Rinv);
         XPCS_LAUNCH_CHECK(ctx, "small_matmul");
     }
+    return XPCS_OK;
+}
+
+xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L) {
+    Phase phase_(ctx, "chol_batched");
+    if (n > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "Cholesky larger than 192");
+    hipLaunchKernelGGL(chol_batched_kernel, dim3(nb), dim3(1024), 0, ctx->stream, G, n, 1e-13, L);
+    XPCS_LAUNCH_CHECK(ctx, "chol_batched");
     return XPCS_OK;
 }
 

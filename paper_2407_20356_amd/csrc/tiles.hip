@@ -253,20 +253,32 @@ __device__ __forceinline__ void raw_gram_tile(
 
     double dsum = 0.0;
     int dcnt = 0;
+    // ROI sums of this lane's 16 rows and 4 columns, read once
+    double srow[16], scol[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + 64 * wr + 16 * a + 4 * lg + e;
+            srow[4 * a + e] = i < nw ? (double)Sr[i] : 0.0;
+        }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t j = j0 + 64 * wc + 16 * b + lr;
+        scol[b] = j < nw ? (double)Sr[j] : 0.0;
+    }
     for (int h = 0; h < 2; ++h) {
         if (wr == h) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int c = 64 * wc + 16 * b + lr;
-                const int64_t j = j0 + c;
-                const double sj = j < nw ? (double)Sr[j] : 0.0;
+                const double sj = scol[b];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int rl = 16 * a + 4 * lg + e;
-                        const int64_t i = i0 + kHalf * h + rl;
-                        const double si = i < nw ? (double)Sr[i] : 0.0;
+                        const double si = srow[4 * a + e];
                         double v;
                         if (si > 0.0 && sj > 0.0)
                             v = (npix * (double)gval(a, b, e)) / (si * sj);
@@ -324,15 +336,27 @@ __global__ __launch_bounds__(256, 2) void raw_gram_wide_kernel(
 }
 
 // ---------------------------------------------------------------- low-rank tiles (split-bf16 MFMA)
-// C~[i][j] = A'[i] . W'[j] with A' = |R| W G_R / S and W' = W / S, each carried as
-// bf16 hi + lo; the three products hi.hi + hi.lo + lo.hi are accumulated in FP32.
+// C~[i][j] = Z[i] . Z[j] with Z = sqrt(|R|) (W / S) L_R carried as bf16 hi + lo; the
+// three products hi.hi + hi.lo + lo.hi are accumulated in FP32.  The tile's Z rows
+// (128 of the row block, 128 of the column block; 128 in all on the diagonal) are
+// staged in LDS one 32-wide K chunk at a time, the next chunk being fetched into
+// registers while the current one runs on the MFMAs; the epilogue's staging
+// buffer then reuses the same LDS.
+constexpr int kZp = 40;                                  // LDS row pitch in u16 (32 + 8)
+constexpr int kZUnits = 2 * 2 * kTile * 4;               // 16-byte units per chunk: arrays x rows x 4
+constexpr int kZPer = kZUnits / 256;
+constexpr int kZBytes = 2 * 2 * kTile * kZp * 2;         // 40 KB
+constexpr int kStageBytes = kHalf * kPitch * 4;
+constexpr int kLowrankLds = kZBytes > kStageBytes ? kZBytes : kStageBytes;
+
 template <typename OutT>
 __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
-    const unsigned short *__restrict__ a_hi, const unsigned short *__restrict__ a_lo,
-    const unsigned short *__restrict__ w_hi, const unsigned short *__restrict__ w_lo, int kp,
-    const unsigned char *__restrict__ valid, int64_t nw, int nb, OutT *C, int64_t ldc,
-    int64_t c_roi_stride, bool vec, double *g2_part, int *g2_cnt) {
-    __shared__ float stage[kHalf * kPitch];
+    const unsigned short *__restrict__ z_hi, const unsigned short *__restrict__ z_lo, int kp,
+    const unsigned char *__restrict__ valid, int64_t nw, int nb, OutT *C, int64_t ldc, int64_t c_roi_stride,
+    bool vec, double *g2_part, int *g2_cnt) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kLowrankLds];
+    unsigned short *zs = reinterpret_cast<unsigned short *>(smem);   // [array][row 0..255][kZp]
+    float *stage = reinterpret_cast<float *>(smem);
     const int slot = blockIdx.y;
     int bi, bj;
     tile_coords(blockIdx.x, nb, bi, bj);
@@ -342,6 +366,32 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
     const int lr = lane & 15, lg = lane >> 4;
     const bool skip = diag && wr > wc;
     const int64_t base = (int64_t)slot * nw * kp;
+    const int jrow0 = diag ? 0 : kTile;                  // LDS rows of the column block
+
+    // chunk loader: unit u -> array (u >> 10), LDS row ((u >> 2) & 255), 16-byte part (u & 3)
+    i32x4 nxt[kZPer];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < kZPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            const int arr = u >> 10, row = (u >> 2) & 255, part = u & 3;
+            const int64_t t = row < kTile ? i0 + row : j0 + (row - kTile);
+            i32x4 v = {0, 0, 0, 0};
+            if (t < nw && !(diag && row >= kTile)) {
+                const unsigned short *src = (arr ? z_lo : z_hi) + base + t * kp + k0 + 8 * part;
+                v = *reinterpret_cast<const i32x4 *>(src);
+            }
+            nxt[q] = v;
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int q = 0; q < kZPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            const int arr = u >> 10, row = (u >> 2) & 255, part = u & 3;
+            *reinterpret_cast<i32x4 *>(zs + (arr * 2 * kTile + row) * kZp + 8 * part) = nxt[q];
+        }
+    };
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -349,26 +399,20 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    if (!skip) {
-        int64_t aoff[4], boff[4];
-        bool aok[4], bok[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int64_t ta = i0 + 64 * wr + 16 * b + lr, tb = j0 + 64 * wc + 16 * b + lr;
-            aok[b] = ta < nw;
-            bok[b] = tb < nw;
-            aoff[b] = base + (aok[b] ? ta : 0) * kp + 8 * lg;
-            boff[b] = base + (bok[b] ? tb : 0) * kp + 8 * lg;
-        }
-        const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int k = 0; k < kp; k += 32) {
+    fetch(0);
+    for (int k0 = 0; k0 < kp; k0 += 32) {
+        put();
+        __syncthreads();
+        if (k0 + 32 < kp) fetch(k0 + 32);
+        if (!skip) {
             u16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                ah[b] = aok[b] ? *reinterpret_cast<const u16x8 *>(a_hi + aoff[b] + k) : z;
-                al[b] = aok[b] ? *reinterpret_cast<const u16x8 *>(a_lo + aoff[b] + k) : z;
-                bh[b] = bok[b] ? *reinterpret_cast<const u16x8 *>(w_hi + boff[b] + k) : z;
-                bl[b] = bok[b] ? *reinterpret_cast<const u16x8 *>(w_lo + boff[b] + k) : z;
+                const int ra = 64 * wr + 16 * b + lr, rb = jrow0 + 64 * wc + 16 * b + lr;
+                ah[b] = *reinterpret_cast<const u16x8 *>(zs + ra * kZp + 8 * lg);
+                al[b] = *reinterpret_cast<const u16x8 *>(zs + (2 * kTile + ra) * kZp + 8 * lg);
+                bh[b] = *reinterpret_cast<const u16x8 *>(zs + rb * kZp + 8 * lg);
+                bl[b] = *reinterpret_cast<const u16x8 *>(zs + (2 * kTile + rb) * kZp + 8 * lg);
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -379,6 +423,7 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
                     acc[a][b] = mfma_bf16(ah[a], bh[b], acc[a][b]);
                 }
         }
+        __syncthreads();
     }
 
     const unsigned char *vr = valid + (int64_t)slot * nw;
@@ -396,21 +441,35 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
     }
     __syncthreads();
     const bool any_nan = s_bad != 0;
+    // validity of this lane's 16 rows and 4 columns, read once (all valid in the usual case)
+    unsigned rowok = 0xffffu, colok = 0xfu;
+    if (any_nan) {
+        rowok = colok = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = i0 + 64 * wr + 16 * a + 4 * lg + e;
+                if (i < nw && vr[i]) rowok |= 1u << (4 * a + e);
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t j = j0 + 64 * wc + 16 * b + lr;
+            if (j < nw && vr[j]) colok |= 1u << b;
+        }
+    }
     for (int h = 0; h < 2; ++h) {
         if (wr == h) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int c = 64 * wc + 16 * b + lr;
-                const int64_t j = j0 + c;
-                const bool vj = j < nw && vr[j];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int rl = 16 * a + 4 * lg + e;
-                        const int64_t i = i0 + kHalf * h + rl;
-                        const bool vi = i < nw && vr[i];
-                        stage[rl * kPitch + c] = (vi && vj) ? acc[a][b][e] : __builtin_nanf("");
+                        const bool ok = ((rowok >> (4 * a + e)) & (colok >> b) & 1u) != 0;
+                        stage[rl * kPitch + c] = ok ? acc[a][b][e] : __builtin_nanf("");
                     }
             }
         }
@@ -510,8 +569,7 @@ xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx, 
     return XPCS_OK;
 }
 
-xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *a_hi, const unsigned short *a_lo,
-                                 const unsigned short *w_hi, const unsigned short *w_lo, int kp,
+xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *z_hi, const unsigned short *z_lo, int kp,
                                  const unsigned char *valid, int64_t nw, int nr, const TileOut &o) {
     Phase phase_(ctx, "lowrank_tiles");
     const int nb = (int)((nw + kTile - 1) / kTile);
@@ -522,13 +580,11 @@ xpcs_status launch_lowrank_tiles(xpcs_ctx *ctx, const unsigned short *a_hi, cons
     const bool vec = o.C && o.c_dtype == XPCS_F32 && (o.ldc % 4 == 0) &&
                      ((uintptr_t)o.C % 16 == 0) && (o.c_roi_stride % 4 == 0);
     if (o.C == nullptr || o.c_dtype == XPCS_F32)
-        hipLaunchKernelGGL(lowrank_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, a_hi, a_lo, w_hi,
-                           w_lo, kp, valid, nw, nb, static_cast<float *>(o.C), o.ldc, o.c_roi_stride,
-                           vec, o.g2_part, o.g2_cnt);
+        hipLaunchKernelGGL(lowrank_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, z_hi, z_lo, kp, valid, nw,
+                           nb, static_cast<float *>(o.C), o.ldc, o.c_roi_stride, vec, o.g2_part, o.g2_cnt);
     else
-        hipLaunchKernelGGL(lowrank_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, a_hi, a_lo, w_hi,
-                           w_lo, kp, valid, nw, nb, static_cast<double *>(o.C), o.ldc, o.c_roi_stride,
-                           false, o.g2_part, o.g2_cnt);
+        hipLaunchKernelGGL(lowrank_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, z_hi, z_lo, kp, valid, nw,
+                           nb, static_cast<double *>(o.C), o.ldc, o.c_roi_stride, false, o.g2_part, o.g2_cnt);
     XPCS_LAUNCH_CHECK(ctx, "lowrank_tiles");
     return XPCS_OK;
 }
