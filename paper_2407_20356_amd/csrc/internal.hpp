@@ -172,7 +172,7 @@ xpcs_status launch_matrix_diag_tiles(xpcs_ctx *ctx, const void *C, int c_dtype, 
 xpcs_status launch_g2_reduce(xpcs_ctx *ctx, const double *g2_part, const int *g2_cnt, int64_t nw,
                              int nr, double *g2, int64_t *npairs);
 
-// ---------------------------------------------------------------- projections (project.hip)
+// ---------------------------------------------------------------- projections (proj_pixels.hip, proj_frames*.hip)
 // Rademacher sketch as bf16 rows om[j][t] (row stride ldt >= N padded to 32, zero padded).
 xpcs_status launch_sketch_omega(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell,
                                 int64_t ldt, unsigned short *om);

@@ -1,0 +1,94 @@
+// Frame-space products X^T Q (Sec. 2.1): planning, launch and the fixed-order
+// reduction of the per-chunk partial sums.
+#include "proj_frames.hpp"
+
+namespace xpcs {
+namespace {
+
+__global__ void proj_frames_reduce_kernel(const float *__restrict__ part, int64_t nch, int64_t N, int ncols,
+                                          int L, int n_ind, double *__restrict__ Z, int64_t ldz,
+                                          int64_t *__restrict__ S) {
+    const int64_t total = N * ncols;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = idx / ncols;
+        const int j = (int)(idx % ncols);
+        const bool isq = j < L;
+        const bool isind = S && j >= L && j - L < n_ind;
+        if (!isq && !isind) continue;
+        double s = 0.0;
+        for (int64_t c = 0; c < nch; ++c) s += (double)part[(c * N + t) * ncols + j];
+        if (isq)
+            Z[(int64_t)j * ldz + t] = s;
+        else
+            S[(int64_t)(j - L) * N + t] = (int64_t)__builtin_rint(s);
+    }
+}
+
+}  // namespace
+
+using proj::pf_rb;
+
+FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
+    FrameProj p;
+    const int nib = (n_ind + 15) / 16;
+    p.ncols = L + 16 * nib;
+    const int rb = pf_rb(L / 16, nib, lo);
+    const int64_t fbf = (int64_t)rb * 64;
+    const int64_t nfb = (N + fbf - 1) / fbf;
+    int64_t want = (2048 + nfb - 1) / nfb;                 // blocks ~ 2048
+    if (want < 8) want = 8;
+    int64_t chunk = (M + want - 1) / want;
+    chunk = (chunk + 31) / 32 * 32;
+    if (chunk < 256) chunk = 256;
+    int64_t nch = (M + chunk - 1) / chunk;
+    nch = (nch + 7) / 8 * 8;
+    p.nchunks = nch;
+    p.chunk = chunk;
+    p.frames_per_block = (int)fbf;
+    return p;
+}
+
+xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
+                               const unsigned short *q_hi, const unsigned short *q_lo, int64_t ldq, int L,
+                               const int32_t *labels, int n_ind, const FrameProj &plan, float *part) {
+    Phase phase_(ctx, "proj_frames");
+    if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
+    if (ldq % 32 || ldq < M) return fail(ctx, XPCS_EINVAL, "internal: basis row stride must cover M in steps of 32");
+    const int ncb = L / 16, nib = (n_ind + 15) / 16;
+    if (nib > 4) return fail(ctx, XPCS_EUNSUPPORTED, "more than 64 ROIs in the fused ROI sums");
+    const bool lo = q_lo != nullptr;
+    const int rb = pf_rb(ncb, nib, lo);
+    if (rb * 64 != plan.frames_per_block)
+        return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
+    const int64_t fbf = (int64_t)rb * 64;
+    const int nfb = (int)((N + fbf - 1) / fbf);
+    const int64_t nblocks = (int64_t)nfb * plan.nchunks;
+    if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
+    const size_t esz = dtype == XPCS_U8 ? 1 : 2;
+    const bool vec = (M % 8 == 0) && ((uintptr_t)frames % (8 * esz) == 0) &&
+                     (nib == 0 || (uintptr_t)labels % 16 == 0);
+    const bool ok =
+        dtype == XPCS_U8
+            ? proj::dispatch_pf_u8(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
+                                   plan.chunk, nfb, plan.ncols, part, vec)
+            : proj::dispatch_pf_u16(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
+                                    plan.chunk, nfb, plan.ncols, part, vec);
+    if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
+    XPCS_LAUNCH_CHECK(ctx, "proj_frames");
+    return XPCS_OK;
+}
+
+xpcs_status launch_proj_frames_reduce(xpcs_ctx *ctx, const float *part, const FrameProj &plan, int64_t N,
+                                      int L, int n_ind, double *Z, int64_t ldz, int64_t *S) {
+    Phase phase_(ctx, "proj_frames_reduce");
+    int64_t total = N * plan.ncols;
+    int grid = (int)((total + 255) / 256);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(proj_frames_reduce_kernel, dim3(grid), dim3(256), 0, ctx->stream, part, plan.nchunks, N,
+                       plan.ncols, L, n_ind, Z, ldz, S);
+    XPCS_LAUNCH_CHECK(ctx, "proj_frames_reduce");
+    return XPCS_OK;
+}
+
+}  // namespace xpcs
