@@ -199,6 +199,63 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
 xpcs_status g2_from_two_time(xpcs_ctx *ctx, const void *C, int32_t c_dtype, int64_t n,
                              int64_t ldc, double *g2, int64_t *npairs);
 
+/* ------------------------------------------------------------------ online streams
+ * The paper's online strategy (Sec. 2.2): the encoding basis is fixed beforehand
+ * (e.g. from compress_frames on an earlier measurement or on the first frames of
+ * this one), every new frame is compressed as it arrives (one more row of W,
+ * Eq. 7) and its two-time correlations with the recent frames are computed at
+ * once (Eqs. 9-10 per ROI).  A stream keeps, per ROI, the compressed rows of the
+ * last `window` frames and g2 sums over its whole history.
+ *
+ * For every pushed frame t the stream produces the band row
+ *   band[r][t][tau] = C~_R[t][t - tau],  tau = 0..window-1
+ * (NaN where t - tau < 0 or either frame has no photons in the ROI) and adds
+ * every valid band entry into g2 sums by lag: after frames 0..n-1 have been
+ * pushed, g2[r][tau] = mean of C~_R[t][t - tau] over t < n (Eq. 12 read as the
+ * mean along the diagonals, restricted to lags below the window), npairs[r][tau]
+ * the number of pairs.  With window >= n this equals correlate_two_time's g2 of
+ * the n frames. */
+typedef struct xpcs_stream xpcs_stream;
+
+typedef struct {
+    int64_t M;                  /* pixels per frame */
+    int32_t dtype;              /* XPCS_U8 | XPCS_U16 */
+    int32_t n_roi;              /* 1..64 */
+    int32_t k;                  /* basis columns, 1..192 */
+    int32_t reserved;
+    const int32_t *roi_label;   /* device int32[M] in [-1, n_roi); read at open only */
+    const float *basis;         /* device M x k column-major, orthonormal columns; read at open only */
+    int64_t window;             /* lags kept: 1..65536 */
+    int64_t max_block;          /* most frames per push: 1..4096 */
+} xpcs_stream_desc;
+
+/* Opens a stream on ctx: converts the basis to split bf16, forms G_R = U_R^T U_R
+ * and its Cholesky factor, and allocates the stream's state (compressed rows of
+ * window + max_block frames per ROI, g2 sums), which counts against the
+ * context's HBM budget until xpcs_stream_close.  The stream runs on ctx's
+ * stream; streams of one context run one after the other.
+ * Errors: EINVAL (sizes, NULL), EUNSUPPORTED (k > 192, n_roi > 64), EBUDGET, ENOMEM. */
+xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *desc, xpcs_stream **out);
+
+/* Appends `nframes` frames (device, frame-contiguous, the stream's dtype, M
+ * counts each): encodes them (W rows and exact ROI sums), writes their band rows
+ * into `band` when it is not NULL (device, n_roi x nframes x window elements of
+ * c_dtype, ROI-major, row stride `window`), and adds them to the g2 sums.
+ * Asynchronous on ctx's stream.  Errors: EINVAL (NULL frames, nframes outside
+ * 1..max_block, c_dtype not XPCS_F32), EBUDGET, ENOMEM. */
+xpcs_status xpcs_stream_push(xpcs_stream *s, const void *frames, int64_t nframes, void *band,
+                             int32_t c_dtype);
+
+/* Snapshot of the g2 sums: g2[r*window + tau] (device double, NaN where npairs is
+ * 0) and npairs[r*window + tau] (device int64); either may be NULL. */
+xpcs_status xpcs_stream_g2(xpcs_stream *s, double *g2, int64_t *npairs);
+
+/* Frames pushed so far (host value). */
+int64_t xpcs_stream_frames(const xpcs_stream *s);
+
+/* Releases the stream's device memory (after the work in flight). NULL is ignored. */
+void xpcs_stream_close(xpcs_stream *s);
+
 #ifdef __cplusplus
 }
 #endif

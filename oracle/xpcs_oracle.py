@@ -31,6 +31,9 @@ What is computed, and where it comes from:
   C~_R = |R| * W G_R W^T / (S_R S_R^T) with G_R = U_R^T U_R.
 * g2 (Sec. 3.1, Eq. 12), read as the average of C along its diagonals
   t2 - t1 = tau over the valid frame pairs.
+* Online stream (Sec. 2.2, online strategy): a fixed basis, frames compressed
+  on arrival; each frame's correlations with the earlier frames by lag (band
+  rows) and g2 by lag over the whole history.
 * Relaxation fit (Sec. 3.1, Eq. 13): g2(tau) = B + beta * exp(-2 Gamma tau).
 """
 
@@ -307,6 +310,47 @@ def g2_fft_from_factors(W: np.ndarray, G_R: np.ndarray, S: np.ndarray,
     g2 = np.full(n, np.nan)
     nz = npairs > 0
     g2[nz] = xc[nz] / npairs[nz]
+    return g2, npairs
+
+
+# ----------------------------------------------------------------------------
+# Online stream (Sec. 2.2, online strategy; Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+
+def stream_band(F: np.ndarray, U: np.ndarray, labels: np.ndarray, n_roi: int, window: int) -> np.ndarray:
+    """Band rows of an online stream fed with the frames of F in order, basis U fixed.
+
+    With the encoding basis chosen before the series (Sec. 2.2), every new frame is
+    compressed on arrival and correlated with the frames before it.  For ROI r,
+    frame t and lag tau < window:  band[r, t, tau] = C~_R[t, t - tau]  (Eqs. 9-10
+    per ROI, from compressed_two_time_from_factors), NaN where t - tau < 0 or where
+    either frame has no photons in the ROI.  How the frames are grouped into
+    pushes does not enter: every entry is a function of the two frames only.
+    """
+    F = np.asarray(F)
+    N = F.shape[0]
+    W = encode(F, U)
+    S = roi_frame_sums(F, labels, n_roi)
+    npix = roi_pixel_counts(labels, n_roi)
+    band = np.full((n_roi, N, window), np.nan)
+    for r in range(n_roi):
+        C = compressed_two_time_from_factors(W, roi_basis_gram(U, labels, r), S[r], int(npix[r]))
+        for tau in range(min(window, N)):
+            band[r, tau:, tau] = np.diagonal(C, offset=-tau)     # C[t, t - tau] for t >= tau
+    return band
+
+
+def stream_g2(band: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """g2 of a stream by lag over its whole history (Eq. 12 as the mean along C's
+    diagonals): g2[r, tau] = mean over t of the valid band[r, t, tau], with the
+    number of those pairs.  g2 is NaN where a lag has no pair."""
+    band = np.asarray(band, dtype=np.float64)
+    ok = ~np.isnan(band)
+    npairs = ok.sum(axis=1).astype(np.int64)
+    sums = np.where(ok, band, 0.0).sum(axis=1)
+    g2 = np.full(sums.shape, np.nan)
+    g2[npairs > 0] = sums[npairs > 0] / npairs[npairs > 0]
     return g2, npairs
 
 

@@ -47,6 +47,15 @@ class XpcsCompressOpts(ctypes.Structure):
     ]
 
 
+class XpcsStreamDesc(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int64), ("dtype", ctypes.c_int32), ("n_roi", ctypes.c_int32),
+        ("k", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("roi_label", ctypes.c_void_p), ("basis", ctypes.c_void_p),
+        ("window", ctypes.c_int64), ("max_block", ctypes.c_int64),
+    ]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -68,6 +77,11 @@ SIGNATURES = {
     "g2_from_two_time": (_ST, [_P, _P, _I32, _I64, _I64, _P, _P]),
     "xpcs_enable_phase_timing": (_ST, [_P, _I32]),
     "xpcs_phase_times": (_ST, [_P, _I32, _P, _P, _P, ctypes.POINTER(_I32)]),
+    "xpcs_stream_open": (_ST, [_P, ctypes.POINTER(XpcsStreamDesc), ctypes.POINTER(_P)]),
+    "xpcs_stream_push": (_ST, [_P, _P, _I64, _P, _I32]),
+    "xpcs_stream_g2": (_ST, [_P, _P, _P]),
+    "xpcs_stream_frames": (_I64, [_P]),
+    "xpcs_stream_close": (None, [_P]),
 }
 
 _lib = None

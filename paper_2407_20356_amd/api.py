@@ -231,3 +231,65 @@ def g2_from_two_time(ctx: Context, C: torch.Tensor) -> Tuple[torch.Tensor, torch
     ctx.check(ctx.lib.g2_from_two_time(ctx.handle, _ptr(C), _c_code(C.dtype), n, C.stride(0), _ptr(g2),
                                        _ptr(npairs)))
     return g2, npairs
+
+
+class Stream:
+    """An online stream (xpcs_stream_*): fixed basis, frames pushed in blocks.
+
+    basis: (k, M) float32 device tensor with orthonormal rows (the columns of U);
+    roi_label: (M,) int32.  push() returns the band rows
+    band[r, i, tau] = C~_R[t_i, t_i - tau] of the pushed frames (or None with
+    want_band=False); g2() returns the g2 sums by lag over the whole history.
+    """
+
+    def __init__(self, ctx: Context, roi_label: torch.Tensor, n_roi: int, basis: torch.Tensor, window: int,
+                 max_block: int, dtype=torch.uint8):
+        _check_device(roi_label, "roi_label", ctx.device)
+        _check_device(basis, "basis", ctx.device)
+        if roi_label.dtype != torch.int32:
+            raise TypeError("roi_label must be int32")
+        if basis.dtype != torch.float32 or basis.dim() != 2 or basis.shape[1] != roi_label.shape[0]:
+            raise ValueError("basis must be a (k, M) float32 tensor")
+        self.ctx, self.n_roi, self.window = ctx, n_roi, window
+        self.M, self.k = roi_label.shape[0], basis.shape[0]
+        self.dtype_code = L.XPCS_U8 if dtype == torch.uint8 else L.XPCS_U16
+        d = L.XpcsStreamDesc(self.M, self.dtype_code, n_roi, self.k, 0, roi_label.data_ptr(), basis.data_ptr(),
+                             window, max_block)
+        h = ctypes.c_void_p()
+        ctx.bind_stream()
+        ctx.check(ctx.lib.xpcs_stream_open(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    def push(self, frames: torch.Tensor, want_band: bool = True, band: Optional[torch.Tensor] = None):
+        _check_device(frames, "frames", self.ctx.device)
+        if _frame_dtype(frames) != self.dtype_code:
+            raise TypeError("frames do not have the stream's dtype")
+        nb = frames.shape[0]
+        if band is None and want_band and nb > 0:
+            band = torch.empty((self.n_roi, nb, self.window), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.xpcs_stream_push(self.handle, _ptr(frames), nb, _ptr(band),
+                                                     _c_code(band.dtype) if band is not None else L.XPCS_F32))
+        return band
+
+    def g2(self) -> Tuple[torch.Tensor, torch.Tensor]:
+        g2 = torch.empty((self.n_roi, self.window), dtype=torch.float64, device=self.ctx.device)
+        npairs = torch.empty((self.n_roi, self.window), dtype=torch.int64, device=self.ctx.device)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.xpcs_stream_g2(self.handle, _ptr(g2), _ptr(npairs)))
+        return g2, npairs
+
+    @property
+    def frames(self) -> int:
+        return int(self.ctx.lib.xpcs_stream_frames(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.xpcs_stream_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,7 +23,7 @@ xpcs_status ws_reserve(xpcs_ctx *ctx, size_t total) {
     total = align_up(total, 256) + 256;
     if (ctx->ws.used + total <= ctx->ws.capacity) return XPCS_OK;
     size_t want = ctx->ws.used + total;
-    if (ctx->budget && want + ctx->scratch.capacity > ctx->budget)
+    if (ctx->budget && want + ctx->scratch.capacity + ctx->persistent > ctx->budget)
         return fail(ctx, XPCS_EBUDGET,
                     "workspace of " + std::to_string(want) + " bytes exceeds the HBM budget of " +
                         std::to_string(ctx->budget));
@@ -39,7 +39,7 @@ xpcs_status ws_reserve(xpcs_ctx *ctx, size_t total) {
         if (e != hipSuccess) return check_hip(ctx, e, "hipFree(workspace)");
     }
     size_t grow = want + want / 4;
-    if (ctx->budget && grow + ctx->scratch.capacity > ctx->budget) grow = want;
+    if (ctx->budget && grow + ctx->scratch.capacity + ctx->persistent > ctx->budget) grow = want;
     void *p = nullptr;
     e = hipMalloc(&p, grow);
     if (e != hipSuccess) return check_hip(ctx, e, "hipMalloc(workspace)");
@@ -52,7 +52,7 @@ void *scratch_get(xpcs_ctx *ctx, size_t bytes, xpcs_status *st) {
     *st = XPCS_OK;
     bytes = align_up(bytes, 256);
     if (bytes <= ctx->scratch.capacity) return ctx->scratch.base;
-    const size_t total = ctx->ws.capacity + bytes;
+    const size_t total = ctx->ws.capacity + ctx->persistent + bytes;
     if (ctx->budget && total > ctx->budget) {
         *st = fail(ctx, XPCS_EBUDGET, "scratch of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
         return nullptr;

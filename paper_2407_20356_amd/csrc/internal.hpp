@@ -72,6 +72,7 @@ struct xpcs_ctx {
     hipStream_t stream = nullptr;
     xpcs::Workspace ws;          // per-call buffers (bump allocated, reset by every entry point)
     xpcs::Workspace scratch;     // launcher-private temporaries, reused launch after launch
+    size_t persistent = 0;       // device bytes held by open streams (counted in the budget)
     int *flags = nullptr;        // device int[kNumFlags]
     std::string last_error;
     void *tr_buf = nullptr;                      // small row-major copy of a tall x small product's T

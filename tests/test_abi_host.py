@@ -18,7 +18,7 @@ HEADER = os.path.join(INCLUDE, "xpcs.h")
 def _declared_functions(path=HEADER):
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:xpcs_status|void|const char \*|size_t|int32_t)\s*\**\s*(\w+)\s*\(",
+    names = re.findall(r"^\s*(?:xpcs_status|void|const char \*|size_t|int32_t|int64_t)\s*\**\s*(\w+)\s*\(",
                        text, flags=re.M)
     return sorted(set(names))
 
@@ -78,6 +78,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(xpcs_compress_opts), offsetof(xpcs_compress_opts, oversample),
          offsetof(xpcs_compress_opts, power_iters), offsetof(xpcs_compress_opts, precision),
          offsetof(xpcs_compress_opts, seed), offsetof(xpcs_compress_opts, basis));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(xpcs_stream_desc), offsetof(xpcs_stream_desc, dtype),
+         offsetof(xpcs_stream_desc, n_roi), offsetof(xpcs_stream_desc, k), offsetof(xpcs_stream_desc, roi_label),
+         offsetof(xpcs_stream_desc, basis), offsetof(xpcs_stream_desc, window), offsetof(xpcs_stream_desc, max_block));
   printf("%d %d %d %d %d %d\n", XPCS_U8, XPCS_U16, XPCS_F32, XPCS_F64, XPCS_ALL_ROIS, XPCS_PREC_BF16);
   return 0;
 }
@@ -95,7 +98,11 @@ int main(void) {
     want_o = [ctypes.sizeof(O), O.oversample.offset, O.power_iters.offset, O.precision.offset, O.seed.offset,
               O.basis.offset]
     assert [int(x) for x in lines[1].split()] == want_o
-    assert [int(x) for x in lines[2].split()] == [_lib.XPCS_U8, _lib.XPCS_U16, _lib.XPCS_F32, _lib.XPCS_F64,
+    D = _lib.XpcsStreamDesc
+    want_d = [ctypes.sizeof(D), D.dtype.offset, D.n_roi.offset, D.k.offset, D.roi_label.offset, D.basis.offset,
+              D.window.offset, D.max_block.offset]
+    assert [int(x) for x in lines[2].split()] == want_d
+    assert [int(x) for x in lines[3].split()] == [_lib.XPCS_U8, _lib.XPCS_U16, _lib.XPCS_F32, _lib.XPCS_F64,
                                                    _lib.XPCS_ALL_ROIS, _lib.XPCS_PREC_BF16]
 
 
@@ -107,6 +114,11 @@ def test_null_context_is_rejected_without_a_gpu(lib):
     assert lib.g2_from_two_time(None, None, 10, 1, 1, None, None) == -1
     assert lib.xpcs_sync(None) == -1
     assert lib.xpcs_last_error(None) == b""
+    assert lib.xpcs_stream_open(None, None, None) == -1
+    assert lib.xpcs_stream_push(None, None, 1, None, 10) == -1
+    assert lib.xpcs_stream_g2(None, None, None) == -1
+    assert lib.xpcs_stream_frames(None) == 0
+    lib.xpcs_stream_close(None)
     lib.xpcs_destroy(None)
 
 

@@ -105,3 +105,34 @@ def test_fft_g2_with_reversed_lag(monkeypatch):
         return g2[::-1].copy(), n
     monkeypatch.setattr(O, "g2_fft_from_factors", wrong)
     _expect_pin_failure(pins.test_g2_fft_matches_diagonal_mean)
+
+
+def test_stream_band_reads_the_wrong_side_of_the_diagonal(monkeypatch):
+    from tests import test_oracle_stream as spins
+
+    def wrong(F, U, labels, n_roi, window):
+        F = np.asarray(F)
+        N = F.shape[0]
+        W = OX.encode(F, U)
+        S = OX.roi_frame_sums(F, labels, n_roi)
+        npix = OX.roi_pixel_counts(labels, n_roi)
+        band = np.full((n_roi, N, window), np.nan)
+        for r in range(n_roi):
+            C = OX.compressed_two_time_from_factors(W, OX.roi_basis_gram(U, labels, r), S[r], int(npix[r]))
+            for tau in range(min(window, N)):
+                band[r, :N - tau, tau] = np.diagonal(C, offset=tau)    # C[t, t + tau]: the future side
+        return band
+    monkeypatch.setattr(O, "stream_band", wrong)
+    _expect_pin_failure(spins.test_band_entries_equal_the_explicit_decompression)
+
+
+def test_stream_g2_divides_by_history_length(monkeypatch):
+    from tests import test_oracle_stream as spins
+
+    def wrong(band):
+        band = np.asarray(band, dtype=np.float64)
+        ok = ~np.isnan(band)
+        npairs = ok.sum(axis=1).astype(np.int64)
+        return np.where(ok, band, 0.0).sum(axis=1) / band.shape[1], npairs
+    monkeypatch.setattr(O, "stream_g2", wrong)
+    _expect_pin_failure(spins.test_full_window_g2_equals_diagonal_mean_of_full_matrix)
