@@ -67,6 +67,48 @@ def cpu_baseline(frames_host, labels, n_roi, k, seed, n_sample):
             "seconds": dt}
 
 
+def stream_latency(api, torch, dev, n_blocks):
+    """Per-push device time of an online stream at the largest serving shape:
+    1024 x 512 px, 36 ROIs, uint8, k = 64, 256-frame blocks, a 4096-frame window
+    (lags), band rows written.  The basis is a fixed orthonormal one (the cost does
+    not depend on it); pushes after the window has filled are the steady state."""
+    import numpy as np
+    import synth
+    H, Wd, n_roi, k, nb, window = 1024, 512, 36, 64, 256, 4096
+    M = H * Wd
+    labels = torch.from_numpy(synth.annular_labels(H, Wd, n_roi)).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(52000)
+    Q, _ = torch.linalg.qr(torch.randn(M, k, device=dev, generator=g, dtype=torch.float32))
+    basis = Q.T.contiguous()
+    pool = [synth.speckle_frames_torch(M, nb, 0.05, 0.2, 50.0, "u8", seed=52001 + i, device=dev) for i in range(4)]
+    ctx = api.Context(0)
+    s = api.Stream(ctx, labels, n_roi, basis, window=window, max_block=nb)
+    band = torch.empty((n_roi, nb, window), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    times = []
+    for i in range(n_blocks):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.push(pool[i % len(pool)], band=band)
+        b.record(stream)
+        times.append((a, b))
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = [a.elapsed_time(b) for a, b in times]
+    steady = ms[window // nb + 1:] or ms
+    g2, npairs = s.g2()
+    torch.cuda.synchronize()
+    ok = bool(torch.isfinite(g2[:, :window - nb]).all().item())
+    s.close()
+    ctx.close()
+    p50 = percentile(steady, 50)
+    return {"workload": "stream_1024x512_36roi_k64_w4096", "block_frames": nb, "pushes": n_blocks,
+            "steady_pushes": len(steady), "push_p50_ms": p50, "push_p99_ms": percentile(steady, 99),
+            "frames_per_s_one_stream": nb / (p50 / 1e3), "band_bytes_per_push": n_roi * nb * window * 4,
+            "frames_pushed": int(n_blocks * nb), "g2_finite": ok}
+
+
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summaries.
 
@@ -108,6 +150,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-frames", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--no-stream", action="store_true", help="skip the online-stream latency measurement")
+    ap.add_argument("--stream-blocks", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -259,6 +303,12 @@ def main():
         raw["gram_int8_TOPs"] = ops / (tot_ms / cnt / 1e3) / 1e12
         raw["gram_frac_of_int8_peak"] = raw["gram_int8_TOPs"] / PEAK_I8_TOPS
 
+    serving = None
+    if not args.no_stream:
+        log("online stream: per-push latency at 1024 x 512 px, 36 ROIs, k = 64, window 4096")
+        serving = stream_latency(api, torch, dev, args.stream_blocks)
+        log(f"online stream: push p50 {serving['push_p50_ms']:.3f} ms, p99 {serving['push_p99_ms']:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the first {args.cpu_sample_frames} frames")
@@ -288,6 +338,7 @@ def main():
         "speedup_vs_raw": (raw["ms_per_step"] / ms_c) if raw else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "stream": serving,
         "kernels": kernels,
         "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
         "parity": parity,
