@@ -141,14 +141,7 @@ xpcs_status xpcs_create(int device, size_t hbm_budget_bytes, xpcs_ctx **out) {
         return XPCS_ENOMEM;
     }
     ctx->flags = static_cast<int *>(p);
-    // small row-major copy of the coefficient matrix of a tall x small product (at most 192 x 192)
-    if (hipMalloc(&ctx->tr_buf, 192 * 192 * sizeof(double)) != hipSuccess) {
-        (void)hipFree(p);
-        delete ctx;
-        return XPCS_ENOMEM;
-    }
     if (hipMemset(ctx->flags, 0, kNumFlags * sizeof(int)) != hipSuccess) {
-        (void)hipFree(ctx->tr_buf);
         (void)hipFree(p);
         delete ctx;
         return XPCS_EDEVICE;
@@ -169,7 +162,6 @@ void xpcs_destroy(xpcs_ctx *ctx) {
     if (ctx->ws.base) (void)hipFree(ctx->ws.base);
     if (ctx->scratch.base) (void)hipFree(ctx->scratch.base);
     if (ctx->flags) (void)hipFree(ctx->flags);
-    if (ctx->tr_buf) (void)hipFree(ctx->tr_buf);
     delete ctx;
 }
 

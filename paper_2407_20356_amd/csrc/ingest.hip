@@ -87,6 +87,108 @@ __global__ __launch_bounds__(1024) void roi_order_kernel(const int32_t *__restri
     }
 }
 
+// Stable ROI order in three short passes over chunks of kOrderChunk pixels:
+// per-chunk ROI counts, their scan into per-chunk starting positions, and the
+// scatter.  One wave walks a chunk in pixel order; the pixels of a 64-pixel
+// step are grouped by label (ballot of the lanes that share the first unplaced
+// label, until none is left), so every ROI's pixels land in increasing pixel
+// order.  Running positions live in LDS and are only touched by the one wave.
+constexpr int kOrderChunk = 4096;
+constexpr int kOrderMaxRoi = 8192;
+
+__device__ __forceinline__ int lane_label(const int32_t *__restrict__ labels, int64_t p, int64_t end, int n_roi) {
+    if (p >= end) return -1;
+    const int r = labels[p];
+    return (r >= 0 && r < n_roi) ? r : -1;
+}
+
+__global__ __launch_bounds__(64) void roi_chunk_count_kernel(const int32_t *__restrict__ labels, int64_t M, int n_roi,
+                                                             int64_t *__restrict__ counts) {
+    extern __shared__ int64_t cnt[];
+    const int lane = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * kOrderChunk;
+    const int64_t end = c0 + kOrderChunk < M ? c0 + kOrderChunk : M;
+    for (int r = lane; r < n_roi; r += 64) cnt[r] = 0;
+    __syncthreads();
+    for (int64_t p0 = c0; p0 < end; p0 += 64) {
+        const int lab = lane_label(labels, p0 + lane, end, n_roi);
+        unsigned long long left = __ballot(lab >= 0);
+        while (left) {
+            const int leader = __ffsll((long long)left) - 1;
+            const int lr = __shfl(lab, leader);
+            const unsigned long long mk = __ballot(lab == lr);
+            if (lane == leader) cnt[lr] += __popcll(mk);
+            left &= ~mk;
+        }
+    }
+    __syncthreads();
+    for (int r = lane; r < n_roi; r += 64) counts[(int64_t)blockIdx.x * n_roi + r] = cnt[r];
+}
+
+// off[r] = start of ROI r (lengths padded to `pad`); counts[c][r] -> starting position
+// of chunk c's pixels of ROI r; the padding slots get perm = -1.
+__global__ __launch_bounds__(256) void roi_chunk_scan_kernel(int n_roi, int64_t nchunks,
+                                                             const int64_t *__restrict__ roi_npix, int pad,
+                                                             int64_t *__restrict__ counts, int64_t *off,
+                                                             int32_t *perm, int32_t *qroi) {
+    for (int r0 = 0; r0 < n_roi; r0 += 256) {
+        // exclusive scan of the padded lengths, 256 ROIs at a time (one thread carries the base)
+        if (threadIdx.x == 0) {
+            int64_t s = r0 == 0 ? 0 : off[r0];
+            for (int r = r0; r < r0 + 256 && r < n_roi; ++r) {
+                off[r] = s;
+                s += (roi_npix[r] + pad - 1) / pad * pad;
+            }
+            off[r0 + 256 < n_roi ? r0 + 256 : n_roi] = s;
+        }
+        __syncthreads();
+        const int r = r0 + threadIdx.x;
+        if (r < n_roi) {
+            int64_t pos = off[r];
+            for (int64_t c = 0; c < nchunks; ++c) {
+                const int64_t n = counts[c * n_roi + r];
+                counts[c * n_roi + r] = pos;
+                pos += n;
+            }
+            const int64_t padded_end = off[r] + (roi_npix[r] + pad - 1) / pad * pad;
+            for (int64_t q = off[r] + roi_npix[r]; q < padded_end; ++q) {
+                perm[q] = -1;
+                qroi[q] = r;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void roi_chunk_scatter_kernel(const int32_t *__restrict__ labels, int64_t M,
+                                                               int n_roi, const int64_t *__restrict__ starts,
+                                                               int32_t *perm, int32_t *qroi) {
+    extern __shared__ int64_t pos[];
+    const int lane = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * kOrderChunk;
+    const int64_t end = c0 + kOrderChunk < M ? c0 + kOrderChunk : M;
+    for (int r = lane; r < n_roi; r += 64) pos[r] = starts[(int64_t)blockIdx.x * n_roi + r];
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int64_t p0 = c0; p0 < end; p0 += 64) {
+        const int lab = lane_label(labels, p0 + lane, end, n_roi);
+        unsigned long long left = __ballot(lab >= 0);
+        while (left) {
+            const int leader = __ffsll((long long)left) - 1;
+            const int lr = __shfl(lab, leader);
+            const unsigned long long mk = __ballot(lab == lr);
+            const int64_t b = pos[lr];
+            if (lab == lr) {
+                const int64_t q = b + __popcll(mk & below);
+                perm[q] = (int32_t)(p0 + lane);
+                qroi[q] = lr;
+            }
+            if (lane == leader) pos[lr] = b + __popcll(mk);
+            left &= ~mk;
+        }
+    }
+}
+
 // Block = (4096 ROI-sorted positions) x (32 frames).  A thread owns 4 consecutive
 // positions (never split between ROIs: ROI starts are multiples of 64), keeps
 // their pixel indices in registers for all 32 frames, and writes one packed
@@ -193,9 +295,26 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
                              int32_t *qroi, int64_t total_cap) {
     Phase phase_(ctx, "roi_order");
     (void)total_cap;
-    hipLaunchKernelGGL(roi_order_kernel, dim3(n_roi), dim3(1024), 0, ctx->stream, labels, M, n_roi,
-                       roi_npix, pad, off, perm, qroi);
-    XPCS_LAUNCH_CHECK(ctx, "roi_order");
+    if (n_roi > kOrderMaxRoi) {
+        hipLaunchKernelGGL(roi_order_kernel, dim3(n_roi), dim3(1024), 0, ctx->stream, labels, M, n_roi,
+                           roi_npix, pad, off, perm, qroi);
+        XPCS_LAUNCH_CHECK(ctx, "roi_order");
+        return XPCS_OK;
+    }
+    const int64_t nchunks = (M + kOrderChunk - 1) / kOrderChunk;
+    xpcs_status st;
+    auto *counts = static_cast<int64_t *>(scratch_get(ctx, (size_t)nchunks * n_roi * sizeof(int64_t), &st));
+    if (!counts) return st;
+    const size_t lds = (size_t)n_roi * sizeof(int64_t);
+    hipLaunchKernelGGL(roi_chunk_count_kernel, dim3((unsigned)nchunks), dim3(64), lds, ctx->stream, labels, M, n_roi,
+                       counts);
+    XPCS_LAUNCH_CHECK(ctx, "roi_chunk_count");
+    hipLaunchKernelGGL(roi_chunk_scan_kernel, dim3(1), dim3(256), 0, ctx->stream, n_roi, nchunks, roi_npix, pad,
+                       counts, off, perm, qroi);
+    XPCS_LAUNCH_CHECK(ctx, "roi_chunk_scan");
+    hipLaunchKernelGGL(roi_chunk_scatter_kernel, dim3((unsigned)nchunks), dim3(64), lds, ctx->stream, labels, M,
+                       n_roi, counts, perm, qroi);
+    XPCS_LAUNCH_CHECK(ctx, "roi_chunk_scatter");
     return XPCS_OK;
 }
 

@@ -75,7 +75,6 @@ struct xpcs_ctx {
     size_t persistent = 0;       // device bytes held by open streams (counted in the budget)
     int *flags = nullptr;        // device int[kNumFlags]
     std::string last_error;
-    void *tr_buf = nullptr;                      // small row-major copy of a tall x small product's T
     bool timing = false;                         // phase timing enabled
     std::vector<xpcs::PhaseRecord> phases;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;          // reusable events

@@ -14,18 +14,31 @@ constexpr int kMaxSmall = 192;                    // largest l handled on chip
 constexpr int kPacked = kMaxSmall * (kMaxSmall + 1) / 2;
 
 // ---------------------------------------------------------------- tall-skinny Gram
-// Partial Grams over row chunks: part[(seg*gridDim.x + blk)][a][b] (upper 4x4 blocks
-// written in full).  A thread owns BPT 4x4 blocks of the upper block triangle.
-constexpr int kGramRows = 32;
+// Partial Grams over row ranges: part[(seg*gridDim.x + blk)][a][b] (upper 4x4 blocks
+// written in full), FP64 throughout (products of fp32 inputs are exact in FP64).
+// A block of 1, 2 or 4 groups of 256 threads walks its rows in chunks, each chunk
+// staged in LDS as doubles (coalesced column reads, the next chunk fetched into
+// registers while the current one is multiplied).  Each group takes an equal
+// share of every chunk; thread j of a group owns 4x4 blocks j, j + 256, ... of the
+// upper block triangle, and the groups' sums are added in a fixed order at the end.
+// Groups per block and rows per chunk by blocks per thread (register budget):
+// BPT 1: 4 groups x 32 rows; BPT 2: 2 x 32; BPT >= 3: 1 x 16.
+template <int BPT>
+struct GramShape {
+    static constexpr int kGroups = BPT == 1 ? 4 : (BPT == 2 ? 2 : 1);
+    static constexpr int kRows = BPT <= 2 ? 32 : 16;
+};
 
 template <typename T, int BPT>
-__global__ __launch_bounds__(256) void tsgram_kernel(const T *__restrict__ A, int64_t rows, int64_t lda, int ncols,
-                                                     const int32_t *__restrict__ row_idx,
-                                                     const int64_t *__restrict__ seg_off, double *part) {
-    __shared__ double tile[kGramRows * (kMaxSmall + 4)];
+__global__ __launch_bounds__(256 * GramShape<BPT>::kGroups) void tsgram_kernel(const T *__restrict__ A, int64_t rows, int64_t lda,
+                                                              int ncols, const int32_t *__restrict__ row_idx,
+                                                              const int64_t *__restrict__ seg_off, double *part) {
+    constexpr int kGramGroups = GramShape<BPT>::kGroups, kGramRows = GramShape<BPT>::kRows;
+    constexpr int kGramThreads = 256 * kGramGroups;
+    extern __shared__ double tile[];                 // [kGramRows][pitch], later the groups' sums
     const int seg = blockIdx.y;
     const int nc4 = (ncols + 3) / 4;
-    const int pitch = nc4 * 4;
+    const int pitch = nc4 * 4 + 2;                   // even (16-byte reads), not a multiple of 32 banks
     const int nblk = nc4 * (nc4 + 1) / 2;
     int64_t r_begin = 0, r_end = rows;
     if (seg_off) {
@@ -36,11 +49,12 @@ __global__ __launch_bounds__(256) void tsgram_kernel(const T *__restrict__ A, in
     const int64_t per = (span + gridDim.x - 1) / gridDim.x;
     const int64_t my0 = r_begin + per * blockIdx.x;
     const int64_t my1 = my0 + per < r_end ? my0 + per : r_end;
+    const int grp = threadIdx.x >> 8, tj = threadIdx.x & 255;
 
     int ab[BPT], bb[BPT];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
-        int b = threadIdx.x + 256 * k;
+        const int b = tj + 256 * k;
         ab[k] = bb[k] = -1;
         if (b < nblk) {
             // linear b -> (x <= y) in the row-major upper block triangle
@@ -61,30 +75,60 @@ __global__ __launch_bounds__(256) void tsgram_kernel(const T *__restrict__ A, in
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[k][i][j] = 0.0;
 
-    for (int64_t r0 = my0; r0 < my1; r0 += kGramRows) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kGramRows * pitch; idx += 256) {
-            const int rr = idx / pitch, c = idx % pitch;
+    // chunk element e = c * kGramRows + rr (consecutive threads: consecutive rows of a column)
+    const int per_thr = (kGramRows * nc4 * 4 + kGramThreads - 1) / kGramThreads;
+    constexpr int kMaxPer = (kGramRows * kMaxSmall + kGramThreads - 1) / kGramThreads;
+    double nxt[kMaxPer];
+    auto fetch = [&](int64_t r0) {
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) {
+            if (q >= per_thr) break;
+            const int e = threadIdx.x + kGramThreads * q;
+            const int c = e / kGramRows, rr = e % kGramRows;
             const int64_t r = r0 + rr;
             double v = 0.0;
-            if (r < my1 && c < ncols) {
-                int64_t src = row_idx ? (int64_t)row_idx[r] : r;
+            if (c < ncols && r < my1) {
+                const int64_t src = row_idx ? (int64_t)row_idx[r] : r;
                 if (src >= 0) v = (double)A[(int64_t)c * lda + src];
             }
-            tile[rr * pitch + c] = v;
+            nxt[q] = v;
         }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int q = 0; q < kMaxPer; ++q) {
+            if (q >= per_thr) break;
+            const int e = threadIdx.x + kGramThreads * q;
+            const int c = e / kGramRows, rr = e % kGramRows;
+            if (c < nc4 * 4) tile[rr * pitch + c] = nxt[q];
+        }
+    };
+    if (my0 < my1) fetch(my0);
+    for (int64_t r0 = my0; r0 < my1; r0 += kGramRows) {
         __syncthreads();
+        put();
+        __syncthreads();
+        if (r0 + kGramRows < my1) fetch(r0 + kGramRows);
+        constexpr int kRowsPerGroup = kGramRows / kGramGroups;
+        const int rbeg = grp * kRowsPerGroup;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             if (ab[k] >= 0) {
-                const int a4 = 4 * ab[k], b4 = 4 * bb[k];
-#pragma unroll 4
-                for (int rr = 0; rr < kGramRows; ++rr) {
-                    double x[4], y[4];
+                const double *xa = tile + 4 * ab[k], *ya = tile + 4 * bb[k];
+                // the next row's operands are read while the current row is multiplied
+                double2 x01 = *reinterpret_cast<const double2 *>(xa + rbeg * pitch);
+                double2 x23 = *reinterpret_cast<const double2 *>(xa + rbeg * pitch + 2);
+                double2 y01 = *reinterpret_cast<const double2 *>(ya + rbeg * pitch);
+                double2 y23 = *reinterpret_cast<const double2 *>(ya + rbeg * pitch + 2);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        x[i] = tile[rr * pitch + a4 + i];
-                        y[i] = tile[rr * pitch + b4 + i];
+                for (int q = 0; q < kRowsPerGroup; ++q) {
+                    const double x[4] = {x01.x, x01.y, x23.x, x23.y}, y[4] = {y01.x, y01.y, y23.x, y23.y};
+                    if (q + 1 < kRowsPerGroup) {
+                        const int o = (rbeg + q + 1) * pitch;
+                        x01 = *reinterpret_cast<const double2 *>(xa + o);
+                        x23 = *reinterpret_cast<const double2 *>(xa + o + 2);
+                        y01 = *reinterpret_cast<const double2 *>(ya + o);
+                        y23 = *reinterpret_cast<const double2 *>(ya + o + 2);
                     }
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
@@ -94,14 +138,41 @@ __global__ __launch_bounds__(256) void tsgram_kernel(const T *__restrict__ A, in
             }
         }
     }
-    double *out = part + ((int64_t)seg * gridDim.x + blockIdx.x) * pitch * pitch;
+    // groups 1..3 hand their sums to group 0 through LDS, one at a time; group 0
+    // adds them in group order and writes the partial
+    for (int g = 1; g < kGramGroups; ++g) {
+        __syncthreads();
+        if (grp == g) {
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-        if (ab[k] >= 0) {
+            for (int k = 0; k < BPT; ++k)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) out[(4 * ab[k] + i) * pitch + 4 * bb[k] + j] = acc[k][i][j];
+                    for (int j = 0; j < 4; ++j)
+                        if (ab[k] >= 0) tile[((k * 256 + tj) * 4 + i) * 4 + j] = acc[k][i][j];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int k = 0; k < BPT; ++k)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ab[k] >= 0) acc[k][i][j] += tile[((k * 256 + tj) * 4 + i) * 4 + j];
+        }
+    }
+    if (grp == 0) {
+        const int pw = nc4 * 4;
+        double *out = part + ((int64_t)seg * gridDim.x + blockIdx.x) * pw * pw;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if (ab[k] >= 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) out[(4 * ab[k] + i) * pw + 4 * bb[k] + j] = acc[k][i][j];
+            }
         }
     }
 }
@@ -279,46 +350,75 @@ __global__ __launch_bounds__(256) void small_matmul_kernel(const double *__restr
 }
 
 // ---------------------------------------------------------------- tall x small product
-// Thread per row, 32 output columns per pass.  T is given row-major (Tr[i*m + j]),
-// so the 32 coefficients of row i are one uniform, contiguous read that every
-// lane shares; the row of A is streamed once per pass.
-constexpr int kTsCols = 32;
+// out = A T (rows x m) with A column-major (rows x n, fp32 or fp64) and T column-major
+// n x m, in FP64.  Grid: (row blocks of 256 * kTsRows, column groups of kTsCols).
+// A thread owns kTsRows rows (strided by 256, so every load and store of a column
+// is contiguous across the wave) and the group's kTsCols columns; the block stages
+// those columns of T in LDS (row-major, read as broadcasts).  The next inner term's
+// operands are loaded while the current one is multiplied.
+constexpr int kTsRows = 2;
+constexpr int kTsCols = 16;
 
 template <typename TA>
 __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda, int n,
-                                                    const double *__restrict__ Tr, int m,
+                                                    const double *__restrict__ T, int m,
                                                     const double *__restrict__ colscale, float *out32,
                                                     int64_t ld32, double *out64, int64_t ld64, unsigned short *hi,
                                                     unsigned short *lo, int64_t ldh, int Lpad, int64_t rows_pad) {
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool live = row < rows;
-    const int64_t rr = live ? row : 0;
-    for (int j0 = 0; j0 < m; j0 += kTsCols) {
-        double acc[kTsCols];
+    __shared__ double Ts[kMaxSmall * kTsCols];        // T[i][j0 + jj] at i * kTsCols + jj
+    const int j0 = blockIdx.y * kTsCols;
+    const int64_t base = (int64_t)blockIdx.x * (256 * kTsRows) + threadIdx.x;
+    int64_t rr[kTsRows];
+    bool live[kTsRows];
 #pragma unroll
-        for (int jj = 0; jj < kTsCols; ++jj) acc[jj] = 0.0;
-        if (j0 + kTsCols <= m) {
-            for (int i = 0; i < n; ++i) {
-                const double ai = (double)A[(int64_t)i * lda + rr];
-                const double *t = Tr + (int64_t)i * m + j0;
+    for (int q = 0; q < kTsRows; ++q) {
+        const int64_t row = base + 256 * q;
+        live[q] = row < rows;
+        rr[q] = live[q] ? row : 0;
+    }
+    if (j0 < m) {
+        for (int idx = threadIdx.x; idx < n * kTsCols; idx += 256) {
+            const int i = idx / kTsCols, jj = idx % kTsCols;
+            Ts[idx] = j0 + jj < m ? T[(int64_t)(j0 + jj) * n + i] : 0.0;
+        }
+    }
+    __syncthreads();
+    if (j0 < m) {
+        double acc[kTsRows][kTsCols];
 #pragma unroll
-                for (int jj = 0; jj < kTsCols; ++jj) acc[jj] = fma(ai, t[jj], acc[jj]);
+        for (int q = 0; q < kTsRows; ++q)
+#pragma unroll
+            for (int jj = 0; jj < kTsCols; ++jj) acc[q][jj] = 0.0;
+        double an[kTsRows];
+#pragma unroll
+        for (int q = 0; q < kTsRows; ++q) an[q] = n > 0 ? (double)A[rr[q]] : 0.0;
+        for (int i = 0; i < n; ++i) {
+            double a[kTsRows];
+#pragma unroll
+            for (int q = 0; q < kTsRows; ++q) a[q] = an[q];
+            if (i + 1 < n) {
+#pragma unroll
+                for (int q = 0; q < kTsRows; ++q) an[q] = (double)A[(int64_t)(i + 1) * lda + rr[q]];
             }
-        } else {
-            for (int i = 0; i < n; ++i) {
-                const double ai = (double)A[(int64_t)i * lda + rr];
-                const double *t = Tr + (int64_t)i * m + j0;
 #pragma unroll
-                for (int jj = 0; jj < kTsCols; ++jj)
-                    if (j0 + jj < m) acc[jj] = fma(ai, t[jj], acc[jj]);
+            for (int jj = 0; jj < kTsCols; jj += 2) {
+                const double2 t = *reinterpret_cast<const double2 *>(&Ts[i * kTsCols + jj]);
+#pragma unroll
+                for (int q = 0; q < kTsRows; ++q) {
+                    acc[q][jj] = fma(a[q], t.x, acc[q][jj]);
+                    acc[q][jj + 1] = fma(a[q], t.y, acc[q][jj + 1]);
+                }
             }
         }
-        if (live) {
+#pragma unroll
+        for (int q = 0; q < kTsRows; ++q) {
+            if (!live[q]) continue;
+            const int64_t row = rr[q];
 #pragma unroll
             for (int jj = 0; jj < kTsCols; ++jj) {
                 const int j = j0 + jj;
                 if (j < m) {
-                    double v = acc[jj];
+                    double v = acc[q][jj];
                     if (colscale) v *= colscale[j];
                     if (out32) out32[(int64_t)j * ld32 + row] = (float)v;
                     if (out64) out64[(int64_t)j * ld64 + row] = v;
@@ -331,20 +431,18 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
             }
         }
     }
-    // zero padding of the bf16 rows: columns [m, Lpad) for live rows, all columns for pad rows
-    if (hi && row < rows_pad) {
-        for (int j = live ? m : 0; j < Lpad; ++j) {
-            hi[(int64_t)j * ldh + row] = 0;
-            if (lo) lo[(int64_t)j * ldh + row] = 0;
+    // zero padding of the bf16 rows (column group 0 only): columns [m, Lpad) of live
+    // rows, all columns of pad rows
+    if (hi && blockIdx.y == 0) {
+#pragma unroll
+        for (int q = 0; q < kTsRows; ++q) {
+            const int64_t row = base + 256 * q;
+            if (row >= rows_pad) continue;
+            for (int j = row < rows ? m : 0; j < Lpad; ++j) {
+                hi[(int64_t)j * ldh + row] = 0;
+                if (lo) lo[(int64_t)j * ldh + row] = 0;
+            }
         }
-    }
-}
-
-// Tr[i*m + j] = T[j*n + i] (column-major n x m to row-major).
-__global__ void transpose_small_kernel(const double *__restrict__ T, int n, int m, double *__restrict__ Tr) {
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * m; idx += gridDim.x * blockDim.x) {
-        const int i = idx / m, j = idx % m;
-        Tr[idx] = T[(int64_t)j * n + i];
     }
 }
 
@@ -352,9 +450,10 @@ __global__ void transpose_small_kernel(const double *__restrict__ T, int n, int 
 // Parallel-order (round-robin) cyclic Jacobi on a symmetric n x n matrix, n even.
 // In step s the n/2 disjoint pairs are (0, x(0)) and (x(a), x(m-a)), a = 1..n/2-1,
 // with m = n-1 and x(i) = 1 + (i + s) mod m; every pair occurs once per sweep.
-// B lives in LDS as the packed upper triangle.  The eigenvectors P = J_1 J_2 ...
-// are accumulated in LDS when they fit (n <= kJacobiPLds); otherwise every
-// step's rotations are logged and replayed row-parallel afterwards.
+// B lives in LDS as the packed upper triangle.  A step computes the n/2 rotations,
+// then updates B on the 2x2 blocks of every pair of pairs (a <= b), spread evenly
+// over the block's threads; the rotations of every step are logged, and the
+// eigenvectors P = J_1 J_2 ... are formed afterwards, one row per wave.
 __device__ __forceinline__ void rr_pair(int s, int a, int n, int &p, int &q) {
     const int m = n - 1;
     int u, v;
@@ -369,41 +468,77 @@ __device__ __forceinline__ void rr_pair(int s, int a, int n, int &p, int &q) {
     q = u < v ? v : u;
 }
 __device__ __forceinline__ int pidx_upper(int i, int j) { return j * (j + 1) / 2 + i; }   // i <= j
+__device__ __forceinline__ int pidx_sym(int i, int j) { return i <= j ? pidx_upper(i, j) : pidx_upper(j, i); }
 
 constexpr int kMaxSweeps = 30;
-constexpr int kJacobiPLds = 112;
+constexpr int kJacobiThreads = 1024;
+constexpr int kMaxItems = (kMaxSmall / 2) * (kMaxSmall / 2 + 1) / 2;
 
-template <bool P_LDS>
-__global__ __launch_bounds__(1024) void jacobi_kernel(const double *__restrict__ Bg, int n, double *__restrict__ lam,
-                                                      double *__restrict__ Pout, double2 *__restrict__ rot_log,
-                                                      int *__restrict__ nsteps_out, int *flags) {
-    constexpr int kPk = P_LDS ? kJacobiPLds * (kJacobiPLds + 1) / 2 : kPacked;
-    __shared__ double B[kPk];
-    __shared__ double P[P_LDS ? kJacobiPLds * kJacobiPLds : 1];
+// Reciprocal and inverse square root refined from the hardware estimates by two
+// Newton steps (quadratic convergence from the estimate's ~2^-22 to full FP64).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// (a, b), a <= b < h, from the row-major linear index of the upper triangle of an h x h grid
+__device__ __forceinline__ void tri_pair(int idx, int h, int &a, int &b) {
+    const float hf = (float)h + 0.5f;
+    int x = (int)(hf - sqrtf(hf * hf - 2.0f * (float)idx));
+    if (x < 0) x = 0;
+    if (x > h - 1) x = h - 1;
+    // start(x) = x*h - x*(x-1)/2: correct the float estimate by at most one row
+    while (x > 0 && x * h - x * (x - 1) / 2 > idx) --x;
+    while ((x + 1) * h - (x + 1) * x / 2 <= idx) ++x;
+    a = x;
+    b = x + (idx - (x * h - x * (x - 1) / 2));
+}
+
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double *__restrict__ Bg, int n,
+                                                                double *__restrict__ lam,
+                                                                double2 *__restrict__ rot_log,
+                                                                int *__restrict__ nsteps_out, int *flags) {
+    __shared__ double B[kPacked];
+    __shared__ unsigned short items[kMaxItems];        // (a, b), a <= b < h, as a | b << 8
     __shared__ double2 rot[kMaxSmall / 2];
     __shared__ int pp[kMaxSmall / 2], qq[kMaxSmall / 2];
-    __shared__ double red_off[16], red_dg[16];
+    __shared__ double red_off[kJacobiThreads / 64], red_dg[kJacobiThreads / 64];
     __shared__ int s_done;
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, h = n / 2, m = n - 1;
-    for (int j = ty; j < n; j += 32)
-        for (int i = tx; i <= j; i += 32) B[pidx_upper(i, j)] = 0.5 * (Bg[(int64_t)i * n + j] + Bg[(int64_t)j * n + i]);
-    if constexpr (P_LDS) {
-        for (int i = ty; i < n; i += 32)
-            for (int j = tx; j < n; j += 32) P[i * n + j] = (i == j) ? 1.0 : 0.0;
+    const int tid = threadIdx.x, h = n / 2, m = n - 1;
+    const int npk = n * (n + 1) / 2, nitems = h * (h + 1) / 2;
+    for (int idx = tid; idx < nitems; idx += kJacobiThreads) {
+        int a, b;
+        tri_pair(idx, h, a, b);
+        items[idx] = (unsigned short)(a | (b << 8));
+    }
+    for (int idx = tid; idx < npk; idx += kJacobiThreads) {
+        int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > idx) --j;
+        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+        const int i = idx - j * (j + 1) / 2;
+        B[idx] = 0.5 * (Bg[(int64_t)i * n + j] + Bg[(int64_t)j * n + i]);
     }
     __syncthreads();
     int nsteps = 0;
     bool converged = false;
     for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
         double off = 0.0, dg = 0.0;
-        for (int j = ty; j < n; j += 32)
-            for (int i = tx; i <= j; i += 32) {
-                const double v = B[pidx_upper(i, j)];
-                if (i == j)
-                    dg += v * v;
-                else
-                    off += v * v;
-            }
+        for (int idx = tid; idx < npk; idx += kJacobiThreads) {
+            int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+            while (j * (j + 1) / 2 > idx) --j;
+            while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+            const double v = B[idx];
+            if (idx - j * (j + 1) / 2 == j)
+                dg += v * v;
+            else
+                off += v * v;
+        }
         for (int o = 32; o > 0; o >>= 1) {
             off += __shfl_xor(off, o);
             dg += __shfl_xor(dg, o);
@@ -415,7 +550,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double *__restrict__
         __syncthreads();
         if (tid == 0) {
             double so = 0.0, sd = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            for (int w = 0; w < kJacobiThreads / 64; ++w) {
                 so += red_off[w];
                 sd += red_dg[w];
             }
@@ -434,116 +569,113 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double *__restrict__
                 pp[tid] = p;
                 qq[tid] = q;
                 const double app = B[pidx_upper(p, p)], aqq = B[pidx_upper(q, q)], apq = B[pidx_upper(p, q)];
+                // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), tau = (aqq - app) / (2 apq), the
+                // smaller rotation angle; c = 1 / sqrt(1 + t^2), s = t c
                 double c = 1.0, sn = 0.0;
-                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
-                    const double tau = (aqq - app) / (2.0 * apq);
+                if (fabs(apq) > 1e-300 && apq * apq > 1e-36 * fabs(app) * fabs(aqq)) {
+                    const double tau = (aqq - app) * rcp_nr(2.0 * apq);
                     double t;
-                    if (fabs(tau) > 1e150)
-                        t = 0.5 / tau;
-                    else
-                        t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
+                    if (fabs(tau) > 1e150) {
+                        t = 0.5 * rcp_nr(tau);
+                    } else {
+                        const double r = 1.0 + tau * tau;
+                        t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + r * rsq_nr(r));
+                    }
+                    c = rsq_nr(1.0 + t * t);
                     sn = t * c;
                 }
                 rot[tid] = make_double2(c, sn);
-                if constexpr (!P_LDS) rot_log[(int64_t)nsteps * h + tid] = make_double2(c, sn);
+                rot_log[(int64_t)nsteps * h + tid] = make_double2(c, sn);
             }
             __syncthreads();
             // B <- J^T B J on the 2x2 blocks of pairs (a <= b)
-            for (int a = ty; a < h; a += 32) {
+            for (int idx = tid; idx < nitems; idx += kJacobiThreads) {
+                const int ab = items[idx], a = ab & 0xff, b = ab >> 8;
                 const int pa = pp[a], qa = qq[a];
                 const double ca = rot[a].x, sa = rot[a].y;
-                for (int b = a + tx; b < h; b += 32) {
-                    if (a == b) {
-                        const int ipp = pidx_upper(pa, pa), iqq = pidx_upper(qa, qa), ipq = pidx_upper(pa, qa);
-                        const double app = B[ipp], aqq = B[iqq], apq = B[ipq];
-                        B[ipp] = ca * ca * app - 2.0 * ca * sa * apq + sa * sa * aqq;
-                        B[iqq] = sa * sa * app + 2.0 * ca * sa * apq + ca * ca * aqq;
-                        B[ipq] = 0.0;
-                    } else {
-                        const int pb = pp[b], qb = qq[b];
-                        const double cb = rot[b].x, sb = rot[b].y;
-                        const int i1 = pa < pb ? pidx_upper(pa, pb) : pidx_upper(pb, pa);
-                        const int i2 = pa < qb ? pidx_upper(pa, qb) : pidx_upper(qb, pa);
-                        const int i3 = qa < pb ? pidx_upper(qa, pb) : pidx_upper(pb, qa);
-                        const int i4 = qa < qb ? pidx_upper(qa, qb) : pidx_upper(qb, qa);
-                        const double x = B[i1], y = B[i2], z = B[i3], w = B[i4];
-                        const double x1 = cb * x - sb * y, y1 = sb * x + cb * y;
-                        const double z1 = cb * z - sb * w, w1 = sb * z + cb * w;
-                        B[i1] = ca * x1 - sa * z1;
-                        B[i3] = sa * x1 + ca * z1;
-                        B[i2] = ca * y1 - sa * w1;
-                        B[i4] = sa * y1 + ca * w1;
-                    }
+                if (a == b) {
+                    const int ipp = pidx_upper(pa, pa), iqq = pidx_upper(qa, qa), ipq = pidx_upper(pa, qa);
+                    const double app = B[ipp], aqq = B[iqq], apq = B[ipq];
+                    B[ipp] = ca * ca * app - 2.0 * ca * sa * apq + sa * sa * aqq;
+                    B[iqq] = sa * sa * app + 2.0 * ca * sa * apq + ca * ca * aqq;
+                    B[ipq] = 0.0;
+                } else {
+                    const int pb = pp[b], qb = qq[b];
+                    const double cb = rot[b].x, sb = rot[b].y;
+                    const int i1 = pidx_sym(pa, pb), i2 = pidx_sym(pa, qb), i3 = pidx_sym(qa, pb), i4 = pidx_sym(qa, qb);
+                    const double x = B[i1], y = B[i2], z = B[i3], w = B[i4];
+                    const double x1 = cb * x - sb * y, y1 = sb * x + cb * y;
+                    const double z1 = cb * z - sb * w, w1 = sb * z + cb * w;
+                    B[i1] = ca * x1 - sa * z1;
+                    B[i3] = sa * x1 + ca * z1;
+                    B[i2] = ca * y1 - sa * w1;
+                    B[i4] = sa * y1 + ca * w1;
                 }
-            }
-            if constexpr (P_LDS) {
-                // P <- P J: rows i, pairs a
-                for (int i = ty; i < n; i += 32)
-                    for (int a = tx; a < h; a += 32) {
-                        const int p = pp[a], q = qq[a];
-                        const double c = rot[a].x, sn = rot[a].y;
-                        const double x = P[i * n + p], y = P[i * n + q];
-                        P[i * n + p] = c * x - sn * y;
-                        P[i * n + q] = sn * x + c * y;
-                    }
             }
             __syncthreads();
             ++nsteps;
         }
     }
-    for (int i = tid; i < n; i += blockDim.x) lam[i] = B[pidx_upper(i, i)];
-    if constexpr (P_LDS) {
-        for (int i = ty; i < n; i += 32)
-            for (int j = tx; j < n; j += 32) Pout[(int64_t)i * n + j] = P[i * n + j];
-    }
+    for (int i = tid; i < n; i += kJacobiThreads) lam[i] = B[pidx_upper(i, i)];
     if (tid == 0) {
         *nsteps_out = nsteps;
         if (!converged) atomicOr(&flags[kFlagNumeric], 1);
     }
 }
 
-// Eigenvectors from the rotation log: row i of P = e_i^T J_1 J_2 ... J_S, 8 rows per
-// block; the rotations of 16 steps are staged in LDS at a time.
-constexpr int kReplayRows = 8;
-constexpr int kReplayBatch = 16;
-__global__ __launch_bounds__(256) void jacobi_replay_kernel(const double2 *__restrict__ rot_log,
-                                                            const int *__restrict__ nsteps_ptr, int n,
-                                                            double *__restrict__ P) {
-    __shared__ double rowv[kReplayRows][kMaxSmall];
-    __shared__ double2 cs[kReplayBatch][kMaxSmall / 2];
+// Eigenvectors from the rotation log: row i of P = e_i^T J_1 J_2 ... J_S.  Rows are
+// independent, so each wave forms one row in its own piece of LDS, lane a applying
+// pair a's rotation of every step in order (a wave's LDS accesses complete in
+// program order, so no barrier is needed between steps); the next step's
+// rotations are loaded while the current one is applied.
+constexpr int kReplayWaves = 4;
+__global__ __launch_bounds__(64 * kReplayWaves) void jacobi_replay_kernel(const double2 *__restrict__ rot_log,
+                                                                          const int *__restrict__ nsteps_ptr, int n,
+                                                                          double *__restrict__ P) {
+    __shared__ double rowv[kReplayWaves][kMaxSmall];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * kReplayWaves + w;
     const int h = n / 2, m = n - 1;
-    const int r0 = blockIdx.x * kReplayRows;
-    for (int idx = threadIdx.x; idx < kReplayRows * n; idx += blockDim.x) {
-        const int rr = idx / n, j = idx % n;
-        rowv[rr][j] = (r0 + rr == j) ? 1.0 : 0.0;
-    }
+    if (row >= n) return;
+    double *rv = rowv[w];
+    for (int j = lane; j < n; j += 64) rv[j] = (j == row) ? 1.0 : 0.0;
     const int nsteps = *nsteps_ptr;
-    for (int st0 = 0; st0 < nsteps; st0 += kReplayBatch) {
-        const int nb = nsteps - st0 < kReplayBatch ? nsteps - st0 : kReplayBatch;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nb * h; idx += blockDim.x)
-            cs[idx / h][idx % h] = rot_log[(int64_t)(st0 + idx / h) * h + idx % h];
-        __syncthreads();
-        for (int b = 0; b < nb; ++b) {
-            const int s = (st0 + b) % m;
-            for (int idx = threadIdx.x; idx < kReplayRows * h; idx += blockDim.x) {
-                const int rr = idx / h, a = idx % h;
-                int p, q;
-                rr_pair(s, a, n, p, q);
-                const double2 c = cs[b][a];
-                const double x = rowv[rr][p], y = rowv[rr][q];
-                rowv[rr][p] = c.x * x - c.y * y;
-                rowv[rr][q] = c.y * x + c.x * y;
-            }
-            __syncthreads();
+    // lane a handles pairs a and a + 64 (h <= 96)
+    double2 c0 = make_double2(1.0, 0.0), c1 = make_double2(1.0, 0.0);
+    if (nsteps > 0) {
+        if (lane < h) c0 = rot_log[lane];
+        if (lane + 64 < h) c1 = rot_log[lane + 64];
+    }
+    for (int st = 0; st < nsteps; ++st) {
+        const double2 r0 = c0, r1 = c1;
+        if (st + 1 < nsteps) {
+            if (lane < h) c0 = rot_log[(int64_t)(st + 1) * h + lane];
+            if (lane + 64 < h) c1 = rot_log[(int64_t)(st + 1) * h + lane + 64];
+        }
+        const int s = st % m;
+        int p, q;
+        double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
+        int p1 = 0, q1 = 0;
+        if (lane < h) {
+            rr_pair(s, lane, n, p, q);
+            x0 = rv[p];
+            y0 = rv[q];
+        }
+        if (lane + 64 < h) {
+            rr_pair(s, lane + 64, n, p1, q1);
+            x1 = rv[p1];
+            y1 = rv[q1];
+        }
+        if (lane < h) {
+            rv[p] = r0.x * x0 - r0.y * y0;
+            rv[q] = r0.y * x0 + r0.x * y0;
+        }
+        if (lane + 64 < h) {
+            rv[p1] = r1.x * x1 - r1.y * y1;
+            rv[q1] = r1.y * x1 + r1.x * y1;
         }
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kReplayRows * n; idx += blockDim.x) {
-        const int rr = idx / n, j = idx % n;
-        if (r0 + rr < n) P[(int64_t)(r0 + rr) * n + j] = rowv[rr][j];
-    }
+    for (int j = lane; j < n; j += 64) P[(int64_t)row * n + j] = rv[j];
 }
 
 // ---------------------------------------------------------------- basis selection
@@ -669,21 +801,27 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     Phase phase_(ctx, "tsgram");
     if (ncols > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "Gram wider than 192 columns");
     const int nc4 = (ncols + 3) / 4;
-    const int pitch = nc4 * 4;
+    const int pw = nc4 * 4;
     const int nblk = nc4 * (nc4 + 1) / 2;
     const int bpt = (nblk + 255) / 256;
+    // about 1024 rows per block, at most 256 blocks; segmented Grams split the blocks
     int nparts = (int)((rows + 1023) / 1024);
     if (nparts > 256) nparts = 256;
     if (seg_off) nparts = (int)(256 / (nseg > 0 ? nseg : 1)) + 1;
     if (nparts < 1) nparts = 1;
-    const size_t pbytes = (size_t)nseg * nparts * pitch * pitch * sizeof(double);
+    const size_t pbytes = (size_t)nseg * nparts * pw * pw * sizeof(double);
     xpcs_status st;
     double *part = static_cast<double *>(scratch_get(ctx, pbytes, &st));
     if (!part) return st;
+    const int grows = bpt <= 2 ? GramShape<1>::kRows : GramShape<3>::kRows;
+    const int gthreads = 256 * (bpt == 1 ? GramShape<1>::kGroups : (bpt == 2 ? GramShape<2>::kGroups : 1));
+    const size_t lds_tile = (size_t)grows * (pw + 2) * sizeof(double);
+    const size_t lds_sums = (size_t)nblk * 16 * sizeof(double);     // one 4x4 block per owned block id
+    const size_t lds = lds_tile > lds_sums ? lds_tile : lds_sums;
     dim3 grid(nparts, nseg);
-#define XPCS_TSG(T, B)                                                                                         \
-    hipLaunchKernelGGL((tsgram_kernel<T, B>), grid, dim3(256), 0, ctx->stream, static_cast<const T *>(A), rows, \
-                       lda, ncols, row_idx, seg_off, part)
+#define XPCS_TSG(T, B)                                                                                          \
+    hipLaunchKernelGGL((tsgram_kernel<T, B>), grid, dim3(gthreads), lds, ctx->stream,                            \
+                       static_cast<const T *>(A), rows, lda, ncols, row_idx, seg_off, part)
 #define XPCS_TSG_T(T)                   \
     switch (bpt) {                      \
         case 1: XPCS_TSG(T, 1); break;  \
@@ -701,7 +839,7 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
 #undef XPCS_TSG
     XPCS_LAUNCH_CHECK(ctx, "tsgram");
     hipLaunchKernelGGL(tsgram_reduce_kernel, dim3((ncols * ncols + 31) / 32, nseg), dim3(256), 0, ctx->stream,
-                       part, nparts, ncols, pitch, G);
+                       part, nparts, ncols, pw, G);
     XPCS_LAUNCH_CHECK(ctx, "tsgram_reduce");
     return XPCS_OK;
 }
@@ -740,18 +878,15 @@ xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows,
                          const double *T, int m, const double *colscale, const TsOut &out) {
     Phase phase_(ctx, "tsmul");
     if (n > kMaxSmall || m > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "tall x small product wider than 192");
-    // T (column-major) -> row-major in the context's small-transpose buffer
-    double *Tr = static_cast<double *>(ctx->tr_buf);
-    hipLaunchKernelGGL(transpose_small_kernel, dim3((n * m + 255) / 256), dim3(256), 0, ctx->stream, T, n, m, Tr);
     const int64_t span = out.hi && out.rows_pad > rows ? out.rows_pad : rows;
-    dim3 grid((unsigned)((span + 255) / 256));
+    dim3 grid((unsigned)((span + 256 * kTsRows - 1) / (256 * kTsRows)), (unsigned)((m + kTsCols - 1) / kTsCols));
     if (a_f64)
         hipLaunchKernelGGL(tsmul_kernel<double>, grid, dim3(256), 0, ctx->stream, static_cast<const double *>(A), rows,
-                           lda, n, Tr, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
+                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
                            out.Lpad, out.rows_pad);
     else
         hipLaunchKernelGGL(tsmul_kernel<float>, grid, dim3(256), 0, ctx->stream, static_cast<const float *>(A), rows,
-                           lda, n, Tr, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
+                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
                            out.Lpad, out.rows_pad);
     XPCS_LAUNCH_CHECK(ctx, "tsmul");
     return XPCS_OK;
@@ -762,17 +897,11 @@ xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, do
     if (n > kMaxSmall || n % 2) return fail(ctx, XPCS_EUNSUPPORTED, "eigen size must be even and <= 192");
     int *nsteps = static_cast<int *>(rot);
     double2 *log = reinterpret_cast<double2 *>(static_cast<char *>(rot) + 256);
-    if (n <= kJacobiPLds) {
-        hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), 0, ctx->stream, B, n, lam, P, log, nsteps,
-                           ctx->flags);
-        XPCS_LAUNCH_CHECK(ctx, "jacobi");
-        return XPCS_OK;
-    }
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, ctx->stream, B, n, lam, P, log, nsteps,
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, ctx->stream, B, n, lam, log, nsteps,
                        ctx->flags);
     XPCS_LAUNCH_CHECK(ctx, "jacobi");
-    hipLaunchKernelGGL(jacobi_replay_kernel, dim3((n + kReplayRows - 1) / kReplayRows), dim3(256), 0, ctx->stream,
-                       log, nsteps, n, P);
+    hipLaunchKernelGGL(jacobi_replay_kernel, dim3((n + kReplayWaves - 1) / kReplayWaves), dim3(64 * kReplayWaves), 0,
+                       ctx->stream, log, nsteps, n, P);
     XPCS_LAUNCH_CHECK(ctx, "jacobi_replay");
     return XPCS_OK;
 }
