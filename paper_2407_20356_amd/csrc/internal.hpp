@@ -182,10 +182,10 @@ xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int
                                const unsigned short *B, int64_t ldb, int L, float *Y);
 // Frame-space partial products P[c][t][j] = sum_{p in chunk c} X[p][t] Q[j][p] for
 // j < L (bf16 hi, optional lo) and, when n_ind > 0, the indicator columns
-// j = L + r (label == r).  Q rows have stride ldq (>= M padded to 32, zero padded).
+// j = L + r (label == r).  Q rows have stride ldq (>= M padded to 64, zero padded).
 struct FrameProj {
     int64_t nchunks = 0;
-    int64_t chunk = 0;      // pixels per chunk (multiple of 32)
+    int64_t chunk = 0;      // pixels per chunk (multiple of 64)
     int ncols = 0;          // L + indicator columns rounded to 16
     int frames_per_block = 0;
 };

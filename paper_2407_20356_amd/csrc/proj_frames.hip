@@ -39,7 +39,7 @@ FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
     int64_t want = (2048 + nfb - 1) / nfb;                 // blocks ~ 2048
     if (want < 8) want = 8;
     int64_t chunk = (M + want - 1) / want;
-    chunk = (chunk + 31) / 32 * 32;
+    chunk = (chunk + 63) / 64 * 64;                        // a multiple of either K step
     if (chunk < 256) chunk = 256;
     int64_t nch = (M + chunk - 1) / chunk;
     nch = (nch + 7) / 8 * 8;
@@ -54,7 +54,8 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
                                const int32_t *labels, int n_ind, const FrameProj &plan, float *part) {
     Phase phase_(ctx, "proj_frames");
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
-    if (ldq % 32 || ldq < M) return fail(ctx, XPCS_EINVAL, "internal: basis row stride must cover M in steps of 32");
+    if (ldq % 64 || ldq < M)
+        return fail(ctx, XPCS_EINVAL, "internal: basis row stride must cover M in steps of 64");
     const int ncb = L / 16, nib = (n_ind + 15) / 16;
     if (nib > 4) return fail(ctx, XPCS_EUNSUPPORTED, "more than 64 ROIs in the fused ROI sums");
     const bool lo = q_lo != nullptr;

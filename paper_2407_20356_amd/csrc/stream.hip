@@ -361,7 +361,7 @@ xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *d, xpcs_stre
     s->window = d->window;
     s->max_block = d->max_block;
     s->cap = d->window + d->max_block;
-    s->ldq = (d->M + 31) / 32 * 32;
+    s->ldq = (d->M + 63) / 64 * 64;                 // basis rows padded to the projection's K step
 
     // one allocation for the stream's state
     size_t off = 0;

@@ -23,15 +23,18 @@ namespace {
 constexpr int kPitch = kTile + 1;   // odd LDS pitch: column reads are conflict-free
 constexpr int kHalf = kTile / 2;
 
-// Tiles of one ROI in diagonal-major order: id = sum_{d<D} (nb - d) + bi with D = bj - bi.
+// Tiles of one ROI in diagonal-major order: id = start(D) + bi with D = bj - bi and
+// start(D) = sum_{d<D} (nb - d) = D nb - D (D - 1) / 2.  D is the root of the
+// quadratic, corrected by whole steps against rounding.
 __device__ __forceinline__ void tile_coords(int64_t id, int nb, int &bi, int &bj) {
-    int D = 0;
-    while (id >= nb - D) {
-        id -= nb - D;
-        ++D;
-    }
-    bi = (int)id;
-    bj = bi + D;
+    const double b = 2.0 * nb + 1.0;
+    int64_t D = (int64_t)((b - sqrt(b * b - 8.0 * (double)id)) * 0.5);
+    if (D < 0) D = 0;
+    if (D > nb - 1) D = nb - 1;
+    while (D > 0 && D * nb - D * (D - 1) / 2 > id) --D;
+    while (D + 1 < nb && (D + 1) * nb - (D + 1) * D / 2 <= id) ++D;
+    bi = (int)(id - (D * nb - D * (D - 1) / 2));
+    bj = bi + (int)D;
 }
 
 template <typename OutT>
@@ -350,7 +353,7 @@ constexpr int kStageBytes = kHalf * kPitch * 4;
 constexpr int kLowrankLds = kZBytes > kStageBytes ? kZBytes : kStageBytes;
 
 template <typename OutT>
-__global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
+__global__ __launch_bounds__(256, 3) void lowrank_tile_kernel(
     const unsigned short *__restrict__ z_hi, const unsigned short *__restrict__ z_lo, int kp,
     const unsigned char *__restrict__ valid, int64_t nw, int nb, OutT *C, int64_t ldc, int64_t c_roi_stride,
     bool vec, double *g2_part, int *g2_cnt) {
@@ -405,23 +408,25 @@ __global__ __launch_bounds__(256, 2) void lowrank_tile_kernel(
         __syncthreads();
         if (k0 + 32 < kp) fetch(k0 + 32);
         if (!skip) {
-            u16x8 ah[4], al[4], bh[4], bl[4];
+            u16x8 bh[4], bl[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int ra = 64 * wr + 16 * b + lr, rb = jrow0 + 64 * wc + 16 * b + lr;
-                ah[b] = *reinterpret_cast<const u16x8 *>(zs + ra * kZp + 8 * lg);
-                al[b] = *reinterpret_cast<const u16x8 *>(zs + (2 * kTile + ra) * kZp + 8 * lg);
+                const int rb = jrow0 + 64 * wc + 16 * b + lr;
                 bh[b] = *reinterpret_cast<const u16x8 *>(zs + rb * kZp + 8 * lg);
                 bl[b] = *reinterpret_cast<const u16x8 *>(zs + (2 * kTile + rb) * kZp + 8 * lg);
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a) {
+                const int ra = 64 * wr + 16 * a + lr;
+                const u16x8 ah = *reinterpret_cast<const u16x8 *>(zs + ra * kZp + 8 * lg);
+                const u16x8 al = *reinterpret_cast<const u16x8 *>(zs + (2 * kTile + ra) * kZp + 8 * lg);
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    acc[a][b] = mfma_bf16(al[a], bh[b], acc[a][b]);
-                    acc[a][b] = mfma_bf16(ah[a], bl[b], acc[a][b]);
-                    acc[a][b] = mfma_bf16(ah[a], bh[b], acc[a][b]);
+                    acc[a][b] = mfma_bf16(al, bh[b], acc[a][b]);
+                    acc[a][b] = mfma_bf16(ah, bl[b], acc[a][b]);
+                    acc[a][b] = mfma_bf16(ah, bh[b], acc[a][b]);
                 }
+            }
         }
         __syncthreads();
     }
