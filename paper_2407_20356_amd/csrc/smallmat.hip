@@ -215,14 +215,42 @@ __device__ __forceinline__ int pidx_lower(int i, int j) { return i * (i + 1) / 2
 constexpr int kInvLds = 128;
 constexpr int kPackedInv = kInvLds * (kInvLds + 1) / 2;
 
+// One barrier per column: every thread reads the pivot d_j itself, and the trailing
+// update uses the column before scaling, L[r][c] -= L[r][j] L[c][j] / d_j; the
+// columns are scaled by 1 / sqrt(d_j) once the factorization is done.  A pivot
+// at or below the threshold leaves its column out (zero).
+__device__ __forceinline__ void chol_packed_lds(double *L, double *piv, int n, double thresh) {
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    for (int j = 0; j < n; ++j) {
+        const double d = L[pidx_lower(j, j)];
+        const bool keep = d > thresh && d > 0.0;
+        if (keep) {
+            const double rd = 1.0 / d;
+            for (int r = j + 1 + ty; r < n; r += 32) {
+                const double lrj = L[pidx_lower(r, j)] * rd;
+                if (lrj == 0.0) continue;
+                for (int c = j + 1 + tx; c <= r; c += 32) L[pidx_lower(r, c)] -= lrj * L[pidx_lower(c, j)];
+            }
+        }
+        if (tid == 0) piv[j] = keep ? sqrt(d) : 0.0;
+        __syncthreads();
+    }
+    // scale: L[r][j] /= piv_j below the diagonal, L[j][j] = piv_j
+    for (int r = ty; r < n; r += 32)
+        for (int c = tx; c <= r; c += 32) {
+            const double pj = piv[c];
+            L[pidx_lower(r, c)] = r == c ? pj : (pj > 0.0 ? L[pidx_lower(r, c)] / pj : 0.0);
+        }
+    __syncthreads();
+}
+
 template <bool LDS_INV>
 __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict__ G, int n, double rel_tol,
                                                        double *__restrict__ Rinv, int *flags) {
     __shared__ double L[LDS_INV ? kPackedInv : kPacked];
     __shared__ double Li[LDS_INV ? kPackedInv : 1];
-    __shared__ double s_piv;
+    __shared__ double piv[kMaxSmall];
     __shared__ double s_max;
-    __shared__ int s_kept;
     const int tid = threadIdx.x;
     const int ty = tid >> 5, tx = tid & 31;
     for (int i = ty; i < n; i += 32)
@@ -231,55 +259,37 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict_
         double m = 0.0;
         for (int i = 0; i < n; ++i) m = fmax(m, G[(int64_t)i * n + i]);
         s_max = m;
-        s_kept = 0;
     }
     __syncthreads();
-    const double thresh = rel_tol * s_max;
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            const double d = L[pidx_lower(j, j)];
-            if (d > thresh && d > 0.0) {
-                s_piv = sqrt(d);
-                ++s_kept;
-            } else {
-                s_piv = 0.0;
-            }
-        }
-        __syncthreads();
-        const double piv = s_piv;
-        const double rp = piv > 0.0 ? 1.0 / piv : 0.0;
-        for (int i = j + 1 + tid; i < n; i += blockDim.x) L[pidx_lower(i, j)] *= rp;
-        if (tid == 0) L[pidx_lower(j, j)] = piv;
-        __syncthreads();
-        for (int r = j + 1 + ty; r < n; r += 32) {
-            const double lrj = L[pidx_lower(r, j)];
-            if (lrj == 0.0) continue;
-            for (int c = j + 1 + tx; c <= r; c += 32) L[pidx_lower(r, c)] -= lrj * L[pidx_lower(c, j)];
-        }
-        __syncthreads();
+    chol_packed_lds(L, piv, n, rel_tol * s_max);
+    if (tid == 0) {
+        bool any = false;
+        for (int j = 0; j < n; ++j) any |= piv[j] > 0.0;
+        if (!any) atomicOr(&flags[kFlagNumeric], 1);
     }
-    if (tid == 0 && s_kept == 0) atomicOr(&flags[kFlagNumeric], 1);
     if constexpr (LDS_INV) {
-        // L^{-1} by right-looking elimination on [L | I]: row j is final once scaled,
-        // then removed from the rows below it.
+        // L^{-1} by right-looking elimination on [L | I], one barrier per column: row j
+        // is read scaled on the fly (by 1 / L[j][j]) while it updates the rows below,
+        // and scaled in place at the end.
         for (int i = ty; i < n; i += 32)
             for (int c = tx; c <= i; c += 32) Li[pidx_lower(i, c)] = (i == c) ? 1.0 : 0.0;
         __syncthreads();
         for (int j = 0; j < n; ++j) {
             const double ljj = L[pidx_lower(j, j)];
             const double rj = ljj != 0.0 ? 1.0 / ljj : 0.0;
-            for (int c = tid; c <= j; c += blockDim.x) Li[pidx_lower(j, c)] *= rj;
-            __syncthreads();
             for (int i = j + 1 + ty; i < n; i += 32) {
-                const double lij = L[pidx_lower(i, j)];
+                const double lij = L[pidx_lower(i, j)] * rj;
                 if (lij == 0.0) continue;
                 for (int c = tx; c <= j; c += 32) Li[pidx_lower(i, c)] -= lij * Li[pidx_lower(j, c)];
             }
             __syncthreads();
         }
-        // Rinv (column-major) = Linv^T: Rinv[c][i] = Linv[i][c] at i*n + c
-        for (int i = ty; i < n; i += 32)
-            for (int c = tx; c < n; c += 32) Rinv[(int64_t)i * n + c] = c <= i ? Li[pidx_lower(i, c)] : 0.0;
+        // Rinv (column-major) = Linv^T: Rinv[c][i] = Linv[i][c] at i*n + c, rows scaled
+        for (int i = ty; i < n; i += 32) {
+            const double lii = L[pidx_lower(i, i)];
+            const double ri = lii != 0.0 ? 1.0 / lii : 0.0;
+            for (int c = tx; c < n; c += 32) Rinv[(int64_t)i * n + c] = c <= i ? Li[pidx_lower(i, c)] * ri : 0.0;
+        }
     } else {
         for (int c = tid; c < n; c += blockDim.x) {
             for (int i = 0; i < c; ++i) Rinv[(int64_t)i * n + c] = 0.0;
@@ -303,7 +313,8 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict_
 __global__ __launch_bounds__(1024) void chol_batched_kernel(const double *__restrict__ Gb, int n, double rel_tol,
                                                             double *__restrict__ Lb) {
     __shared__ double L[kPacked];
-    __shared__ double s_piv, s_max;
+    __shared__ double piv[kMaxSmall];
+    __shared__ double s_max;
     const double *G = Gb + (int64_t)blockIdx.x * n * n;
     double *Lo = Lb + (int64_t)blockIdx.x * n * n;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
@@ -315,25 +326,7 @@ __global__ __launch_bounds__(1024) void chol_batched_kernel(const double *__rest
         s_max = m;
     }
     __syncthreads();
-    const double thresh = rel_tol * s_max;
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            const double d = L[pidx_lower(j, j)];
-            s_piv = (d > thresh && d > 0.0) ? sqrt(d) : 0.0;
-        }
-        __syncthreads();
-        const double piv = s_piv;
-        const double rp = piv > 0.0 ? 1.0 / piv : 0.0;
-        for (int i = j + 1 + tid; i < n; i += blockDim.x) L[pidx_lower(i, j)] *= rp;
-        if (tid == 0) L[pidx_lower(j, j)] = piv;
-        __syncthreads();
-        for (int r = j + 1 + ty; r < n; r += 32) {
-            const double lrj = L[pidx_lower(r, j)];
-            if (lrj == 0.0) continue;
-            for (int c = j + 1 + tx; c <= r; c += 32) L[pidx_lower(r, c)] -= lrj * L[pidx_lower(c, j)];
-        }
-        __syncthreads();
-    }
+    chol_packed_lds(L, piv, n, rel_tol * s_max);
     for (int i = ty; i < n; i += 32)
         for (int j = tx; j < n; j += 32) Lo[(int64_t)i * n + j] = j <= i ? L[pidx_lower(i, j)] : 0.0;
 }
@@ -510,8 +503,10 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double *__
     __shared__ int pp[kMaxSmall / 2], qq[kMaxSmall / 2];
     __shared__ double red_off[kJacobiThreads / 64], red_dg[kJacobiThreads / 64];
     __shared__ int s_done;
+    __shared__ int s_rot[2];            // a step has a non-identity rotation (by parity of the step count)
     const int tid = threadIdx.x, h = n / 2, m = n - 1;
     const int npk = n * (n + 1) / 2, nitems = h * (h + 1) / 2;
+    if (tid == 0) s_rot[0] = s_rot[1] = 0;
     for (int idx = tid; idx < nitems; idx += kJacobiThreads) {
         int a, b;
         tri_pair(idx, h, a, b);
@@ -572,7 +567,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double *__
                 // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), tau = (aqq - app) / (2 apq), the
                 // smaller rotation angle; c = 1 / sqrt(1 + t^2), s = t c
                 double c = 1.0, sn = 0.0;
-                if (fabs(apq) > 1e-300 && apq * apq > 1e-36 * fabs(app) * fabs(aqq)) {
+                if (fabs(apq) > 1e-300 && apq * apq > 1e-30 * fabs(app) * fabs(aqq)) {
                     const double tau = (aqq - app) * rcp_nr(2.0 * apq);
                     double t;
                     if (fabs(tau) > 1e150) {
@@ -586,10 +581,14 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double *__
                 }
                 rot[tid] = make_double2(c, sn);
                 rot_log[(int64_t)nsteps * h + tid] = make_double2(c, sn);
+                if (sn != 0.0) s_rot[nsteps & 1] = 1;
             }
             __syncthreads();
-            // B <- J^T B J on the 2x2 blocks of pairs (a <= b)
-            for (int idx = tid; idx < nitems; idx += kJacobiThreads) {
+            const bool any_rot = s_rot[nsteps & 1] != 0;
+            if (tid == 0) s_rot[(nsteps + 1) & 1] = 0;
+            // B <- J^T B J on the 2x2 blocks of pairs (a <= b); a step of identity
+            // rotations (off-diagonal entries below 1e-15 relative) changes nothing
+            for (int idx = tid; any_rot && idx < nitems; idx += kJacobiThreads) {
                 const int ab = items[idx], a = ab & 0xff, b = ab >> 8;
                 const int pa = pp[a], qa = qq[a];
                 const double ca = rot[a].x, sa = rot[a].y;
