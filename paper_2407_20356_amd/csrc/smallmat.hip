@@ -443,7 +443,8 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
 // Parallel-order (round-robin) cyclic Jacobi on a symmetric n x n matrix, n even.
 // In step s the n/2 disjoint pairs are (0, x(0)) and (x(a), x(m-a)), a = 1..n/2-1,
 // with m = n-1 and x(i) = 1 + (i + s) mod m; every pair occurs once per sweep.
-// B lives in LDS as the packed upper triangle.  A step computes the n/2 rotations,
+// This version (used for n > 128) keeps B in LDS as the packed upper triangle.
+// A step computes the n/2 rotations,
 // then updates B on the 2x2 blocks of every pair of pairs (a <= b), spread evenly
 // over the block's threads; the rotations of every step are logged, and the
 // eigenvectors P = J_1 J_2 ... are formed afterwards, one row per wave.
@@ -677,6 +678,306 @@ __global__ __launch_bounds__(64 * kReplayWaves) void jacobi_replay_kernel(const 
     for (int j = lane; j < n; j += 64) P[(int64_t)row * n + j] = rv[j];
 }
 
+// ---------------------------------------------------------------- Jacobi on slots (n <= 128)
+// The same round-robin order, with B physically permuted after every step so
+// that the pairs are always slots (2a, 2a+1).  Circle position c (0 <= c < m)
+// holds index 1 + (c + s) mod m at step s; slot 0 holds index 0, slot 1 circle
+// 0, slot 2a circle a and slot 2a+1 circle m-a (a >= 1).  Between steps every
+// circle position moves down by one, a fixed slot permutation pi, so each
+// thread reads and writes the same LDS words in every step.
+//
+// B is kept as 2x2 blocks of slot pairs (a <= b) in four planes (plane 2r+t
+// holds element (2a+r, 2b+t) of block b(b+1)/2 + a), double-buffered: a step
+// reads one buffer and writes the rotated, permuted blocks into the other.
+// Wave 0 computes the next step's rotations while the other waves update B: the
+// next diagonal block of pair a comes from three blocks of the current step
+// (those of the two slots that move into 2a and 2a+1), so the only barrier of a
+// step is the one that ends it.  Rotations are logged in slot roles.
+constexpr int kSlotMaxH = 64;
+constexpr int kSlotMaxBlk = kSlotMaxH * (kSlotMaxH + 1) / 2;
+constexpr int kSlotThreads = 1024;
+
+__device__ __forceinline__ int slot_circ(int j, int m) { return j == 1 ? 0 : ((j & 1) ? m - (j >> 1) : (j >> 1)); }
+__device__ __forceinline__ int circ_slot(int c, int h, int m) { return c == 0 ? 1 : (c < h ? 2 * c : 2 * (m - c) + 1); }
+__device__ __forceinline__ int next_slot(int j, int h, int m) {
+    if (j == 0) return 0;
+    const int c = slot_circ(j, m);
+    return circ_slot(c == 0 ? m - 1 : c - 1, h, m);
+}
+__device__ __forceinline__ int prev_slot(int j, int h, int m) {
+    if (j == 0) return 0;
+    const int c = slot_circ(j, m) + 1;
+    return circ_slot(c == m ? 0 : c, h, m);
+}
+__device__ __forceinline__ int slot_index_at0(int j, int m) { return j == 0 ? 0 : 1 + slot_circ(j, m); }
+// LDS word of element (i, j) of the slot matrix, either order
+__device__ __forceinline__ int slot_elem(int i, int j) {
+    int pa = i >> 1, pb = j >> 1, r = i & 1, t = j & 1;
+    if (pa > pb) {
+        int x = pa;
+        pa = pb;
+        pb = x;
+        x = r;
+        r = t;
+        t = x;
+    }
+    if (pa == pb && r > t) {
+        r = 0;
+        t = 1;
+    }
+    return (r * 2 + t) * kSlotMaxBlk + pb * (pb + 1) / 2 + pa;
+}
+__device__ __forceinline__ void slot_blk_ab(int idx, int &a, int &b) {
+    int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+    while (j * (j + 1) / 2 > idx) --j;
+    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+    b = j;
+    a = idx - j * (j + 1) / 2;
+}
+__device__ __forceinline__ int slot_blk(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
+
+// Rotation of the pair (x, y) with entries (app, apq, aqq): t = tan of the smaller
+// angle, t = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app, from the
+// hardware estimates (the angle need not be exact: the rotated off-diagonal
+// entry is computed, not assumed zero); c = 1 / sqrt(1 + t^2) to full precision,
+// so the rotation is orthogonal to rounding.
+__device__ __forceinline__ double2 slot_rotation(double app, double apq, double aqq) {
+    double c = 1.0, sn = 0.0;
+    if (fabs(apq) > 1e-300 && apq * apq > 1e-30 * fabs(app) * fabs(aqq)) {
+        const double d = aqq - app, a2 = 2.0 * apq;
+        const double r2 = fma(d, d, a2 * a2);
+        const double hyp = r2 * __builtin_amdgcn_rsq(r2);
+        const double t = (d >= 0.0 ? a2 : -a2) * __builtin_amdgcn_rcp(fabs(d) + hyp);
+        c = rsq_nr(fma(t, t, 1.0));
+        sn = t * c;
+    }
+    return make_double2(c, sn);
+}
+// column r of the rotation [[c, s], [-s, c]]
+__device__ __forceinline__ void rot_col(double2 q, int r, double &u0, double &u1) {
+    u0 = r == 0 ? q.x : q.y;
+    u1 = r == 0 ? -q.y : q.x;
+}
+
+__global__ __launch_bounds__(kSlotThreads) void jacobi_slots_kernel(const double *__restrict__ Bg, int n,
+                                                                    double *__restrict__ lam,
+                                                                    double2 *__restrict__ rot_log,
+                                                                    int *__restrict__ nsteps_out, int *flags) {
+    constexpr int kWork = kSlotThreads - 64;       // waves 1.. own the blocks
+    constexpr int kIPT = (kSlotMaxBlk + kWork - 1) / kWork;
+    constexpr int kW = kSlotThreads / 64;
+    __shared__ __align__(16) double buf[2][4 * kSlotMaxBlk];
+    __shared__ __align__(16) double2 rot[2][kSlotMaxH];
+    __shared__ double red_off[kW], red_dg[kW];
+    __shared__ int s_done;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int h = n / 2, m = n - 1, nblk = h * (h + 1) / 2;
+    // blocks owned by this thread: pairs (a, b), destinations of their four elements
+    int ia[kIPT], ib[kIPT], dst[kIPT][4];
+#pragma unroll
+    for (int u = 0; u < kIPT; ++u) {
+        const int idx = tid - 64 + kWork * u;
+        ia[u] = -1;
+        ib[u] = 0;
+        dst[u][0] = dst[u][1] = dst[u][2] = dst[u][3] = 0;
+        if (wv > 0 && idx < nblk) {
+            int a, b;
+            slot_blk_ab(idx, a, b);
+            ia[u] = a;
+            ib[u] = b;
+            const int p0 = next_slot(2 * a, h, m), p1 = next_slot(2 * a + 1, h, m);
+            const int q0 = next_slot(2 * b, h, m), q1 = next_slot(2 * b + 1, h, m);
+            dst[u][0] = slot_elem(p0, q0);
+            dst[u][1] = slot_elem(p0, q1);
+            dst[u][2] = slot_elem(p1, q0);
+            dst[u][3] = slot_elem(p1, q1);
+        }
+    }
+    // wave 0, lane a: the slots that move into 2a and 2a+1, their pairs and blocks
+    const int la = lane < h ? lane : 0;
+    const int s0 = prev_slot(2 * la, h, m), s1 = prev_slot(2 * la + 1, h, m);
+    const int P0 = s0 >> 1, P1 = s1 >> 1, r0 = s0 & 1, r1 = s1 & 1;
+    const int d0 = P0 * (P0 + 3) / 2, d1 = P1 * (P1 + 3) / 2, xb = slot_blk(P0, P1);
+    for (int e = tid; e < nblk * 4; e += kSlotThreads) {
+        const int blk = e >> 2, pos = e & 3;
+        int a, b;
+        slot_blk_ab(blk, a, b);
+        const int gi = slot_index_at0(2 * a + (pos >> 1), m), gj = slot_index_at0(2 * b + (pos & 1), m);
+        buf[0][pos * kSlotMaxBlk + blk] = 0.5 * (Bg[(int64_t)gi * n + gj] + Bg[(int64_t)gj * n + gi]);
+    }
+    __syncthreads();
+    if (wv == 0 && lane < h) {
+        const int dblk = lane * (lane + 3) / 2;
+        const double2 r = slot_rotation(buf[0][dblk], buf[0][kSlotMaxBlk + dblk], buf[0][3 * kSlotMaxBlk + dblk]);
+        rot[0][lane] = r;
+        rot_log[lane] = r;
+    }
+    // circle offsets of the indices in slots 2a (a >= 1) and 2a+1 of pair `lane`
+    int xa = lane % m, ya = (m - lane) % m;
+    int cur = 0, nsteps = 0;
+    bool converged = false;
+    for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int e = tid; e < nblk; e += kSlotThreads) {
+            int a, b;
+            slot_blk_ab(e, a, b);
+            const double *q = buf[cur] + e;
+            const double x = q[0], y = q[kSlotMaxBlk], z = q[2 * kSlotMaxBlk], w = q[3 * kSlotMaxBlk];
+            if (a == b) {
+                off += y * y;
+                dg += x * x + w * w;
+            } else {
+                off += x * x + y * y + z * z + w * w;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            dg += __shfl_xor(dg, o);
+        }
+        if (lane == 0) {
+            red_off[wv] = off;
+            red_dg[wv] = dg;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double so = 0.0, sd = 0.0;
+            for (int w = 0; w < kW; ++w) {
+                so += red_off[w];
+                sd += red_dg[w];
+            }
+            s_done = (so <= 1e-26 * sd) || so == 0.0;
+        }
+        __syncthreads();
+        if (s_done) {
+            converged = true;
+            break;
+        }
+        if (sweep == kMaxSweeps) break;
+        for (int s = 0; s < m; ++s) {
+            const double *B = buf[cur];
+            double *Bn = buf[cur ^ 1];
+            const double2 *R = rot[nsteps & 1];
+            if (wv == 0) {
+                if (lane < h) {
+                    // next step's diagonal block of pair `lane`, rotated out of this step's blocks
+                    double u00, u01, u10, u11;
+                    rot_col(R[P0], r0, u00, u01);
+                    rot_col(R[P1], r1, u10, u11);
+                    const double a0 = B[d0], b0 = B[kSlotMaxBlk + d0], c0 = B[3 * kSlotMaxBlk + d0];
+                    const double a1 = B[d1], b1 = B[kSlotMaxBlk + d1], c1 = B[3 * kSlotMaxBlk + d1];
+                    const double x = B[xb], y = B[kSlotMaxBlk + xb], z = B[2 * kSlotMaxBlk + xb],
+                                 w = B[3 * kSlotMaxBlk + xb];
+                    const double app = u00 * (u00 * a0 + u01 * b0) + u01 * (u00 * b0 + u01 * c0);
+                    const double aqq = u10 * (u10 * a1 + u11 * b1) + u11 * (u10 * b1 + u11 * c1);
+                    double apq;
+                    if (P0 < P1)
+                        apq = u00 * (x * u10 + y * u11) + u01 * (z * u10 + w * u11);
+                    else if (P0 > P1)
+                        apq = u10 * (x * u00 + y * u01) + u11 * (z * u00 + w * u01);
+                    else   // n = 2: the same pair again
+                        apq = u00 * (u10 * a0 + u11 * b0) + u01 * (u10 * b0 + u11 * c0);
+                    const double2 r = slot_rotation(app, apq, aqq);
+                    rot[(nsteps + 1) & 1][lane] = r;
+                    rot_log[(int64_t)(nsteps + 1) * h + lane] = r;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kIPT; ++u) {
+                    if (ia[u] < 0) continue;
+                    const int a = ia[u], b = ib[u];
+                    const double *q = B + (b * (b + 1) / 2 + a);
+                    const double x = q[0], y = q[kSlotMaxBlk], z = q[2 * kSlotMaxBlk], w = q[3 * kSlotMaxBlk];
+                    const double2 ra = R[a], rb = R[b];
+                    if (a != b) {
+                        const double x1 = rb.x * x - rb.y * y, y1 = rb.y * x + rb.x * y;
+                        const double z1 = rb.x * z - rb.y * w, w1 = rb.y * z + rb.x * w;
+                        Bn[dst[u][0]] = ra.x * x1 - ra.y * z1;
+                        Bn[dst[u][1]] = ra.x * y1 - ra.y * w1;
+                        Bn[dst[u][2]] = ra.y * x1 + ra.x * z1;
+                        Bn[dst[u][3]] = ra.y * y1 + ra.x * w1;
+                    } else {
+                        const double c = ra.x, sn = ra.y;
+                        Bn[dst[u][0]] = c * c * x - 2.0 * c * sn * y + sn * sn * w;
+                        Bn[dst[u][3]] = sn * sn * x + 2.0 * c * sn * y + c * c * w;
+                        Bn[dst[u][1]] = (c * c - sn * sn) * y + c * sn * (x - w);
+                    }
+                }
+            }
+            __syncthreads();
+            cur ^= 1;
+            ++nsteps;
+            xa = xa + 1 == m ? 0 : xa + 1;
+            ya = ya + 1 == m ? 0 : ya + 1;
+        }
+    }
+    if (wv == 0 && lane < h) {
+        const int dblk = lane * (lane + 3) / 2;
+        lam[lane == 0 ? 0 : 1 + xa] = buf[cur][dblk];
+        lam[1 + ya] = buf[cur][3 * kSlotMaxBlk + dblk];
+    }
+    if (tid == 0) {
+        *nsteps_out = nsteps;
+        if (!converged) atomicOr(&flags[kFlagNumeric], 1);
+    }
+}
+
+// Lane shifts across the wave (DPP wave_shl:1 / wave_shr:1), on the two halves of a double.
+__device__ __forceinline__ double wave_from_next(double v) {   // lane i receives lane i + 1
+    const int2 x = __builtin_bit_cast(int2, v);
+    int2 y;
+    y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x130, 0xf, 0xf, false);
+    y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, y);
+}
+__device__ __forceinline__ double wave_from_prev(double v) {   // lane i receives lane i - 1
+    const int2 x = __builtin_bit_cast(int2, v);
+    int2 y;
+    y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x138, 0xf, 0xf, false);
+    y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x138, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, y);
+}
+
+// Eigenvectors from the slot log: one wave per row of P, lane a holding the row's
+// entries in slots 2a and 2a+1.  A step rotates them in registers and applies pi
+// with lane shifts (pi moves slot 2a to 2a-2 and slot 2a+1 to 2a+3, except at
+// pairs 0, 1 and h-1); rotations are prefetched kSlotRing steps ahead.
+constexpr int kSlotRing = 8;
+__global__ __launch_bounds__(256) void jacobi_slots_replay_kernel(const double2 *__restrict__ rot_log,
+                                                                  const int *__restrict__ nsteps_ptr, int n,
+                                                                  double *__restrict__ P) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int h = n / 2, m = n - 1;
+    const int srow = row == 0 ? 0 : circ_slot(row - 1, h, m);
+    double v0 = (lane < h && 2 * lane == srow) ? 1.0 : 0.0;
+    double v1 = (lane < h && 2 * lane + 1 == srow) ? 1.0 : 0.0;
+    const int nsteps = *nsteps_ptr;
+    const int la = lane < h ? lane : h - 1;
+    const int last = nsteps > 0 ? nsteps - 1 : 0;
+    double2 ring[kSlotRing];
+#pragma unroll
+    for (int d = 0; d < kSlotRing; ++d) ring[d] = rot_log[(int64_t)(d < last ? d : last) * h + la];
+    for (int st = 0; st < nsteps; st += kSlotRing) {
+#pragma unroll
+        for (int d = 0; d < kSlotRing; ++d) {
+            const double2 r = ring[d];
+            const int nx = st + d + kSlotRing < last ? st + d + kSlotRing : last;
+            ring[d] = rot_log[(int64_t)nx * h + la];
+            if (st + d < nsteps) {
+                const double a0 = r.x * v0 - r.y * v1, a1 = r.y * v0 + r.x * v1;
+                const double from_next = wave_from_next(a0), from_prev = wave_from_prev(a1);
+                v0 = lane == 0 ? a0 : (lane == h - 1 ? a1 : from_next);
+                v1 = lane == 0 ? (h == 1 ? a1 : from_next) : from_prev;
+            }
+        }
+    }
+    if (lane < h) {
+        P[(int64_t)row * n + (lane == 0 ? 0 : 1 + (lane + nsteps) % m)] = v0;
+        P[(int64_t)row * n + 1 + (m - lane + nsteps) % m] = v1;
+    }
+}
+
 // ---------------------------------------------------------------- basis selection
 // perm by decreasing eigenvalue (ties by index), T_u[i][r] = P[i][perm[r]], sigma.
 __global__ __launch_bounds__(256) void select_kernel(const double *__restrict__ lam, const double *__restrict__ P,
@@ -896,6 +1197,14 @@ xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, do
     if (n > kMaxSmall || n % 2) return fail(ctx, XPCS_EUNSUPPORTED, "eigen size must be even and <= 192");
     int *nsteps = static_cast<int *>(rot);
     double2 *log = reinterpret_cast<double2 *>(static_cast<char *>(rot) + 256);
+    if (n <= 2 * kSlotMaxH) {
+        hipLaunchKernelGGL(jacobi_slots_kernel, dim3(1), dim3(kSlotThreads), 0, ctx->stream, B, n, lam, log, nsteps,
+                           ctx->flags);
+        XPCS_LAUNCH_CHECK(ctx, "jacobi_slots");
+        hipLaunchKernelGGL(jacobi_slots_replay_kernel, dim3((n + 3) / 4), dim3(256), 0, ctx->stream, log, nsteps, n, P);
+        XPCS_LAUNCH_CHECK(ctx, "jacobi_slots_replay");
+        return XPCS_OK;
+    }
     hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, ctx->stream, B, n, lam, log, nsteps,
                        ctx->flags);
     XPCS_LAUNCH_CHECK(ctx, "jacobi");

@@ -212,6 +212,27 @@ def test_offline_pipeline_parity_without_power_iteration(ctx):
     _assert_parity(C, g2, npairs, _oracle_compressed(F, Uo, labels, 4))
 
 
+@pytest.mark.parametrize("k,oversample", [(100, 28), (150, 30)])
+def test_offline_pipeline_parity_wide_sketch(ctx, k, oversample):
+    """As above with wide sketches: l = 128 is the largest eigenproblem solved on
+    slot-paired blocks, l = 180 takes the packed-triangle eigensolver."""
+    from paper_2407_20356_amd import api
+    H = W = 64
+    labels = synth.annular_labels(H, W, 3, r_in=3.0)
+    F = synth.speckle_frames_numpy(H * W, 600, 0.3, 0.2, 30.0, "u8", seed=32)
+    seed = 777
+    say(f"offline q=0 parity, k={k} oversample={oversample}")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 3, k=k, oversample=oversample, seed=seed,
+                            power_iters=0)
+    ctx.sync()
+    fn = _factors_np(f)
+    Uo, so, Vo = O.randomized_basis(F, k, oversample, 0, seed=seed)
+    np.testing.assert_allclose(fn["sigma"], so, rtol=1e-5)
+    assert np.abs(fn["U"].T @ fn["U"] - np.eye(k)).max() <= 1e-5
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, _oracle_compressed(F, Uo, labels, 3))
+
+
 def test_offline_basis_multi_roi_u16(ctx):
     from paper_2407_20356_amd import api
     H = W = 96
