@@ -50,6 +50,7 @@ typedef int32_t xpcs_status;
 #define XPCS_EBUDGET (-4)       /* the workspace would exceed the context's HBM budget  */
 #define XPCS_EDEVICE (-5)       /* HIP runtime error or a failed device-side step      */
 #define XPCS_EUNSUPPORTED (-6)  /* valid request outside what this build implements    */
+#define XPCS_EQUEUED (-7)       /* the served stream still waits for admission          */
 
 /* element type of the frames */
 #define XPCS_U8 1
@@ -255,6 +256,73 @@ int64_t xpcs_stream_frames(const xpcs_stream *s);
 
 /* Releases the stream's device memory (after the work in flight). NULL is ignored. */
 void xpcs_stream_close(xpcs_stream *s);
+
+/* ------------------------------------------------------------------ serving
+ * A server runs many online streams (above) -- detectors of different sizes
+ * and ROI maps -- on one GPU at once (the real-time use of the online strategy,
+ * Sec. 2.2 and Sec. 3.2).  Each admitted stream is placed on one of `lanes`
+ * lanes (the one with the fewest streams); a lane is a HIP stream with its own
+ * workspace, so that the blocks of streams on different lanes run concurrently
+ * on the device.  Requests are admitted in the order they are made, while a
+ * slot (`max_streams`) and HBM under `hbm_budget_bytes` (0 = no budget) are free
+ * -- stream state plus lane workspaces; the others wait, and a close admits the
+ * waiting requests that then fit, in order.  Every block is timed from the push
+ * call to the end of its work on the GPU with device events.
+ *
+ * A stream's results are those of the same stream run alone with
+ * xpcs_stream_* (the same kernels on the same data, in the same order).  The
+ * calls on one server must not overlap (one host thread at a time). */
+typedef struct xpcs_server xpcs_server;
+
+#define XPCS_STREAM_QUEUED 1
+#define XPCS_STREAM_ADMITTED 2
+#define XPCS_STREAM_FAILED 3     /* admitted later, but its open failed (see last_error) */
+
+/* lanes in 1..16, max_streams >= 1.  Errors: EINVAL, EDEVICE, ENOMEM. */
+xpcs_status xpcs_server_create(int device, size_t hbm_budget_bytes, int32_t lanes, int32_t max_streams,
+                               xpcs_server **out);
+/* Closes every stream (after its work) and frees the server. NULL is ignored. */
+void xpcs_server_destroy(xpcs_server *srv);
+const char *xpcs_server_last_error(const xpcs_server *srv);
+
+/* Requests a stream described as for xpcs_stream_open; *id names it from now on
+ * and *state (may be NULL) says whether it was admitted at once -- its open then
+ * ran to completion in this call, so roi_label and basis may be released -- or
+ * queued, in which case roi_label and basis must stay valid until
+ * xpcs_server_state reports XPCS_STREAM_ADMITTED or XPCS_STREAM_FAILED.
+ * Errors: those of xpcs_stream_open; EBUDGET when the stream alone exceeds the
+ * budget. */
+xpcs_status xpcs_server_open(xpcs_server *srv, const xpcs_stream_desc *desc, int64_t *id, int32_t *state);
+xpcs_status xpcs_server_state(xpcs_server *srv, int64_t id, int32_t *state);
+
+/* Pushes a block of stream `id` as xpcs_stream_push does, on the stream's lane,
+ * after the work enqueued so far on `producer` (a hipStream_t, NULL = none), so
+ * that frames written there are complete.  frames and band must stay valid until
+ * xpcs_server_poll reports the block.  Errors: EQUEUED while the stream waits;
+ * those of xpcs_stream_push. */
+xpcs_status xpcs_server_push(xpcs_server *srv, int64_t id, const void *frames, int64_t nframes, void *band,
+                             int32_t c_dtype, void *producer);
+
+/* Reports, without waiting, the stream's completed blocks in push order: up to
+ * `cap` of them, latency_ms[i] (push call to the end of the block's work on the
+ * GPU) and frames[i] (either may be NULL); *count = how many were reported. */
+xpcs_status xpcs_server_poll(xpcs_server *srv, int64_t id, int32_t cap, double *latency_ms, int64_t *frames,
+                             int32_t *count);
+
+/* g2 snapshot of stream `id` (as xpcs_stream_g2), enqueued on its lane. */
+xpcs_status xpcs_server_g2(xpcs_server *srv, int64_t id, double *g2, int64_t *npairs);
+
+/* Waits for the work enqueued for stream `id` (its lane), or for every lane
+ * when id == 0, and reports device-side errors as xpcs_sync does. */
+xpcs_status xpcs_server_wait(xpcs_server *srv, int64_t id);
+
+/* Closes stream `id` (waiting for its lane) or withdraws its request, releases
+ * its memory and admits waiting requests that now fit. */
+xpcs_status xpcs_server_close(xpcs_server *srv, int64_t id);
+
+/* Device bytes held (stream state plus lane workspaces), admitted streams and
+ * waiting requests; any pointer may be NULL. */
+xpcs_status xpcs_server_stats(const xpcs_server *srv, size_t *bytes_used, int32_t *admitted, int32_t *queued);
 
 #ifdef __cplusplus
 }

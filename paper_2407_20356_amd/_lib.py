@@ -19,8 +19,13 @@ XPCS_ERANGE = -3
 XPCS_EBUDGET = -4
 XPCS_EDEVICE = -5
 XPCS_EUNSUPPORTED = -6
+XPCS_EQUEUED = -7
 STATUS_NAMES = {0: "XPCS_OK", -1: "XPCS_EINVAL", -2: "XPCS_ENOMEM", -3: "XPCS_ERANGE",
-                -4: "XPCS_EBUDGET", -5: "XPCS_EDEVICE", -6: "XPCS_EUNSUPPORTED"}
+                -4: "XPCS_EBUDGET", -5: "XPCS_EDEVICE", -6: "XPCS_EUNSUPPORTED", -7: "XPCS_EQUEUED"}
+
+XPCS_STREAM_QUEUED = 1
+XPCS_STREAM_ADMITTED = 2
+XPCS_STREAM_FAILED = 3
 
 XPCS_U8 = 1
 XPCS_U16 = 2
@@ -82,6 +87,17 @@ SIGNATURES = {
     "xpcs_stream_g2": (_ST, [_P, _P, _P]),
     "xpcs_stream_frames": (_I64, [_P]),
     "xpcs_stream_close": (None, [_P]),
+    "xpcs_server_create": (_ST, [ctypes.c_int, ctypes.c_size_t, _I32, _I32, ctypes.POINTER(_P)]),
+    "xpcs_server_destroy": (None, [_P]),
+    "xpcs_server_last_error": (ctypes.c_char_p, [_P]),
+    "xpcs_server_open": (_ST, [_P, ctypes.POINTER(XpcsStreamDesc), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    "xpcs_server_state": (_ST, [_P, _I64, ctypes.POINTER(_I32)]),
+    "xpcs_server_push": (_ST, [_P, _I64, _P, _I64, _P, _I32, _P]),
+    "xpcs_server_poll": (_ST, [_P, _I64, _I32, _P, _P, ctypes.POINTER(_I32)]),
+    "xpcs_server_g2": (_ST, [_P, _I64, _P, _P]),
+    "xpcs_server_wait": (_ST, [_P, _I64]),
+    "xpcs_server_close": (_ST, [_P, _I64]),
+    "xpcs_server_stats": (_ST, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
 }
 
 _lib = None

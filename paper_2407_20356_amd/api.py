@@ -6,9 +6,10 @@ computation runs in libxpcs.so.  Function names follow the C entry points.
 
 from __future__ import annotations
 
+import collections
 import ctypes
 from dataclasses import dataclass
-from typing import Optional, Tuple
+from typing import List, Optional, Tuple
 
 import torch
 
@@ -291,5 +292,117 @@ class Stream:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Many online streams served on one GPU (xpcs_server_*).
+
+    open() requests a stream (same arguments as Stream) and returns (id, state):
+    XPCS_STREAM_ADMITTED at once, or XPCS_STREAM_QUEUED until a close frees a slot
+    and memory.  push() enqueues a block on the stream's lane after the work on
+    the current torch stream (which produced the frames) and returns the band
+    tensor, to be read once poll() has reported the block (or after wait()).
+    poll() returns the completed blocks' (latency_ms, frames) in push order.
+    """
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, lanes: int = 4, max_streams: int = 64):
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.lib.xpcs_server_create(device, hbm_budget_bytes, lanes, max_streams, ctypes.byref(h))
+        if st != L.XPCS_OK:
+            raise XpcsError(st, "xpcs_server_create failed")
+        self.handle = h
+        self._info = {}
+
+    def check(self, status: int):
+        if status != L.XPCS_OK:
+            raise XpcsError(status, self.lib.xpcs_server_last_error(self.handle).decode())
+
+    def open(self, roi_label: torch.Tensor, n_roi: int, basis: torch.Tensor, window: int, max_block: int,
+             dtype=torch.uint8) -> Tuple[int, int]:
+        _check_device(roi_label, "roi_label", self.device)
+        _check_device(basis, "basis", self.device)
+        if roi_label.dtype != torch.int32:
+            raise TypeError("roi_label must be int32")
+        if basis.dtype != torch.float32 or basis.dim() != 2 or basis.shape[1] != roi_label.shape[0]:
+            raise ValueError("basis must be a (k, M) float32 tensor")
+        code = L.XPCS_U8 if dtype == torch.uint8 else L.XPCS_U16
+        d = L.XpcsStreamDesc(roi_label.shape[0], code, n_roi, basis.shape[0], 0, roi_label.data_ptr(),
+                             basis.data_ptr(), window, max_block)
+        torch.cuda.current_stream(self.device).synchronize()      # labels and basis are complete
+        sid, state = ctypes.c_int64(), ctypes.c_int32()
+        self.check(self.lib.xpcs_server_open(self.handle, ctypes.byref(d), ctypes.byref(sid), ctypes.byref(state)))
+        # a queued request reads roi_label and basis when it is admitted: keep them
+        self._info[sid.value] = dict(n_roi=n_roi, window=window, dtype=code, refs=(roi_label, basis),
+                                     pending=collections.deque(), held=[])
+        return sid.value, state.value
+
+    def state(self, sid: int) -> int:
+        s = ctypes.c_int32()
+        self.check(self.lib.xpcs_server_state(self.handle, sid, ctypes.byref(s)))
+        return s.value
+
+    def push(self, sid: int, frames: torch.Tensor, want_band: bool = True, band: Optional[torch.Tensor] = None):
+        info = self._info[sid]
+        _check_device(frames, "frames", self.device)
+        if _frame_dtype(frames) != info["dtype"]:
+            raise TypeError("frames do not have the stream's dtype")
+        nb = frames.shape[0]
+        if band is None and want_band and nb > 0:
+            band = torch.empty((info["n_roi"], nb, info["window"]), dtype=torch.float32, device=self.device)
+        producer = torch.cuda.current_stream(self.device).cuda_stream
+        self.check(self.lib.xpcs_server_push(self.handle, sid, _ptr(frames), nb, _ptr(band),
+                                             _c_code(band.dtype) if band is not None else L.XPCS_F32,
+                                             ctypes.c_void_p(producer)))
+        info["pending"].append((frames, band))     # kept alive until the block is reported
+        return band
+
+    def poll(self, sid: int, cap: int = 4096) -> List[Tuple[float, int]]:
+        info = self._info[sid]
+        lat = (ctypes.c_double * cap)()
+        nfr = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        self.check(self.lib.xpcs_server_poll(self.handle, sid, cap, ctypes.cast(lat, ctypes.c_void_p),
+                                             ctypes.cast(nfr, ctypes.c_void_p), ctypes.byref(n)))
+        for _ in range(n.value):
+            info["pending"].popleft()
+        return [(lat[i], nfr[i]) for i in range(n.value)]
+
+    def g2(self, sid: int) -> Tuple[torch.Tensor, torch.Tensor]:
+        """g2 sums of the stream (enqueued on its lane: valid after wait())."""
+        info = self._info[sid]
+        g2 = torch.empty((info["n_roi"], info["window"]), dtype=torch.float64, device=self.device)
+        npairs = torch.empty((info["n_roi"], info["window"]), dtype=torch.int64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()      # the buffers exist before the lane writes
+        self.check(self.lib.xpcs_server_g2(self.handle, sid, _ptr(g2), _ptr(npairs)))
+        info["held"].append((g2, npairs))
+        return g2, npairs
+
+    def wait(self, sid: int = 0):
+        self.check(self.lib.xpcs_server_wait(self.handle, sid))
+        for info in ([self._info[sid]] if sid else self._info.values()):
+            info["held"].clear()
+
+    def close(self, sid: int):
+        self.check(self.lib.xpcs_server_close(self.handle, sid))
+        self._info.pop(sid, None)
+
+    def stats(self) -> Tuple[int, int, int]:
+        b, a, q = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int32()
+        self.check(self.lib.xpcs_server_stats(self.handle, ctypes.byref(b), ctypes.byref(a), ctypes.byref(q)))
+        return b.value, a.value, q.value
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self.lib.xpcs_server_destroy(self.handle)
+            self.handle = None
+            self._info.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass

@@ -257,4 +257,9 @@ xpcs_status launch_lowrank_prep(xpcs_ctx *ctx, const xpcs_factors *f, const doub
                                 int64_t t0, int64_t nw, int kp, unsigned short *z_hi, unsigned short *z_lo,
                                 unsigned char *valid);
 
+// ---------------------------------------------------------------- online streams (stream.hip)
+// Device bytes of a stream's state, and the most workspace its open and pushes take.
+size_t stream_state_bytes(const xpcs_stream_desc *d);
+size_t stream_workspace_bytes(const xpcs_stream_desc *d);
+
 }  // namespace xpcs

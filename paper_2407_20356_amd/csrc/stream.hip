@@ -40,6 +40,60 @@ namespace xpcs {
 namespace {
 
 constexpr int kMaxStreamK = 192;
+
+// Offsets of the pieces of a stream's single device allocation.
+struct StreamLayout {
+    int kp, L16;
+    int64_t cap, ldq;
+    size_t o_lab, o_uh, o_ul, o_np, o_lr, o_zh, o_zl, o_va, o_gs, o_gc, total;
+};
+StreamLayout stream_layout(const xpcs_stream_desc *d) {
+    StreamLayout l;
+    l.kp = (int)((d->k + 31) / 32 * 32);
+    l.L16 = (d->k + 15) / 16 * 16;
+    l.cap = d->window + d->max_block;
+    l.ldq = (d->M + 63) / 64 * 64;                  // basis rows padded to the projection's K step
+    size_t off = 0;
+    auto carve = [&](size_t b) { size_t o = off; off += align_up(b, 256); return o; };
+    l.o_lab = carve((size_t)d->M * 4);
+    l.o_uh = carve((size_t)l.L16 * l.ldq * 2);
+    l.o_ul = carve((size_t)l.L16 * l.ldq * 2);
+    l.o_np = carve((size_t)d->n_roi * 8);
+    l.o_lr = carve((size_t)d->n_roi * d->k * d->k * 8);
+    l.o_zh = carve((size_t)d->n_roi * l.cap * l.kp * 2);
+    l.o_zl = carve((size_t)d->n_roi * l.cap * l.kp * 2);
+    l.o_va = carve((size_t)d->n_roi * l.cap);
+    l.o_gs = carve((size_t)d->n_roi * d->window * 8);
+    l.o_gc = carve((size_t)d->n_roi * d->window * 8);
+    l.total = off;
+    return l;
+}
+
+// Workspace pieces of a push of nb frames after n frames (every piece 256-byte aligned).
+struct PushSizes {
+    size_t part, zb, sb, tp, tc, total;
+};
+PushSizes push_sizes(int64_t M, int L16, int n_roi, int64_t window, int64_t nb, int64_t n) {
+    const int64_t c0 = n - window + 1 > 0 ? n - window + 1 : 0;
+    const int64_t nbi = (nb + kTile - 1) / kTile, nbj = (n + nb - c0 + kTile - 1) / kTile;
+    const int64_t ntiles = (int64_t)n_roi * nbi * nbj;
+    const FrameProj plan = plan_proj_frames(M, nb, L16, n_roi, true);
+    PushSizes p;
+    p.part = (size_t)plan.nchunks * plan.ncols * nb * 4;
+    p.zb = (size_t)L16 * nb * 8;
+    p.sb = (size_t)n_roi * nb * 8;
+    p.tp = (size_t)ntiles * kDiag * 8;
+    p.tc = (size_t)ntiles * kDiag * 4;
+    p.total = align_up(p.part, 256) + align_up(p.zb, 256) + align_up(p.sb, 256) + align_up(p.tp, 256) +
+              align_up(p.tc, 256) + 2048;
+    return p;
+}
+// The same for the Gram pieces taken when the stream opens.
+size_t open_ws_bytes(const xpcs_stream_desc *d) {
+    const int64_t tcap = d->M + d->n_roi;
+    return align_up((size_t)(d->n_roi + 1) * 8, 256) + 2 * align_up((size_t)tcap * 4, 256) +
+           align_up((size_t)d->n_roi * d->k * d->k * 8, 256) + 1024;
+}
 constexpr int kPrepF = 32;          // frames per prep block
 constexpr int kPrepC = 16;          // rows of L staged per step
 constexpr int kPitch = kTile + 1;
@@ -329,6 +383,21 @@ inline int grid_for(int64_t total) {
 }
 
 }  // namespace
+
+size_t stream_state_bytes(const xpcs_stream_desc *d) { return stream_layout(d).total; }
+
+size_t stream_workspace_bytes(const xpcs_stream_desc *d) {
+    // the Gram pieces of the open, and the largest push: every block size, with
+    // the band of the window fully populated (n >= window - 1 frames before it)
+    size_t w = open_ws_bytes(d);
+    const int L16 = stream_layout(d).L16;
+    for (int64_t nb = 1; nb <= d->max_block; ++nb) {
+        const size_t p = push_sizes(d->M, L16, d->n_roi, d->window, nb, d->window).total;
+        w = p > w ? p : w;
+    }
+    return w;
+}
+
 }  // namespace xpcs
 
 using namespace xpcs;
@@ -351,28 +420,19 @@ xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *d, xpcs_stre
     (void)hipSetDevice(ctx->device);
 
     auto *s = new xpcs_stream;
+    const StreamLayout lay = stream_layout(d);
     s->ctx = ctx;
     s->M = d->M;
     s->dtype = d->dtype;
     s->n_roi = d->n_roi;
     s->k = d->k;
-    s->kp = (int)((d->k + 31) / 32 * 32);
-    s->L16 = (d->k + 15) / 16 * 16;
+    s->kp = lay.kp;
+    s->L16 = lay.L16;
     s->window = d->window;
     s->max_block = d->max_block;
-    s->cap = d->window + d->max_block;
-    s->ldq = (d->M + 63) / 64 * 64;                 // basis rows padded to the projection's K step
-
-    // one allocation for the stream's state
-    size_t off = 0;
-    auto carve = [&](size_t b) { size_t o = off; off += align_up(b, 256); return o; };
-    const size_t o_lab = carve((size_t)d->M * 4);
-    const size_t o_uh = carve((size_t)s->L16 * s->ldq * 2), o_ul = carve((size_t)s->L16 * s->ldq * 2);
-    const size_t o_np = carve((size_t)d->n_roi * 8);
-    const size_t o_lr = carve((size_t)d->n_roi * d->k * d->k * 8);
-    const size_t o_zh = carve((size_t)d->n_roi * s->cap * s->kp * 2), o_zl = carve((size_t)d->n_roi * s->cap * s->kp * 2);
-    const size_t o_va = carve((size_t)d->n_roi * s->cap);
-    const size_t o_gs = carve((size_t)d->n_roi * d->window * 8), o_gc = carve((size_t)d->n_roi * d->window * 8);
+    s->cap = lay.cap;
+    s->ldq = lay.ldq;
+    const size_t off = lay.total;
     s->bytes = off;
     if (ctx->budget && ctx->ws.capacity + ctx->scratch.capacity + ctx->persistent + s->bytes > ctx->budget) {
         delete s;
@@ -385,16 +445,16 @@ xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *d, xpcs_stre
     }
     ctx->persistent += s->bytes;
     char *base = static_cast<char *>(s->mem);
-    s->labels = reinterpret_cast<int32_t *>(base + o_lab);
-    s->u_hi = reinterpret_cast<unsigned short *>(base + o_uh);
-    s->u_lo = reinterpret_cast<unsigned short *>(base + o_ul);
-    s->roi_npix = reinterpret_cast<int64_t *>(base + o_np);
-    s->Lr = reinterpret_cast<double *>(base + o_lr);
-    s->z_hi = reinterpret_cast<unsigned short *>(base + o_zh);
-    s->z_lo = reinterpret_cast<unsigned short *>(base + o_zl);
-    s->valid = reinterpret_cast<unsigned char *>(base + o_va);
-    s->g2_sum = reinterpret_cast<double *>(base + o_gs);
-    s->g2_cnt = reinterpret_cast<int64_t *>(base + o_gc);
+    s->labels = reinterpret_cast<int32_t *>(base + lay.o_lab);
+    s->u_hi = reinterpret_cast<unsigned short *>(base + lay.o_uh);
+    s->u_lo = reinterpret_cast<unsigned short *>(base + lay.o_ul);
+    s->roi_npix = reinterpret_cast<int64_t *>(base + lay.o_np);
+    s->Lr = reinterpret_cast<double *>(base + lay.o_lr);
+    s->z_hi = reinterpret_cast<unsigned short *>(base + lay.o_zh);
+    s->z_lo = reinterpret_cast<unsigned short *>(base + lay.o_zl);
+    s->valid = reinterpret_cast<unsigned char *>(base + lay.o_va);
+    s->g2_sum = reinterpret_cast<double *>(base + lay.o_gs);
+    s->g2_cnt = reinterpret_cast<int64_t *>(base + lay.o_gc);
 
     auto bail = [&](xpcs_status st) {
         xpcs_stream_close(s);
@@ -409,9 +469,7 @@ xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *d, xpcs_stre
     ws_begin(ctx);
     const int64_t tcap = d->M + d->n_roi;
     const size_t b_g = (size_t)d->n_roi * d->k * d->k * 8;
-    if ((st = ws_reserve(ctx, align_up((size_t)(d->n_roi + 1) * 8, 256) + 2 * align_up((size_t)tcap * 4, 256) +
-                                  align_up(b_g, 256) + 1024)))
-        return bail(st);
+    if ((st = ws_reserve(ctx, open_ws_bytes(d)))) return bail(st);
     auto *roff = static_cast<int64_t *>(ws_take(ctx, (size_t)(d->n_roi + 1) * 8));
     auto *perm = static_cast<int32_t *>(ws_take(ctx, (size_t)tcap * 4));
     auto *qroi = static_cast<int32_t *>(ws_take(ctx, (size_t)tcap * 4));
@@ -439,20 +497,15 @@ xpcs_status xpcs_stream_push(xpcs_stream *s, const void *frames, int64_t nb, voi
     const int64_t c0 = n - W + 1 > 0 ? n - W + 1 : 0;
     const int nbi = (int)((nb + kTile - 1) / kTile);
     const int nbj = (int)((n + nb - c0 + kTile - 1) / kTile);
-    const int64_t ntiles = (int64_t)s->n_roi * nbi * nbj;
     const FrameProj plan = plan_proj_frames(s->M, nb, s->L16, s->n_roi, true);
-    const size_t b_part = (size_t)plan.nchunks * plan.ncols * nb * 4;
-    const size_t b_zb = (size_t)s->L16 * nb * 8, b_sb = (size_t)s->n_roi * nb * 8;
-    const size_t b_tp = (size_t)ntiles * kDiag * 8, b_tc = (size_t)ntiles * kDiag * 4;
+    const PushSizes ps = push_sizes(s->M, s->L16, s->n_roi, W, nb, n);
     xpcs_status st;
-    if ((st = ws_reserve(ctx, align_up(b_part, 256) + align_up(b_zb, 256) + align_up(b_sb, 256) +
-                                  align_up(b_tp, 256) + align_up(b_tc, 256) + 2048)))
-        return st;
-    auto *part = static_cast<float *>(ws_take(ctx, b_part));
-    auto *Zb = static_cast<double *>(ws_take(ctx, b_zb));
-    auto *Sb = static_cast<int64_t *>(ws_take(ctx, b_sb));
-    auto *tp = static_cast<double *>(ws_take(ctx, b_tp));
-    auto *tc = static_cast<int *>(ws_take(ctx, b_tc));
+    if ((st = ws_reserve(ctx, ps.total))) return st;
+    auto *part = static_cast<float *>(ws_take(ctx, ps.part));
+    auto *Zb = static_cast<double *>(ws_take(ctx, ps.zb));
+    auto *Sb = static_cast<int64_t *>(ws_take(ctx, ps.sb));
+    auto *tp = static_cast<double *>(ws_take(ctx, ps.tp));
+    auto *tc = static_cast<int *>(ws_take(ctx, ps.tc));
     // 1. W rows and exact ROI sums of the new frames (one pass over their counts)
     if ((st = launch_proj_frames(ctx, frames, s->dtype, s->M, nb, s->u_hi, s->u_lo, s->ldq, s->L16, s->labels,
                                  s->n_roi, plan, part)))

@@ -82,6 +82,7 @@ int main(void) {
          offsetof(xpcs_stream_desc, n_roi), offsetof(xpcs_stream_desc, k), offsetof(xpcs_stream_desc, roi_label),
          offsetof(xpcs_stream_desc, basis), offsetof(xpcs_stream_desc, window), offsetof(xpcs_stream_desc, max_block));
   printf("%d %d %d %d %d %d\n", XPCS_U8, XPCS_U16, XPCS_F32, XPCS_F64, XPCS_ALL_ROIS, XPCS_PREC_BF16);
+  printf("%d %d %d %d\n", XPCS_EQUEUED, XPCS_STREAM_QUEUED, XPCS_STREAM_ADMITTED, XPCS_STREAM_FAILED);
   return 0;
 }
 """
@@ -104,6 +105,8 @@ int main(void) {
     assert [int(x) for x in lines[2].split()] == want_d
     assert [int(x) for x in lines[3].split()] == [_lib.XPCS_U8, _lib.XPCS_U16, _lib.XPCS_F32, _lib.XPCS_F64,
                                                    _lib.XPCS_ALL_ROIS, _lib.XPCS_PREC_BF16]
+    assert [int(x) for x in lines[4].split()] == [_lib.XPCS_EQUEUED, _lib.XPCS_STREAM_QUEUED,
+                                                   _lib.XPCS_STREAM_ADMITTED, _lib.XPCS_STREAM_FAILED]
 
 
 def test_null_context_is_rejected_without_a_gpu(lib):
@@ -120,6 +123,17 @@ def test_null_context_is_rejected_without_a_gpu(lib):
     assert lib.xpcs_stream_frames(None) == 0
     lib.xpcs_stream_close(None)
     lib.xpcs_destroy(None)
+    assert lib.xpcs_server_create(0, 0, 1, 1, None) == -1
+    assert lib.xpcs_server_open(None, None, None, None) == -1
+    assert lib.xpcs_server_state(None, 1, None) == -1
+    assert lib.xpcs_server_push(None, 1, None, 1, None, 10, None) == -1
+    assert lib.xpcs_server_poll(None, 1, 1, None, None, None) == -1
+    assert lib.xpcs_server_g2(None, 1, None, None) == -1
+    assert lib.xpcs_server_wait(None, 0) == -1
+    assert lib.xpcs_server_close(None, 1) == -1
+    assert lib.xpcs_server_stats(None, None, None, None) == -1
+    assert lib.xpcs_server_last_error(None) == b"NULL server"
+    lib.xpcs_server_destroy(None)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
