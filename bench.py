@@ -109,6 +109,97 @@ def stream_latency(api, torch, dev, n_blocks):
             "frames_pushed": int(n_blocks * nb), "g2_finite": ok}
 
 
+def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, seed=4000):
+    """Many online streams served at once (the serving workload): detectors drawn
+    from {256x256, 512x512, 1024x512} px, 8..36 annular ROIs, uint8 counts
+    (mean 0.05, beta 0.2, tau_c 50), k = 64 with each stream's basis compressed
+    from its first 4 blocks, a 4096-lag window, 256-frame blocks arriving every
+    256 / 52,000 s per stream with a random phase, stream starts as Poisson
+    arrivals, lifetimes of life_lo..life_hi blocks.  One run pushes the blocks back
+    to back (the rate the server sustains); the next pushes every block at its
+    arrival time (latency = push call to the end of the block's work, by device
+    events, plus how late the host issued the push)."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    shapes = [(256, 256), (512, 512), (1024, 512)]
+    nb, window, k, period = 256, 4096, 64, 256 / 52000.0
+    streams = []
+    ctx = api.Context(0)
+    for i in range(n_streams):
+        H, Wd = shapes[rng.integers(len(shapes))]
+        n_roi = int(rng.integers(8, 37))
+        M = H * Wd
+        labels = torch.from_numpy(synth.annular_labels(H, Wd, n_roi)).to(dev)
+        pool = synth.speckle_frames_torch(M, 4 * nb, 0.05, 0.2, 50.0, "u8", seed=seed + 1 + i, device=dev)
+        f = api.compress_frames(ctx, pool, labels, n_roi, k=k, seed=seed + 100 + i)
+        basis = f.U.contiguous()
+        band = torch.empty((n_roi, nb, window), dtype=torch.float32, device=dev)
+        streams.append(dict(M=M, shape=(H, Wd), n_roi=n_roi, labels=labels, pool=pool, basis=basis, band=band,
+                            life=int(rng.integers(life_lo, life_hi + 1))))
+    ctx.sync()
+    ctx.close()
+    torch.cuda.synchronize()
+    starts = np.cumsum(rng.exponential(2 * period, size=n_streams))
+    events = []
+    for i, st in enumerate(streams):
+        phase = rng.uniform(0, period)
+        for b in range(st["life"]):
+            events.append((starts[i] + phase + b * period, i, b))
+    events.sort()
+
+    def run(paced):
+        srv = api.Server(0, lanes=lanes, max_streams=n_streams)
+        ids, lat, lag, opens, arrival_to_done = {}, [], {}, [], []
+        seen = {i: 0 for i in range(n_streams)}
+
+        def collect(i):
+            for ms, _ in srv.poll(ids[i]):
+                lat.append(ms)
+                arrival_to_done.append(lag[(i, seen[i])] + ms)
+                seen[i] += 1
+
+        t0 = time.perf_counter()
+        for (ta, i, b) in events:
+            st = streams[i]
+            if paced:
+                while time.perf_counter() - t0 < ta:
+                    pass
+            if b == 0:
+                to = time.perf_counter()
+                ids[i], state = srv.open(st["labels"], st["n_roi"], st["basis"], window, nb)
+                opens.append((time.perf_counter() - to) * 1e3)
+            lag[(i, b)] = max(0.0, (time.perf_counter() - t0 - ta) * 1e3) if paced else 0.0
+            srv.push(ids[i], st["pool"][(b % 4) * nb:(b % 4 + 1) * nb], band=st["band"])
+            for j in ids:
+                collect(j)
+        srv.wait()
+        wall = time.perf_counter() - t0
+        for j in ids:
+            collect(j)
+        g2, _ = srv.g2(ids[0])
+        srv.wait()
+        ok = bool(torch.isfinite(g2[:, :nb]).all().item())
+        srv.destroy()
+        return lat, arrival_to_done, opens, wall, ok
+
+    run(False)                                   # loads every kernel; not timed
+    lat_b, _, _, wall_b, ok_b = run(False)
+    lat, a2d, opens, wall_p, ok_p = run(True)
+    total_frames = sum(st["life"] for st in streams) * nb
+    return {"workload": f"serve_{n_streams}streams_u8_k64_w4096_b256",
+            "streams": [{"px": f"{st['shape'][0]}x{st['shape'][1]}", "n_roi": st["n_roi"], "blocks": st["life"]}
+                        for st in streams],
+            "lanes": lanes, "blocks": len(events), "frames": total_frames,
+            "block_latency_p50_ms": percentile(lat, 50), "block_latency_p99_ms": percentile(lat, 99),
+            "arrival_to_done_p50_ms": percentile(a2d, 50), "arrival_to_done_p99_ms": percentile(a2d, 99),
+            "open_ms_p50": percentile(opens, 50), "open_ms_max": max(opens),
+            "paced_wall_s": wall_p, "arrival_frames_per_s": total_frames / (events[-1][0] + period),
+            "saturated_frames_per_s": total_frames / wall_b, "saturated_wall_s": wall_b,
+            "saturated_block_latency_p50_ms": percentile(lat_b, 50),
+            "g2_finite": ok_p and ok_b}
+
+
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summaries.
 
@@ -152,6 +243,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-stream", action="store_true", help="skip the online-stream latency measurement")
     ap.add_argument("--stream-blocks", type=int, default=40)
+    ap.add_argument("--no-serve", action="store_true", help="skip the many-stream serving measurement")
+    ap.add_argument("--serve-streams", type=int, default=16)
+    ap.add_argument("--serve-life", type=int, nargs=2, default=[16, 48], metavar=("LO", "HI"),
+                    help="stream lifetimes in blocks")
+    ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -308,6 +404,15 @@ def main():
         log("online stream: per-push latency at 1024 x 512 px, 36 ROIs, k = 64, window 4096")
         serving = stream_latency(api, torch, dev, args.stream_blocks)
         log(f"online stream: push p50 {serving['push_p50_ms']:.3f} ms, p99 {serving['push_p99_ms']:.3f} ms")
+    served = None
+    if not args.no_serve:
+        log(f"serving: {args.serve_streams} streams, lifetimes {args.serve_life} blocks, {args.serve_lanes} lanes")
+        served = serving_run(api, torch, dev, args.serve_streams, args.serve_life[0], args.serve_life[1],
+                             args.serve_lanes)
+        log(f"serving: block latency p50 {served['block_latency_p50_ms']:.3f} ms, "
+            f"p99 {served['block_latency_p99_ms']:.3f} ms; arrival to done p99 "
+            f"{served['arrival_to_done_p99_ms']:.3f} ms; open max {served['open_ms_max']:.1f} ms; "
+            f"saturated {served['saturated_frames_per_s']:.0f} frames/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -339,6 +444,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stream": serving,
+        "serving": served,
         "kernels": kernels,
         "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
         "parity": parity,
