@@ -89,17 +89,25 @@ __global__ __launch_bounds__(1024) void roi_order_kernel(const int32_t *__restri
 
 // Stable ROI order in three short passes over chunks of kOrderChunk pixels:
 // per-chunk ROI counts, their scan into per-chunk starting positions, and the
-// scatter.  One wave walks a chunk in pixel order; the pixels of a 64-pixel
-// step are grouped by label (ballot of the lanes that share the first unplaced
-// label, until none is left), so every ROI's pixels land in increasing pixel
-// order.  Running positions live in LDS and are only touched by the one wave.
-constexpr int kOrderChunk = 4096;
+// scatter.  One wave walks a chunk in pixel order, each lane holding the labels
+// of its pixels (loaded at once, so the walk waits for memory only once); the
+// pixels of a 64-pixel step are grouped by label (ballot of the lanes that share
+// the first unplaced label, until none is left), so every ROI's pixels land in
+// increasing pixel order.  Running positions live in LDS and are only touched by
+// the one wave.
+constexpr int kOrderSteps = 16;                      // 64-pixel steps per chunk
+constexpr int kOrderChunk = 64 * kOrderSteps;
 constexpr int kOrderMaxRoi = 8192;
 
-__device__ __forceinline__ int lane_label(const int32_t *__restrict__ labels, int64_t p, int64_t end, int n_roi) {
-    if (p >= end) return -1;
-    const int r = labels[p];
-    return (r >= 0 && r < n_roi) ? r : -1;
+__device__ __forceinline__ void chunk_labels(const int32_t *__restrict__ labels, int64_t c0, int64_t end, int n_roi,
+                                             int (&lab)[kOrderSteps]) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kOrderSteps; ++i) {
+        const int64_t p = c0 + 64 * i + lane;
+        const int r = p < end ? labels[p] : -1;
+        lab[i] = (r >= 0 && r < n_roi) ? r : -1;
+    }
 }
 
 __global__ __launch_bounds__(64) void roi_chunk_count_kernel(const int32_t *__restrict__ labels, int64_t M, int n_roi,
@@ -108,15 +116,17 @@ __global__ __launch_bounds__(64) void roi_chunk_count_kernel(const int32_t *__re
     const int lane = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * kOrderChunk;
     const int64_t end = c0 + kOrderChunk < M ? c0 + kOrderChunk : M;
+    int lab[kOrderSteps];
+    chunk_labels(labels, c0, end, n_roi, lab);
     for (int r = lane; r < n_roi; r += 64) cnt[r] = 0;
     __syncthreads();
-    for (int64_t p0 = c0; p0 < end; p0 += 64) {
-        const int lab = lane_label(labels, p0 + lane, end, n_roi);
-        unsigned long long left = __ballot(lab >= 0);
+#pragma unroll
+    for (int i = 0; i < kOrderSteps; ++i) {
+        unsigned long long left = __ballot(lab[i] >= 0);
         while (left) {
             const int leader = __ffsll((long long)left) - 1;
-            const int lr = __shfl(lab, leader);
-            const unsigned long long mk = __ballot(lab == lr);
+            const int lr = __shfl(lab[i], leader);
+            const unsigned long long mk = __ballot(lab[i] == lr);
             if (lane == leader) cnt[lr] += __popcll(mk);
             left &= ~mk;
         }
@@ -125,38 +135,56 @@ __global__ __launch_bounds__(64) void roi_chunk_count_kernel(const int32_t *__re
     for (int r = lane; r < n_roi; r += 64) counts[(int64_t)blockIdx.x * n_roi + r] = cnt[r];
 }
 
-// off[r] = start of ROI r (lengths padded to `pad`); counts[c][r] -> starting position
-// of chunk c's pixels of ROI r; the padding slots get perm = -1.
+// One block per ROI r: its start (the padded lengths of ROIs below it, summed),
+// then the exclusive scan of its per-chunk counts over the chunks, 256 at a
+// time, in place; the padding slots after its pixels get perm -1.
 __global__ __launch_bounds__(256) void roi_chunk_scan_kernel(int n_roi, int64_t nchunks,
                                                              const int64_t *__restrict__ roi_npix, int pad,
                                                              int64_t *__restrict__ counts, int64_t *off,
                                                              int32_t *perm, int32_t *qroi) {
-    for (int r0 = 0; r0 < n_roi; r0 += 256) {
-        // exclusive scan of the padded lengths, 256 ROIs at a time (one thread carries the base)
-        if (threadIdx.x == 0) {
-            int64_t s = r0 == 0 ? 0 : off[r0];
-            for (int r = r0; r < r0 + 256 && r < n_roi; ++r) {
-                off[r] = s;
-                s += (roi_npix[r] + pad - 1) / pad * pad;
-            }
-            off[r0 + 256 < n_roi ? r0 + 256 : n_roi] = s;
-        }
+    __shared__ int64_t wsum[4];
+    __shared__ int64_t carry;
+    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto padded = [&](int i) { return (roi_npix[i] + pad - 1) / pad * pad; };
+    auto block_sum = [&](int64_t v) {        // sum over the block, in a fixed order
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wsum[wv] = v;
         __syncthreads();
-        const int r = r0 + threadIdx.x;
-        if (r < n_roi) {
-            int64_t pos = off[r];
-            for (int64_t c = 0; c < nchunks; ++c) {
-                const int64_t n = counts[c * n_roi + r];
-                counts[c * n_roi + r] = pos;
-                pos += n;
-            }
-            const int64_t padded_end = off[r] + (roi_npix[r] + pad - 1) / pad * pad;
-            for (int64_t q = off[r] + roi_npix[r]; q < padded_end; ++q) {
-                perm[q] = -1;
-                qroi[q] = r;
-            }
-        }
+        const int64_t t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
+        return t;
+    };
+    int64_t below = 0;
+    for (int i = tid; i < r; i += 256) below += padded(i);
+    const int64_t start = block_sum(below);
+    if (tid == 0) {
+        off[r] = start;
+        if (r == n_roi - 1) off[n_roi] = start + padded(r);
+        carry = start;
+    }
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nchunks; c0 += 256) {
+        const int64_t c = c0 + tid;
+        const int64_t n = c < nchunks ? counts[c * n_roi + r] : 0;
+        // inclusive scan of n over the block: within waves, then the wave totals
+        int64_t x = n;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t before = carry;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        const int64_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (c < nchunks) counts[c * n_roi + r] = before + x - n;
+        __syncthreads();
+        if (tid == 0) carry += total;
+        __syncthreads();
+    }
+    for (int64_t q = start + roi_npix[r] + tid; q < start + padded(r); q += 256) {
+        perm[q] = -1;
+        qroi[q] = r;
     }
 }
 
@@ -167,20 +195,23 @@ __global__ __launch_bounds__(64) void roi_chunk_scatter_kernel(const int32_t *__
     const int lane = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * kOrderChunk;
     const int64_t end = c0 + kOrderChunk < M ? c0 + kOrderChunk : M;
+    int lab[kOrderSteps];
+    chunk_labels(labels, c0, end, n_roi, lab);
     for (int r = lane; r < n_roi; r += 64) pos[r] = starts[(int64_t)blockIdx.x * n_roi + r];
     __syncthreads();
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int64_t p0 = c0; p0 < end; p0 += 64) {
-        const int lab = lane_label(labels, p0 + lane, end, n_roi);
-        unsigned long long left = __ballot(lab >= 0);
+#pragma unroll
+    for (int i = 0; i < kOrderSteps; ++i) {
+        const int64_t p = c0 + 64 * i + lane;
+        unsigned long long left = __ballot(lab[i] >= 0);
         while (left) {
             const int leader = __ffsll((long long)left) - 1;
-            const int lr = __shfl(lab, leader);
-            const unsigned long long mk = __ballot(lab == lr);
+            const int lr = __shfl(lab[i], leader);
+            const unsigned long long mk = __ballot(lab[i] == lr);
             const int64_t b = pos[lr];
-            if (lab == lr) {
+            if (lab[i] == lr) {
                 const int64_t q = b + __popcll(mk & below);
-                perm[q] = (int32_t)(p0 + lane);
+                perm[q] = (int32_t)p;
                 qroi[q] = lr;
             }
             if (lane == leader) pos[lr] = b + __popcll(mk);
@@ -309,8 +340,8 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
     hipLaunchKernelGGL(roi_chunk_count_kernel, dim3((unsigned)nchunks), dim3(64), lds, ctx->stream, labels, M, n_roi,
                        counts);
     XPCS_LAUNCH_CHECK(ctx, "roi_chunk_count");
-    hipLaunchKernelGGL(roi_chunk_scan_kernel, dim3(1), dim3(256), 0, ctx->stream, n_roi, nchunks, roi_npix, pad,
-                       counts, off, perm, qroi);
+    hipLaunchKernelGGL(roi_chunk_scan_kernel, dim3((unsigned)n_roi), dim3(256), 0, ctx->stream, n_roi, nchunks,
+                       roi_npix, pad, counts, off, perm, qroi);
     XPCS_LAUNCH_CHECK(ctx, "roi_chunk_scan");
     hipLaunchKernelGGL(roi_chunk_scatter_kernel, dim3((unsigned)nchunks), dim3(64), lds, ctx->stream, labels, M,
                        n_roi, counts, perm, qroi);
