@@ -177,6 +177,91 @@ __global__ __launch_bounds__(256 * GramShape<BPT>::kGroups) void tsgram_kernel(c
     }
 }
 
+// Unsegmented Gram on FP64 MFMA (v_mfma_f64_16x16x4f64), up to 16 * NCB <= 80 columns:
+// every 16 x 16 tile (I <= J) of a wave's Gram stays in registers.  In step j of a
+// 16-row group, lane l supplies column 16 cb + l % 16 at row r0 + 4 (l / 16) + j,
+// which serves as the A operand (tile rows) and as the B operand (tile columns)
+// alike.  Entry (i, j) of a tile is lane l's value v with i = l / 16 + 4 v,
+// j = l % 16.  Waves take every eighth 16-row group of the block's range, load
+// the next group while multiplying the current one, and add their tiles in LDS in
+// wave order; the block writes its partial (upper tiles) for the fixed-order reduce.
+// Eight waves per block, two per SIMD, so that one's loads overlap the other's MFMAs.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kGramMfmaThreads = 512;     // 8 waves: two per SIMD
+constexpr int kGramMfmaWaves = kGramMfmaThreads / 64;
+template <typename TA, int NCB>
+__global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda,
+                                                          int ncols, int pw, double *__restrict__ part) {
+    constexpr int NT = NCB * (NCB + 1) / 2;
+    constexpr int W = NCB * 16;
+    __shared__ double red[W * W];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cl = lane & 15, kq = lane >> 4;
+    const int64_t ngroups = (rows + 15) / 16;
+    const int64_t per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per_blk;
+    const int64_t g1 = g0 + per_blk < ngroups ? g0 + per_blk : ngroups;
+    f64x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int64_t g, TA (&x)[NCB][4]) {
+        const int64_t r = g * 16 + 4 * kq;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int c = 16 * cb + cl;
+            const TA *src = A + (int64_t)(c < ncols ? c : 0) * lda + r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[cb][j] = (c < ncols && r + j < rows) ? src[j] : (TA)0;
+        }
+    };
+    TA cur[NCB][4], nxt[NCB][4];
+    int64_t g = g0 + wv;
+    if (g < g1) load(g, nxt);
+    for (; g < g1; g += kGramMfmaWaves) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[cb][j] = nxt[cb][j];
+        if (g + kGramMfmaWaves < g1) load(g + kGramMfmaWaves, nxt);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double f[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) f[cb] = (double)cur[cb][j];
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NCB; ++I)
+#pragma unroll
+                for (int J = I; J < NCB; ++J) {
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[I], f[J], acc[t], 0, 0, 0);
+                    ++t;
+                }
+        }
+    }
+    for (int w = 0; w < kGramMfmaWaves; ++w) {
+        if (wv == w) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NCB; ++I)
+#pragma unroll
+                for (int J = I; J < NCB; ++J) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int idx = (16 * I + kq + 4 * v) * W + 16 * J + cl;
+                        red[idx] = (w == 0 ? 0.0 : red[idx]) + acc[t][v];
+                    }
+                    ++t;
+                }
+        }
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.x * pw * pw;
+    for (int idx = threadIdx.x; idx < pw * pw; idx += kGramMfmaThreads) {
+        const int a = idx / pw, b = idx % pw;
+        if (a / 16 <= b / 16) out[idx] = red[a * W + b];
+    }
+}
+
 // G[seg][a][b] = sum over parts of part[.][ra][rb], (ra, rb) the copy in an upper block.
 // 8 threads per entry sum interleaved parts; the 8 sums are added in a fixed order.
 __global__ __launch_bounds__(256) void tsgram_reduce_kernel(const double *__restrict__ part, int nparts, int ncols,
@@ -204,6 +289,19 @@ __global__ __launch_bounds__(256) void tsgram_reduce_kernel(const double *__rest
         for (int q = 0; q < 8; ++q) t += red[threadIdx.x + q];
         G[(int64_t)seg * n2 + idx] = t;
     }
+}
+
+// Reciprocal and inverse square root refined from the hardware estimates by two
+// Newton steps (quadratic convergence from the estimate's ~2^-22 to full FP64).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
 // ---------------------------------------------------------------- Cholesky + inverse
@@ -307,6 +405,126 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict_
     }
 }
 
+// The same for n <= kInvLds with the matrix in registers: thread t owns the lower
+// elements t, t + 1024, ... in column-major order.  Right-looking Cholesky, one
+// barrier per column:
+// in step j every thread updates its trailing elements from column j (unscaled,
+// L[r][c] -= L[r][j] L[c][j] / d_j), read from a column buffer that the owners of
+// column j wrote at the end of step j - 1, and the owners of column j + 1 write
+// theirs into the other buffer.  The inverse of L runs the same way on [L | I] by
+// rows: in step j the rows below take row j (final after step j - 1) times
+// L[i][j] / L[j][j] off, and the owners of row j + 1 publish it.
+constexpr int kRegEl = (kPackedInv + 1023) / 1024;
+__global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restrict__ G, int n, double rel_tol,
+                                                           double *__restrict__ Rinv, int *flags) {
+    __shared__ double Lu[kPackedInv];                  // final L, then its columns divided by the diagonal
+    __shared__ double buf[2][kInvLds];
+    __shared__ double piv[kInvLds];
+    __shared__ double s_max;
+    const int tid = threadIdx.x, npk = n * (n + 1) / 2;
+    int er[kRegEl], ec[kRegEl];
+    double v[kRegEl];
+#pragma unroll
+    for (int u = 0; u < kRegEl; ++u) {
+        const int e = tid + 1024 * u;
+        er[u] = -1;
+        ec[u] = 0;
+        v[u] = 0.0;
+        if (e < npk) {
+            // column-major over the lower triangle (column c holds rows c..n-1), so that the
+            // elements still active in a step sit in whole waves
+            int c = 0, off = 0;
+            while (off + (n - c) <= e) {
+                off += n - c;
+                ++c;
+            }
+            er[u] = c + (e - off);
+            ec[u] = c;
+            v[u] = G[(int64_t)er[u] * n + c];
+            if (c == 0) buf[0][er[u]] = v[u];
+        }
+    }
+    if (tid < 64) {
+        double m = 0.0;
+        for (int i = tid; i < n; i += 64) m = fmax(m, G[(int64_t)i * n + i]);
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+        if (tid == 0) s_max = m;
+    }
+    __syncthreads();
+    const double thresh = rel_tol * s_max;
+    for (int j = 0; j < n; ++j) {
+        const double *col = buf[j & 1];
+        double *nxt = buf[(j + 1) & 1];
+        const double d = col[j];
+        const bool keep = d > thresh && d > 0.0;
+        const double rd = keep ? rcp_nr(d) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kRegEl; ++u) {
+            const int r = er[u], c = ec[u];
+            if (c > j) {
+                if (keep) v[u] -= col[r] * col[c] * rd;
+                if (c == j + 1) nxt[r] = v[u];
+            }
+        }
+        if (tid == 0) piv[j] = keep ? sqrt(d) : 0.0;
+        __syncthreads();
+    }
+    // scaled factor into LDS: L[r][c] = v / piv_c below the diagonal, piv_c on it
+#pragma unroll
+    for (int u = 0; u < kRegEl; ++u) {
+        const int r = er[u], c = ec[u];
+        if (r < 0) continue;
+        const double pc = piv[c];
+        Lu[r * (r + 1) / 2 + c] = r == c ? pc : (pc > 0.0 ? v[u] / pc : 0.0);
+    }
+    if (tid == 0) {
+        bool any = false;
+        for (int j = 0; j < n; ++j) any |= piv[j] > 0.0;
+        if (!any) atomicOr(&flags[kFlagNumeric], 1);
+    }
+    __syncthreads();
+    // L[i][j] / L[j][j] below the diagonal (0 for a dropped column)
+#pragma unroll
+    for (int u = 0; u < kRegEl; ++u) {
+        const int r = er[u], c = ec[u];
+        if (r < 0 || r == c) continue;
+        const double pc = piv[c];
+        Lu[r * (r + 1) / 2 + c] = pc > 0.0 ? Lu[r * (r + 1) / 2 + c] / pc : 0.0;
+    }
+    // [L | I] by rows: v now holds L^{-1} (rows unscaled), starting from I
+#pragma unroll
+    for (int u = 0; u < kRegEl; ++u) {
+        v[u] = er[u] >= 0 && er[u] == ec[u] ? 1.0 : 0.0;
+        if (er[u] == 0) buf[0][0] = 1.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double *row = buf[j & 1];
+        double *nxt = buf[(j + 1) & 1];
+#pragma unroll
+        for (int u = 0; u < kRegEl; ++u) {
+            const int i = er[u], c = ec[u];
+            if (i > j) {
+                if (c <= j) v[u] -= Lu[i * (i + 1) / 2 + j] * row[c];
+                if (i == j + 1) nxt[c] = v[u];
+            }
+        }
+        __syncthreads();
+    }
+    // Rinv (column-major) = Linv^T, rows of Linv scaled by 1 / L[i][i]
+#pragma unroll
+    for (int u = 0; u < kRegEl; ++u) {
+        const int i = er[u], c = ec[u];
+        if (i < 0) continue;
+        const double lii = piv[i];
+        Rinv[(int64_t)i * n + c] = lii != 0.0 ? v[u] / lii : 0.0;
+    }
+    for (int e = tid; e < n * n; e += 1024) {
+        const int i = e / n, c = e % n;
+        if (c > i) Rinv[e] = 0.0;
+    }
+}
+
 // Batched Cholesky factor: one block per matrix G[bch] (n x n, symmetric PSD),
 // L[bch] row-major lower triangular (upper part zero), pivots below
 // rel_tol * max(diag) dropped (their column of L is zero).
@@ -351,6 +569,7 @@ __global__ __launch_bounds__(256) void small_matmul_kernel(const double *__restr
 // operands are loaded while the current one is multiplied.
 constexpr int kTsRows = 2;
 constexpr int kTsCols = 16;
+constexpr int kTsAhead = 8;
 
 template <typename TA>
 __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda, int n,
@@ -382,24 +601,37 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
         for (int q = 0; q < kTsRows; ++q)
 #pragma unroll
             for (int jj = 0; jj < kTsCols; ++jj) acc[q][jj] = 0.0;
-        double an[kTsRows];
+        // A is read kTsAhead columns ahead of its use (the loads of the next group are
+        // in flight while the current one is multiplied)
+        TA an[kTsAhead][kTsRows];
 #pragma unroll
-        for (int q = 0; q < kTsRows; ++q) an[q] = n > 0 ? (double)A[rr[q]] : 0.0;
-        for (int i = 0; i < n; ++i) {
-            double a[kTsRows];
+        for (int u = 0; u < kTsAhead; ++u)
 #pragma unroll
-            for (int q = 0; q < kTsRows; ++q) a[q] = an[q];
-            if (i + 1 < n) {
+            for (int q = 0; q < kTsRows; ++q) an[u][q] = u < n ? A[(int64_t)u * lda + rr[q]] : (TA)0;
+        for (int i0 = 0; i0 < n; i0 += kTsAhead) {
+            TA a[kTsAhead][kTsRows];
 #pragma unroll
-                for (int q = 0; q < kTsRows; ++q) an[q] = (double)A[(int64_t)(i + 1) * lda + rr[q]];
+            for (int u = 0; u < kTsAhead; ++u)
+#pragma unroll
+                for (int q = 0; q < kTsRows; ++q) a[u][q] = an[u][q];
+#pragma unroll
+            for (int u = 0; u < kTsAhead; ++u) {
+                const int i = i0 + kTsAhead + u;
+#pragma unroll
+                for (int q = 0; q < kTsRows; ++q) an[u][q] = i < n ? A[(int64_t)i * lda + rr[q]] : (TA)0;
             }
 #pragma unroll
-            for (int jj = 0; jj < kTsCols; jj += 2) {
-                const double2 t = *reinterpret_cast<const double2 *>(&Ts[i * kTsCols + jj]);
+            for (int u = 0; u < kTsAhead; ++u) {
+                const int i = i0 + u;
+                if (i >= n) break;
 #pragma unroll
-                for (int q = 0; q < kTsRows; ++q) {
-                    acc[q][jj] = fma(a[q], t.x, acc[q][jj]);
-                    acc[q][jj + 1] = fma(a[q], t.y, acc[q][jj + 1]);
+                for (int jj = 0; jj < kTsCols; jj += 2) {
+                    const double2 t = *reinterpret_cast<const double2 *>(&Ts[i * kTsCols + jj]);
+#pragma unroll
+                    for (int q = 0; q < kTsRows; ++q) {
+                        acc[q][jj] = fma((double)a[u][q], t.x, acc[q][jj]);
+                        acc[q][jj + 1] = fma((double)a[u][q], t.y, acc[q][jj + 1]);
+                    }
                 }
             }
         }
@@ -467,19 +699,6 @@ __device__ __forceinline__ int pidx_sym(int i, int j) { return i <= j ? pidx_upp
 constexpr int kMaxSweeps = 30;
 constexpr int kJacobiThreads = 1024;
 constexpr int kMaxItems = (kMaxSmall / 2) * (kMaxSmall / 2 + 1) / 2;
-
-// Reciprocal and inverse square root refined from the hardware estimates by two
-// Newton steps (quadratic convergence from the estimate's ~2^-22 to full FP64).
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
-}
 
 // (a, b), a <= b < h, from the row-major linear index of the upper triangle of an h x h grid
 __device__ __forceinline__ void tri_pair(int idx, int h, int &a, int &b) {
@@ -1104,8 +1323,8 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     const int pw = nc4 * 4;
     const int nblk = nc4 * (nc4 + 1) / 2;
     const int bpt = (nblk + 255) / 256;
-    // about 1024 rows per block, at most 256 blocks; segmented Grams split the blocks
-    int nparts = (int)((rows + 1023) / 1024);
+    // up to 256 blocks (one per CU) of at least 64 rows; segmented Grams split the blocks
+    int nparts = (int)(rows / 64);
     if (nparts > 256) nparts = 256;
     if (seg_off) nparts = (int)(256 / (nseg > 0 ? nseg : 1)) + 1;
     if (nparts < 1) nparts = 1;
@@ -1119,6 +1338,33 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     const size_t lds_sums = (size_t)nblk * 16 * sizeof(double);     // one 4x4 block per owned block id
     const size_t lds = lds_tile > lds_sums ? lds_tile : lds_sums;
     dim3 grid(nparts, nseg);
+    // without segments and up to 80 columns: the FP64 MFMA kernel
+    if (!seg_off && !row_idx && nseg == 1 && ncols <= 80) {
+        const int ncb = (ncols + 15) / 16;
+#define XPCS_TSGM(T, C)                                                                                       \
+    hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts), dim3(kGramMfmaThreads), 0, ctx->stream,         \
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part)
+#define XPCS_TSGM_T(T)                \
+    switch (ncb) {                    \
+        case 1: XPCS_TSGM(T, 1); break; \
+        case 2: XPCS_TSGM(T, 2); break; \
+        case 3: XPCS_TSGM(T, 3); break; \
+        case 4: XPCS_TSGM(T, 4); break; \
+        default: XPCS_TSGM(T, 5); break; \
+    }
+        if (a_f64) {
+            XPCS_TSGM_T(double)
+        } else {
+            XPCS_TSGM_T(float)
+        }
+#undef XPCS_TSGM_T
+#undef XPCS_TSGM
+        XPCS_LAUNCH_CHECK(ctx, "tsgram_mfma");
+        hipLaunchKernelGGL(tsgram_reduce_kernel, dim3((ncols * ncols + 31) / 32, nseg), dim3(256), 0, ctx->stream,
+                           part, nparts, ncols, pw, G);
+        XPCS_LAUNCH_CHECK(ctx, "tsgram_reduce");
+        return XPCS_OK;
+    }
 #define XPCS_TSG(T, B)                                                                                          \
     hipLaunchKernelGGL((tsgram_kernel<T, B>), grid, dim3(gthreads), lds, ctx->stream,                            \
                        static_cast<const T *>(A), rows, lda, ncols, row_idx, seg_off, part)
@@ -1155,7 +1401,7 @@ xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol
         if (!dst) return st;
     }
     if (n <= kInvLds)
-        hipLaunchKernelGGL(cholinv_kernel<true>, dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst, ctx->flags);
+        hipLaunchKernelGGL(cholinv_reg_kernel, dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst, ctx->flags);
     else
         hipLaunchKernelGGL(cholinv_kernel<false>, dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst, ctx->flags);
     XPCS_LAUNCH_CHECK(ctx, "cholinv");
