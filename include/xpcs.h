@@ -60,6 +60,7 @@ typedef int32_t xpcs_status;
 #define XPCS_F64 11
 /* arithmetic of the compression products (FP32 accumulation in every case) */
 #define XPCS_PREC_BF16 0
+#define XPCS_PREC_FP8 1
 
 /* `roi` argument selecting every ROI in one call */
 #define XPCS_ALL_ROIS (-1)
@@ -129,7 +130,14 @@ typedef struct {
  *   k            rank kept (the paper's K, Eq. 6), 1 <= k.
  *   oversample   extra sketch columns p (sketch width l = k + p); 16 by default.
  *   power_iters  subspace iterations q (0 or 1).
- *   precision    XPCS_PREC_BF16.
+ *   precision    XPCS_PREC_BF16, or XPCS_PREC_FP8 (offline mode, XPCS_U8 frames
+ *                only): the subspace passes that choose the basis (the sketch
+ *                X Omega and, with q = 1, X^T Q and X Z) take e4m3 operands -- the
+ *                counts as two exact nibble planes, the +-1 sketch exactly, the
+ *                intermediate bases rounded to e4m3 -- on the fp8 MFMA; the
+ *                encoding pass keeps the split-bf16 basis either way.  With q = 0
+ *                both precisions give the same factors (every rounded operand is
+ *                exact).  XPCS_PREC_FP8 with XPCS_U16 frames: EUNSUPPORTED.
  *   seed         seed of the Rademacher sketch Omega[t][j] = +-1, sign = top bit of
  *                SplitMix64(seed XOR (t*2^32 + j)).
  *   basis        NULL: offline mode, the basis is computed from these frames

@@ -32,6 +32,7 @@ XPCS_U16 = 2
 XPCS_F32 = 10
 XPCS_F64 = 11
 XPCS_PREC_BF16 = 0
+XPCS_PREC_FP8 = 1
 XPCS_ALL_ROIS = -1
 
 

@@ -138,8 +138,10 @@ class Factors:
 
 def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int, k: int,
                     oversample: int = 16, power_iters: int = 1, seed: int = 0,
-                    basis: Optional[torch.Tensor] = None, out: Optional[Factors] = None) -> Factors:
-    """frames: (N, M) uint8/uint16 device tensor; roi_label: (M,) int32; basis: optional (k, M) float32."""
+                    basis: Optional[torch.Tensor] = None, out: Optional[Factors] = None,
+                    precision: str = "bf16") -> Factors:
+    """frames: (N, M) uint8/uint16 device tensor; roi_label: (M,) int32; basis: optional (k, M) float32;
+    precision: "bf16" or "fp8" (the subspace passes on e4m3 operands, uint8 frames)."""
     _check_device(frames, "frames", ctx.device)
     _check_device(roi_label, "roi_label", ctx.device)
     if roi_label.dtype != torch.int32:
@@ -150,7 +152,8 @@ def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor,
         if basis.dtype != torch.float32 or tuple(basis.shape) != (k, M):
             raise ValueError("basis must be a (k, M) float32 tensor")
     f = out if out is not None else Factors.empty(M, N, k, n_roi, ctx.device)
-    opts = L.XpcsCompressOpts(k, oversample, power_iters, L.XPCS_PREC_BF16, seed & (2 ** 64 - 1),
+    prec = {"bf16": L.XPCS_PREC_BF16, "fp8": L.XPCS_PREC_FP8}[precision]
+    opts = L.XpcsCompressOpts(k, oversample, power_iters, prec, seed & (2 ** 64 - 1),
                               basis.data_ptr() if basis is not None else None)
     fs = f.struct()
     ctx.bind_stream()

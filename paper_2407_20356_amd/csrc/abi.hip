@@ -93,7 +93,11 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
         return fail(ctx, XPCS_EINVAL, "factor sizes (M, N, k, n_roi) do not match the call");
     const int k = opts->k;
     if (k < 1) return fail(ctx, XPCS_EINVAL, "k must be >= 1");
-    if (opts->precision != XPCS_PREC_BF16) return fail(ctx, XPCS_EUNSUPPORTED, "only XPCS_PREC_BF16 is built");
+    if (opts->precision != XPCS_PREC_BF16 && opts->precision != XPCS_PREC_FP8)
+        return fail(ctx, XPCS_EINVAL, "precision must be XPCS_PREC_BF16 or XPCS_PREC_FP8");
+    // fp8 subspace passes: counts below 256 split into two exact e4m3 nibble planes
+    const bool fp8 = opts->precision == XPCS_PREC_FP8 && !opts->basis;
+    if (fp8 && dtype != XPCS_U8) return fail(ctx, XPCS_EUNSUPPORTED, "XPCS_PREC_FP8 takes XPCS_U8 frames");
     if (n_roi > 64) return fail(ctx, XPCS_EUNSUPPORTED, "compress_frames records at most 64 ROI sums");
     const bool online = opts->basis != nullptr;
     int ell = k + (opts->oversample > 0 ? opts->oversample : 0);
@@ -167,9 +171,33 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
         if ((st = launch_tsmul(ctx, Za, true, N, N, k, Tid, k, scale, ov))) return st;
     } else {
         // 1. sketch Y0 = X Omega (exact: +-1 entries, integer counts)
-        if ((st = launch_sketch_omega(ctx, opts->seed, N, L, ell, ldt, om))) return st;
-        if ((st = launch_proj_pixels(ctx, frames, dtype, M, N, om, ldt, L, Ya))) return st;
-        if (opts->power_iters == 1) {
+        uint8_t *om8 = reinterpret_cast<uint8_t *>(om), *q8 = reinterpret_cast<uint8_t *>(qlo);
+        const uint8_t *f8frames = static_cast<const uint8_t *>(frames);
+        if (fp8) {
+            if ((st = launch_sketch_omega_f8(ctx, opts->seed, N, L, ell, ldt, om8))) return st;
+            if ((st = launch_proj_pixels_f8(ctx, f8frames, M, N, om8, ldt, L, Ya))) return st;
+        } else {
+            if ((st = launch_sketch_omega(ctx, opts->seed, N, L, ell, ldt, om))) return st;
+            if ((st = launch_proj_pixels(ctx, frames, dtype, M, N, om, ldt, L, Ya))) return st;
+        }
+        if (opts->power_iters == 1 && fp8) {
+            // 2. the same with e4m3 operands: Q0 = orth(Y0), Z = X^T Q0, Qz = orth(Z), Y1 = X Qz
+            TsOut o;
+            o.f8 = q8;
+            o.ldh = ldq;
+            o.Lpad = L;
+            o.rows_pad = ldq;
+            if ((st = Orth::run(ctx, Ya, false, M, M, ell, Yb, false, G, R1, R2, o, 1))) return st;
+            if ((st = launch_proj_frames_f8(ctx, f8frames, M, N, q8, ldq, L, plan_q, part))) return st;
+            if ((st = launch_proj_frames_reduce(ctx, part, plan_q, N, L, 0, Za, N, nullptr))) return st;
+            TsOut oz;
+            oz.f8 = om8;                                // reuse the sketch buffer for Qz
+            oz.ldh = ldt;
+            oz.Lpad = L;
+            oz.rows_pad = ldt;
+            if ((st = Orth::run(ctx, Za, true, N, N, ell, Zb, true, G, R1, R2, oz, 1))) return st;
+            if ((st = launch_proj_pixels_f8(ctx, f8frames, M, N, om8, ldt, L, Ya))) return st;
+        } else if (opts->power_iters == 1) {
             // 2. Q0 = orth(Y0) as bf16; Z = X^T Q0; Qz = orth(Z) as bf16; Y1 = X Qz
             TsOut o;
             o.hi = qhi;

@@ -191,6 +191,16 @@ struct FrameProj {
 };
 // Plan for a pass with (lo = true) or without the residual term of Q.
 FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo);
+// FP8 (e4m3) versions of the subspace passes for u8 counts (proj_f8.hip): the
+// same +-1 sketch in e4m3, the pixel-space product with an e4m3 B (rows of stride
+// ldb) and the frame-space power pass with an e4m3 Q (no residual term, no
+// indicator columns; `plan` from plan_proj_frames(M, N, L, 0, false)).
+xpcs_status launch_sketch_omega_f8(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell, int64_t ldt,
+                                   uint8_t *om);
+xpcs_status launch_proj_pixels_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t M, int64_t N, const uint8_t *B,
+                                  int64_t ldb, int L, float *Y);
+xpcs_status launch_proj_frames_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t M, int64_t N, const uint8_t *q8,
+                                  int64_t ldq, int L, const FrameProj &plan, float *part);
 xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
                                const unsigned short *q_hi, const unsigned short *q_lo, int64_t ldq,
                                int L, const int32_t *labels, int n_ind, const FrameProj &plan,
@@ -224,6 +234,7 @@ struct TsOut {
     float *out32 = nullptr; int64_t ld32 = 0;
     double *out64 = nullptr; int64_t ld64 = 0;
     unsigned short *hi = nullptr; unsigned short *lo = nullptr; int64_t ldh = 0;
+    uint8_t *f8 = nullptr;      // e4m3 rows of 256 x value (stride ldh, padded as hi)
     int Lpad = 0; int64_t rows_pad = 0;
 };
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,

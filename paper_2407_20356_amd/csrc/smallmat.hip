@@ -576,7 +576,8 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
                                                     const double *__restrict__ T, int m,
                                                     const double *__restrict__ colscale, float *out32,
                                                     int64_t ld32, double *out64, int64_t ld64, unsigned short *hi,
-                                                    unsigned short *lo, int64_t ldh, int Lpad, int64_t rows_pad) {
+                                                    unsigned short *lo, uint8_t *f8, int64_t ldh, int Lpad,
+                                                    int64_t rows_pad) {
     __shared__ double Ts[kMaxSmall * kTsCols];        // T[i][j0 + jj] at i * kTsCols + jj
     const int j0 = blockIdx.y * kTsCols;
     const int64_t base = (int64_t)blockIdx.x * (256 * kTsRows) + threadIdx.x;
@@ -652,20 +653,24 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
                         hi[(int64_t)j * ldh + row] = h;
                         if (lo) lo[(int64_t)j * ldh + row] = f32_to_bf16_bits((float)(v - (double)bf16_bits_to_f32(h)));
                     }
+                    if (f8)
+                        f8[(int64_t)j * ldh + row] =
+                            (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32((float)v * 256.f, 0.f, 0, false) & 0xff);
                 }
             }
         }
     }
     // zero padding of the bf16 rows (column group 0 only): columns [m, Lpad) of live
     // rows, all columns of pad rows
-    if (hi && blockIdx.y == 0) {
+    if ((hi || f8) && blockIdx.y == 0) {
 #pragma unroll
         for (int q = 0; q < kTsRows; ++q) {
             const int64_t row = base + 256 * q;
             if (row >= rows_pad) continue;
             for (int j = row < rows ? m : 0; j < Lpad; ++j) {
-                hi[(int64_t)j * ldh + row] = 0;
+                if (hi) hi[(int64_t)j * ldh + row] = 0;
                 if (lo) lo[(int64_t)j * ldh + row] = 0;
+                if (f8) f8[(int64_t)j * ldh + row] = 0;
             }
         }
     }
@@ -1424,16 +1429,16 @@ xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows,
                          const double *T, int m, const double *colscale, const TsOut &out) {
     Phase phase_(ctx, "tsmul");
     if (n > kMaxSmall || m > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "tall x small product wider than 192");
-    const int64_t span = out.hi && out.rows_pad > rows ? out.rows_pad : rows;
+    const int64_t span = (out.hi || out.f8) && out.rows_pad > rows ? out.rows_pad : rows;
     dim3 grid((unsigned)((span + 256 * kTsRows - 1) / (256 * kTsRows)), (unsigned)((m + kTsCols - 1) / kTsCols));
     if (a_f64)
         hipLaunchKernelGGL(tsmul_kernel<double>, grid, dim3(256), 0, ctx->stream, static_cast<const double *>(A), rows,
-                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
-                           out.Lpad, out.rows_pad);
+                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.f8,
+                           out.ldh, out.Lpad, out.rows_pad);
     else
         hipLaunchKernelGGL(tsmul_kernel<float>, grid, dim3(256), 0, ctx->stream, static_cast<const float *>(A), rows,
-                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.ldh,
-                           out.Lpad, out.rows_pad);
+                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.f8,
+                           out.ldh, out.Lpad, out.rows_pad);
     XPCS_LAUNCH_CHECK(ctx, "tsmul");
     return XPCS_OK;
 }

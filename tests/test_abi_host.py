@@ -82,7 +82,8 @@ int main(void) {
          offsetof(xpcs_stream_desc, n_roi), offsetof(xpcs_stream_desc, k), offsetof(xpcs_stream_desc, roi_label),
          offsetof(xpcs_stream_desc, basis), offsetof(xpcs_stream_desc, window), offsetof(xpcs_stream_desc, max_block));
   printf("%d %d %d %d %d %d\n", XPCS_U8, XPCS_U16, XPCS_F32, XPCS_F64, XPCS_ALL_ROIS, XPCS_PREC_BF16);
-  printf("%d %d %d %d\n", XPCS_EQUEUED, XPCS_STREAM_QUEUED, XPCS_STREAM_ADMITTED, XPCS_STREAM_FAILED);
+  printf("%d %d %d %d %d\n", XPCS_EQUEUED, XPCS_STREAM_QUEUED, XPCS_STREAM_ADMITTED, XPCS_STREAM_FAILED,
+         XPCS_PREC_FP8);
   return 0;
 }
 """
@@ -106,7 +107,8 @@ int main(void) {
     assert [int(x) for x in lines[3].split()] == [_lib.XPCS_U8, _lib.XPCS_U16, _lib.XPCS_F32, _lib.XPCS_F64,
                                                    _lib.XPCS_ALL_ROIS, _lib.XPCS_PREC_BF16]
     assert [int(x) for x in lines[4].split()] == [_lib.XPCS_EQUEUED, _lib.XPCS_STREAM_QUEUED,
-                                                   _lib.XPCS_STREAM_ADMITTED, _lib.XPCS_STREAM_FAILED]
+                                                   _lib.XPCS_STREAM_ADMITTED, _lib.XPCS_STREAM_FAILED,
+                                                   _lib.XPCS_PREC_FP8]
 
 
 def test_null_context_is_rejected_without_a_gpu(lib):
