@@ -342,71 +342,8 @@ __device__ __forceinline__ void chol_packed_lds(double *L, double *piv, int n, d
     __syncthreads();
 }
 
-template <bool LDS_INV>
-__global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict__ G, int n, double rel_tol,
-                                                       double *__restrict__ Rinv, int *flags) {
-    __shared__ double L[LDS_INV ? kPackedInv : kPacked];
-    __shared__ double Li[LDS_INV ? kPackedInv : 1];
-    __shared__ double piv[kMaxSmall];
-    __shared__ double s_max;
-    const int tid = threadIdx.x;
-    const int ty = tid >> 5, tx = tid & 31;
-    for (int i = ty; i < n; i += 32)
-        for (int j = tx; j <= i; j += 32) L[pidx_lower(i, j)] = G[(int64_t)i * n + j];
-    if (tid == 0) {
-        double m = 0.0;
-        for (int i = 0; i < n; ++i) m = fmax(m, G[(int64_t)i * n + i]);
-        s_max = m;
-    }
-    __syncthreads();
-    chol_packed_lds(L, piv, n, rel_tol * s_max);
-    if (tid == 0) {
-        bool any = false;
-        for (int j = 0; j < n; ++j) any |= piv[j] > 0.0;
-        if (!any) atomicOr(&flags[kFlagNumeric], 1);
-    }
-    if constexpr (LDS_INV) {
-        // L^{-1} by right-looking elimination on [L | I], one barrier per column: row j
-        // is read scaled on the fly (by 1 / L[j][j]) while it updates the rows below,
-        // and scaled in place at the end.
-        for (int i = ty; i < n; i += 32)
-            for (int c = tx; c <= i; c += 32) Li[pidx_lower(i, c)] = (i == c) ? 1.0 : 0.0;
-        __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            const double ljj = L[pidx_lower(j, j)];
-            const double rj = ljj != 0.0 ? 1.0 / ljj : 0.0;
-            for (int i = j + 1 + ty; i < n; i += 32) {
-                const double lij = L[pidx_lower(i, j)] * rj;
-                if (lij == 0.0) continue;
-                for (int c = tx; c <= j; c += 32) Li[pidx_lower(i, c)] -= lij * Li[pidx_lower(j, c)];
-            }
-            __syncthreads();
-        }
-        // Rinv (column-major) = Linv^T: Rinv[c][i] = Linv[i][c] at i*n + c, rows scaled
-        for (int i = ty; i < n; i += 32) {
-            const double lii = L[pidx_lower(i, i)];
-            const double ri = lii != 0.0 ? 1.0 / lii : 0.0;
-            for (int c = tx; c < n; c += 32) Rinv[(int64_t)i * n + c] = c <= i ? Li[pidx_lower(i, c)] * ri : 0.0;
-        }
-    } else {
-        for (int c = tid; c < n; c += blockDim.x) {
-            for (int i = 0; i < c; ++i) Rinv[(int64_t)i * n + c] = 0.0;
-            for (int i = c; i < n; ++i) {
-                const double lii = L[pidx_lower(i, i)];
-                double x = 0.0;
-                if (lii != 0.0) {
-                    double s = (i == c) ? 1.0 : 0.0;
-                    for (int m = c; m < i; ++m) s -= L[pidx_lower(i, m)] * Rinv[(int64_t)m * n + c];
-                    x = s / lii;
-                }
-                Rinv[(int64_t)i * n + c] = x;
-            }
-        }
-    }
-}
-
-// The same for n <= kInvLds with the matrix in registers: thread t owns the lower
-// elements t, t + 1024, ... in column-major order.  Right-looking Cholesky, one
+// Cholesky factor and inverse, with the matrix in registers: thread t owns the
+// lower elements t, t + 1024, ... in column-major order (n <= NMAX).  Right-looking Cholesky, one
 // barrier per column:
 // in step j every thread updates its trailing elements from column j (unscaled,
 // L[r][c] -= L[r][j] L[c][j] / d_j), read from a column buffer that the owners of
@@ -414,21 +351,21 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(const double *__restrict_
 // theirs into the other buffer.  The inverse of L runs the same way on [L | I] by
 // rows: in step j the rows below take row j (final after step j - 1) times
 // L[i][j] / L[j][j] off, and the owners of row j + 1 publish it.
-constexpr int kRegEl = (kPackedInv + 1023) / 1024;
-__global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restrict__ G, int n, double rel_tol,
-                                                           double *__restrict__ Rinv, int *flags) {
-    __shared__ double Lu[kPackedInv];                  // final L, then its columns divided by the diagonal
-    __shared__ double buf[2][kInvLds];
-    __shared__ double piv[kInvLds];
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT) void cholinv_reg_kernel(const double *__restrict__ G, int n, double rel_tol,
+                                                         double *__restrict__ Rinv, int *flags) {
+    constexpr int kRegEl = (NMAX * (NMAX + 1) / 2 + NT - 1) / NT;
+    __shared__ double Lu[NMAX * (NMAX + 1) / 2];       // final L, then its columns divided by the diagonal
+    __shared__ double buf[2][NMAX];
+    __shared__ double piv[NMAX];
     __shared__ double s_max;
     const int tid = threadIdx.x, npk = n * (n + 1) / 2;
-    int er[kRegEl], ec[kRegEl];
+    int rc[kRegEl];                                   // row | column << 16, -1: none
     double v[kRegEl];
 #pragma unroll
     for (int u = 0; u < kRegEl; ++u) {
-        const int e = tid + 1024 * u;
-        er[u] = -1;
-        ec[u] = 0;
+        const int e = tid + NT * u;
+        rc[u] = -1;
         v[u] = 0.0;
         if (e < npk) {
             // column-major over the lower triangle (column c holds rows c..n-1), so that the
@@ -438,10 +375,10 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
                 off += n - c;
                 ++c;
             }
-            er[u] = c + (e - off);
-            ec[u] = c;
-            v[u] = G[(int64_t)er[u] * n + c];
-            if (c == 0) buf[0][er[u]] = v[u];
+            const int r = c + (e - off);
+            rc[u] = r | (c << 16);
+            v[u] = G[(int64_t)r * n + c];
+            if (c == 0) buf[0][r] = v[u];
         }
     }
     if (tid < 64) {
@@ -460,7 +397,7 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
         const double rd = keep ? rcp_nr(d) : 0.0;
 #pragma unroll
         for (int u = 0; u < kRegEl; ++u) {
-            const int r = er[u], c = ec[u];
+            const int r = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
             if (c > j) {
                 if (keep) v[u] -= col[r] * col[c] * rd;
                 if (c == j + 1) nxt[r] = v[u];
@@ -472,7 +409,7 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
     // scaled factor into LDS: L[r][c] = v / piv_c below the diagonal, piv_c on it
 #pragma unroll
     for (int u = 0; u < kRegEl; ++u) {
-        const int r = er[u], c = ec[u];
+        const int r = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
         if (r < 0) continue;
         const double pc = piv[c];
         Lu[r * (r + 1) / 2 + c] = r == c ? pc : (pc > 0.0 ? v[u] / pc : 0.0);
@@ -486,7 +423,7 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
     // L[i][j] / L[j][j] below the diagonal (0 for a dropped column)
 #pragma unroll
     for (int u = 0; u < kRegEl; ++u) {
-        const int r = er[u], c = ec[u];
+        const int r = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
         if (r < 0 || r == c) continue;
         const double pc = piv[c];
         Lu[r * (r + 1) / 2 + c] = pc > 0.0 ? Lu[r * (r + 1) / 2 + c] / pc : 0.0;
@@ -494,8 +431,9 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
     // [L | I] by rows: v now holds L^{-1} (rows unscaled), starting from I
 #pragma unroll
     for (int u = 0; u < kRegEl; ++u) {
-        v[u] = er[u] >= 0 && er[u] == ec[u] ? 1.0 : 0.0;
-        if (er[u] == 0) buf[0][0] = 1.0;
+        const int r = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
+        v[u] = r >= 0 && r == c ? 1.0 : 0.0;
+        if (r == 0) buf[0][0] = 1.0;
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
@@ -503,7 +441,7 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
         double *nxt = buf[(j + 1) & 1];
 #pragma unroll
         for (int u = 0; u < kRegEl; ++u) {
-            const int i = er[u], c = ec[u];
+            const int i = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
             if (i > j) {
                 if (c <= j) v[u] -= Lu[i * (i + 1) / 2 + j] * row[c];
                 if (i == j + 1) nxt[c] = v[u];
@@ -514,12 +452,12 @@ __global__ __launch_bounds__(1024) void cholinv_reg_kernel(const double *__restr
     // Rinv (column-major) = Linv^T, rows of Linv scaled by 1 / L[i][i]
 #pragma unroll
     for (int u = 0; u < kRegEl; ++u) {
-        const int i = er[u], c = ec[u];
+        const int i = rc[u] < 0 ? -1 : (rc[u] & 0xffff), c = rc[u] < 0 ? 0 : (rc[u] >> 16);
         if (i < 0) continue;
         const double lii = piv[i];
         Rinv[(int64_t)i * n + c] = lii != 0.0 ? v[u] / lii : 0.0;
     }
-    for (int e = tid; e < n * n; e += 1024) {
+    for (int e = tid; e < n * n; e += NT) {
         const int i = e / n, c = e % n;
         if (c > i) Rinv[e] = 0.0;
     }
@@ -680,11 +618,9 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
 // Parallel-order (round-robin) cyclic Jacobi on a symmetric n x n matrix, n even.
 // In step s the n/2 disjoint pairs are (0, x(0)) and (x(a), x(m-a)), a = 1..n/2-1,
 // with m = n-1 and x(i) = 1 + (i + s) mod m; every pair occurs once per sweep.
-// This version (used for n > 128) keeps B in LDS as the packed upper triangle.
-// A step computes the n/2 rotations,
-// then updates B on the 2x2 blocks of every pair of pairs (a <= b), spread evenly
-// over the block's threads; the rotations of every step are logged, and the
-// eigenvectors P = J_1 J_2 ... are formed afterwards, one row per wave.
+// The eigensolvers below keep B in slot order; for n > 128 they log each step's
+// rotations in the roles (p, q) = (smaller, larger index) of the pair, and the
+// eigenvectors P = J_1 J_2 ... are formed afterwards from that log, one row per wave.
 __device__ __forceinline__ void rr_pair(int s, int a, int n, int &p, int &q) {
     const int m = n - 1;
     int u, v;
@@ -698,154 +634,8 @@ __device__ __forceinline__ void rr_pair(int s, int a, int n, int &p, int &q) {
     p = u < v ? u : v;
     q = u < v ? v : u;
 }
-__device__ __forceinline__ int pidx_upper(int i, int j) { return j * (j + 1) / 2 + i; }   // i <= j
-__device__ __forceinline__ int pidx_sym(int i, int j) { return i <= j ? pidx_upper(i, j) : pidx_upper(j, i); }
 
 constexpr int kMaxSweeps = 30;
-constexpr int kJacobiThreads = 1024;
-constexpr int kMaxItems = (kMaxSmall / 2) * (kMaxSmall / 2 + 1) / 2;
-
-// (a, b), a <= b < h, from the row-major linear index of the upper triangle of an h x h grid
-__device__ __forceinline__ void tri_pair(int idx, int h, int &a, int &b) {
-    const float hf = (float)h + 0.5f;
-    int x = (int)(hf - sqrtf(hf * hf - 2.0f * (float)idx));
-    if (x < 0) x = 0;
-    if (x > h - 1) x = h - 1;
-    // start(x) = x*h - x*(x-1)/2: correct the float estimate by at most one row
-    while (x > 0 && x * h - x * (x - 1) / 2 > idx) --x;
-    while ((x + 1) * h - (x + 1) * x / 2 <= idx) ++x;
-    a = x;
-    b = x + (idx - (x * h - x * (x - 1) / 2));
-}
-
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double *__restrict__ Bg, int n,
-                                                                double *__restrict__ lam,
-                                                                double2 *__restrict__ rot_log,
-                                                                int *__restrict__ nsteps_out, int *flags) {
-    __shared__ double B[kPacked];
-    __shared__ unsigned short items[kMaxItems];        // (a, b), a <= b < h, as a | b << 8
-    __shared__ double2 rot[kMaxSmall / 2];
-    __shared__ int pp[kMaxSmall / 2], qq[kMaxSmall / 2];
-    __shared__ double red_off[kJacobiThreads / 64], red_dg[kJacobiThreads / 64];
-    __shared__ int s_done;
-    __shared__ int s_rot[2];            // a step has a non-identity rotation (by parity of the step count)
-    const int tid = threadIdx.x, h = n / 2, m = n - 1;
-    const int npk = n * (n + 1) / 2, nitems = h * (h + 1) / 2;
-    if (tid == 0) s_rot[0] = s_rot[1] = 0;
-    for (int idx = tid; idx < nitems; idx += kJacobiThreads) {
-        int a, b;
-        tri_pair(idx, h, a, b);
-        items[idx] = (unsigned short)(a | (b << 8));
-    }
-    for (int idx = tid; idx < npk; idx += kJacobiThreads) {
-        int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-        while (j * (j + 1) / 2 > idx) --j;
-        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-        const int i = idx - j * (j + 1) / 2;
-        B[idx] = 0.5 * (Bg[(int64_t)i * n + j] + Bg[(int64_t)j * n + i]);
-    }
-    __syncthreads();
-    int nsteps = 0;
-    bool converged = false;
-    for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int idx = tid; idx < npk; idx += kJacobiThreads) {
-            int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-            while (j * (j + 1) / 2 > idx) --j;
-            while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-            const double v = B[idx];
-            if (idx - j * (j + 1) / 2 == j)
-                dg += v * v;
-            else
-                off += v * v;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_xor(off, o);
-            dg += __shfl_xor(dg, o);
-        }
-        if ((tid & 63) == 0) {
-            red_off[tid >> 6] = off;
-            red_dg[tid >> 6] = dg;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double so = 0.0, sd = 0.0;
-            for (int w = 0; w < kJacobiThreads / 64; ++w) {
-                so += red_off[w];
-                sd += red_dg[w];
-            }
-            s_done = (so <= 1e-26 * sd) || so == 0.0;
-        }
-        __syncthreads();
-        if (s_done) {
-            converged = true;
-            break;
-        }
-        if (sweep == kMaxSweeps) break;
-        for (int s = 0; s < m; ++s) {
-            if (tid < h) {
-                int p, q;
-                rr_pair(s, tid, n, p, q);
-                pp[tid] = p;
-                qq[tid] = q;
-                const double app = B[pidx_upper(p, p)], aqq = B[pidx_upper(q, q)], apq = B[pidx_upper(p, q)];
-                // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), tau = (aqq - app) / (2 apq), the
-                // smaller rotation angle; c = 1 / sqrt(1 + t^2), s = t c
-                double c = 1.0, sn = 0.0;
-                if (fabs(apq) > 1e-300 && apq * apq > 1e-30 * fabs(app) * fabs(aqq)) {
-                    const double tau = (aqq - app) * rcp_nr(2.0 * apq);
-                    double t;
-                    if (fabs(tau) > 1e150) {
-                        t = 0.5 * rcp_nr(tau);
-                    } else {
-                        const double r = 1.0 + tau * tau;
-                        t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + r * rsq_nr(r));
-                    }
-                    c = rsq_nr(1.0 + t * t);
-                    sn = t * c;
-                }
-                rot[tid] = make_double2(c, sn);
-                rot_log[(int64_t)nsteps * h + tid] = make_double2(c, sn);
-                if (sn != 0.0) s_rot[nsteps & 1] = 1;
-            }
-            __syncthreads();
-            const bool any_rot = s_rot[nsteps & 1] != 0;
-            if (tid == 0) s_rot[(nsteps + 1) & 1] = 0;
-            // B <- J^T B J on the 2x2 blocks of pairs (a <= b); a step of identity
-            // rotations (off-diagonal entries below 1e-15 relative) changes nothing
-            for (int idx = tid; any_rot && idx < nitems; idx += kJacobiThreads) {
-                const int ab = items[idx], a = ab & 0xff, b = ab >> 8;
-                const int pa = pp[a], qa = qq[a];
-                const double ca = rot[a].x, sa = rot[a].y;
-                if (a == b) {
-                    const int ipp = pidx_upper(pa, pa), iqq = pidx_upper(qa, qa), ipq = pidx_upper(pa, qa);
-                    const double app = B[ipp], aqq = B[iqq], apq = B[ipq];
-                    B[ipp] = ca * ca * app - 2.0 * ca * sa * apq + sa * sa * aqq;
-                    B[iqq] = sa * sa * app + 2.0 * ca * sa * apq + ca * ca * aqq;
-                    B[ipq] = 0.0;
-                } else {
-                    const int pb = pp[b], qb = qq[b];
-                    const double cb = rot[b].x, sb = rot[b].y;
-                    const int i1 = pidx_sym(pa, pb), i2 = pidx_sym(pa, qb), i3 = pidx_sym(qa, pb), i4 = pidx_sym(qa, qb);
-                    const double x = B[i1], y = B[i2], z = B[i3], w = B[i4];
-                    const double x1 = cb * x - sb * y, y1 = sb * x + cb * y;
-                    const double z1 = cb * z - sb * w, w1 = sb * z + cb * w;
-                    B[i1] = ca * x1 - sa * z1;
-                    B[i3] = sa * x1 + ca * z1;
-                    B[i2] = ca * y1 - sa * w1;
-                    B[i4] = sa * y1 + ca * w1;
-                }
-            }
-            __syncthreads();
-            ++nsteps;
-        }
-    }
-    for (int i = tid; i < n; i += kJacobiThreads) lam[i] = B[pidx_upper(i, i)];
-    if (tid == 0) {
-        *nsteps_out = nsteps;
-        if (!converged) atomicOr(&flags[kFlagNumeric], 1);
-    }
-}
 
 // Eigenvectors from the rotation log: row i of P = e_i^T J_1 J_2 ... J_S.  Rows are
 // independent, so each wave forms one row in its own piece of LDS, lane a applying
@@ -1145,6 +935,221 @@ __global__ __launch_bounds__(kSlotThreads) void jacobi_slots_kernel(const double
     }
 }
 
+// The same order and slot layout for 64 < h <= 96 pairs (n <= 192), where two copies
+// of B do not fit in LDS: one copy, two barriers per step (every owner reads its
+// blocks and rotates them in registers, then all write the permuted blocks), wave 0
+// computing the next rotations for two pairs per lane.  Rotations are logged in the
+// roles of the packed-triangle kernel (p < q by index) for its eigenvector replay.
+constexpr int kWideMaxH = kMaxSmall / 2;
+constexpr int kWideMaxBlk = kWideMaxH * (kWideMaxH + 1) / 2;
+__device__ __forceinline__ int slot_elem_wide(int i, int j) {
+    int pa = i >> 1, pb = j >> 1, r = i & 1, t = j & 1;
+    if (pa > pb) {
+        int x = pa;
+        pa = pb;
+        pb = x;
+        x = r;
+        r = t;
+        t = x;
+    }
+    if (pa == pb && r > t) {
+        r = 0;
+        t = 1;
+    }
+    return (r * 2 + t) * kWideMaxBlk + pb * (pb + 1) / 2 + pa;
+}
+
+__global__ __launch_bounds__(kSlotThreads) void jacobi_slots_wide_kernel(const double *__restrict__ Bg, int n,
+                                                                         double *__restrict__ lam,
+                                                                         double2 *__restrict__ rot_log,
+                                                                         int *__restrict__ nsteps_out, int *flags) {
+    constexpr int kWork = kSlotThreads - 64;
+    constexpr int kIPT = (kWideMaxBlk + kWork - 1) / kWork;
+    constexpr int kW = kSlotThreads / 64;
+    constexpr int S = kWideMaxBlk;
+    __shared__ __align__(16) double buf[4 * kWideMaxBlk];
+    __shared__ __align__(16) double2 rot[2][kWideMaxH];
+    __shared__ double red_off[kW], red_dg[kW];
+    __shared__ int s_done;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int h = n / 2, m = n - 1, nblk = h * (h + 1) / 2;
+    int ia[kIPT], ib[kIPT], dst[kIPT][4];
+#pragma unroll
+    for (int u = 0; u < kIPT; ++u) {
+        const int idx = tid - 64 + kWork * u;
+        ia[u] = -1;
+        ib[u] = 0;
+        dst[u][0] = dst[u][1] = dst[u][2] = dst[u][3] = 0;
+        if (wv > 0 && idx < nblk) {
+            int a, b;
+            slot_blk_ab(idx, a, b);
+            ia[u] = a;
+            ib[u] = b;
+            const int p0 = next_slot(2 * a, h, m), p1 = next_slot(2 * a + 1, h, m);
+            const int q0 = next_slot(2 * b, h, m), q1 = next_slot(2 * b + 1, h, m);
+            dst[u][0] = slot_elem_wide(p0, q0);
+            dst[u][1] = slot_elem_wide(p0, q1);
+            dst[u][2] = slot_elem_wide(p1, q0);
+            dst[u][3] = slot_elem_wide(p1, q1);
+        }
+    }
+    // wave 0: pairs lane and lane + 64, their look-ahead sources and index offsets
+    int P0[2], P1[2], r0[2], r1[2], d0[2], d1[2], xb[2], xa[2], ya[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int a = lane + 64 * k < h ? lane + 64 * k : 0;
+        const int s0 = prev_slot(2 * a, h, m), s1 = prev_slot(2 * a + 1, h, m);
+        P0[k] = s0 >> 1;
+        P1[k] = s1 >> 1;
+        r0[k] = s0 & 1;
+        r1[k] = s1 & 1;
+        d0[k] = P0[k] * (P0[k] + 3) / 2;
+        d1[k] = P1[k] * (P1[k] + 3) / 2;
+        xb[k] = slot_blk(P0[k], P1[k]);
+        xa[k] = a % m;
+        ya[k] = (m - a) % m;
+    }
+    for (int e = tid; e < nblk * 4; e += kSlotThreads) {
+        const int blk = e >> 2, pos = e & 3;
+        int a, b;
+        slot_blk_ab(blk, a, b);
+        const int gi = slot_index_at0(2 * a + (pos >> 1), m), gj = slot_index_at0(2 * b + (pos & 1), m);
+        buf[pos * S + blk] = 0.5 * (Bg[(int64_t)gi * n + gj] + Bg[(int64_t)gj * n + gi]);
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int a = lane + 64 * k;
+            if (a >= h) continue;
+            const int dblk = a * (a + 3) / 2;
+            const double2 r = slot_rotation(buf[dblk], buf[S + dblk], buf[3 * S + dblk]);
+            rot[0][a] = r;
+            // logged with p < q by index: slot 2a holds 0 (a = 0) or 1 + xa, slot 2a+1 holds 1 + ya
+            rot_log[a] = make_double2(r.x, (a == 0 || xa[k] < ya[k]) ? r.y : -r.y);
+        }
+    }
+    int nsteps = 0;
+    bool converged = false;
+    for (int sweep = 0; sweep <= kMaxSweeps; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int e = tid; e < nblk; e += kSlotThreads) {
+            int a, b;
+            slot_blk_ab(e, a, b);
+            const double x = buf[e], y = buf[S + e], z = buf[2 * S + e], w = buf[3 * S + e];
+            if (a == b) {
+                off += y * y;
+                dg += x * x + w * w;
+            } else {
+                off += x * x + y * y + z * z + w * w;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            dg += __shfl_xor(dg, o);
+        }
+        if (lane == 0) {
+            red_off[wv] = off;
+            red_dg[wv] = dg;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double so = 0.0, sd = 0.0;
+            for (int w = 0; w < kW; ++w) {
+                so += red_off[w];
+                sd += red_dg[w];
+            }
+            s_done = (so <= 1e-26 * sd) || so == 0.0;
+        }
+        __syncthreads();
+        if (s_done) {
+            converged = true;
+            break;
+        }
+        if (sweep == kMaxSweeps) break;
+        for (int st = 0; st < m; ++st) {
+            const double2 *R = rot[nsteps & 1];
+            double out[kIPT][4];
+            if (wv == 0) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int a = lane + 64 * k;
+                    if (a >= h) continue;
+                    double u00, u01, u10, u11;
+                    rot_col(R[P0[k]], r0[k], u00, u01);
+                    rot_col(R[P1[k]], r1[k], u10, u11);
+                    const double a0 = buf[d0[k]], b0 = buf[S + d0[k]], c0 = buf[3 * S + d0[k]];
+                    const double a1 = buf[d1[k]], b1 = buf[S + d1[k]], c1 = buf[3 * S + d1[k]];
+                    const double x = buf[xb[k]], y = buf[S + xb[k]], z = buf[2 * S + xb[k]], w = buf[3 * S + xb[k]];
+                    const double app = u00 * (u00 * a0 + u01 * b0) + u01 * (u00 * b0 + u01 * c0);
+                    const double aqq = u10 * (u10 * a1 + u11 * b1) + u11 * (u10 * b1 + u11 * c1);
+                    const double apq = P0[k] < P1[k] ? u00 * (x * u10 + y * u11) + u01 * (z * u10 + w * u11)
+                                                     : u10 * (x * u00 + y * u01) + u11 * (z * u00 + w * u01);
+                    const double2 r = slot_rotation(app, apq, aqq);
+                    rot[(nsteps + 1) & 1][a] = r;
+                    const int x1 = xa[k] + 1 == m ? 0 : xa[k] + 1, y1 = ya[k] + 1 == m ? 0 : ya[k] + 1;
+                    rot_log[(int64_t)(nsteps + 1) * h + a] = make_double2(r.x, (a == 0 || x1 < y1) ? r.y : -r.y);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kIPT; ++u) {
+                    if (ia[u] < 0) continue;
+                    const int a = ia[u], b = ib[u];
+                    const int e = b * (b + 1) / 2 + a;
+                    const double x = buf[e], y = buf[S + e], z = buf[2 * S + e], w = buf[3 * S + e];
+                    const double2 ra = R[a], rb = R[b];
+                    if (a != b) {
+                        const double x1 = rb.x * x - rb.y * y, y1 = rb.y * x + rb.x * y;
+                        const double z1 = rb.x * z - rb.y * w, w1 = rb.y * z + rb.x * w;
+                        out[u][0] = ra.x * x1 - ra.y * z1;
+                        out[u][1] = ra.x * y1 - ra.y * w1;
+                        out[u][2] = ra.y * x1 + ra.x * z1;
+                        out[u][3] = ra.y * y1 + ra.x * w1;
+                    } else {
+                        const double c = ra.x, sn = ra.y;
+                        out[u][0] = c * c * x - 2.0 * c * sn * y + sn * sn * w;
+                        out[u][3] = sn * sn * x + 2.0 * c * sn * y + c * c * w;
+                        out[u][1] = (c * c - sn * sn) * y + c * sn * (x - w);
+                        out[u][2] = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            if (wv != 0) {
+#pragma unroll
+                for (int u = 0; u < kIPT; ++u) {
+                    if (ia[u] < 0) continue;
+                    buf[dst[u][0]] = out[u][0];
+                    buf[dst[u][1]] = out[u][1];
+                    buf[dst[u][3]] = out[u][3];
+                    if (ia[u] != ib[u]) buf[dst[u][2]] = out[u][2];
+                }
+            }
+            __syncthreads();
+            ++nsteps;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                xa[k] = xa[k] + 1 == m ? 0 : xa[k] + 1;
+                ya[k] = ya[k] + 1 == m ? 0 : ya[k] + 1;
+            }
+        }
+    }
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int a = lane + 64 * k;
+            if (a >= h) continue;
+            const int dblk = a * (a + 3) / 2;
+            lam[a == 0 ? 0 : 1 + xa[k]] = buf[dblk];
+            lam[1 + ya[k]] = buf[3 * S + dblk];
+        }
+    }
+    if (tid == 0) {
+        *nsteps_out = nsteps;
+        if (!converged) atomicOr(&flags[kFlagNumeric], 1);
+    }
+}
+
 // Lane shifts across the wave (DPP wave_shl:1 / wave_shr:1), on the two halves of a double.
 __device__ __forceinline__ double wave_from_next(double v) {   // lane i receives lane i + 1
     const int2 x = __builtin_bit_cast(int2, v);
@@ -1405,10 +1410,15 @@ xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol
         dst = static_cast<double *>(scratch_get(ctx, (size_t)n * n * sizeof(double), &st));
         if (!dst) return st;
     }
-    if (n <= kInvLds)
-        hipLaunchKernelGGL(cholinv_reg_kernel, dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst, ctx->flags);
-    else
-        hipLaunchKernelGGL(cholinv_kernel<false>, dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst, ctx->flags);
+    if (n <= 128)
+        hipLaunchKernelGGL((cholinv_reg_kernel<128, 1024>), dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst,
+                           ctx->flags);
+    else if (n <= 160)
+        hipLaunchKernelGGL((cholinv_reg_kernel<160, 1024>), dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst,
+                           ctx->flags);
+    else        // 512 threads: the 37 elements a thread holds need more than 128 registers
+        hipLaunchKernelGGL((cholinv_reg_kernel<kMaxSmall, 512>), dim3(1), dim3(512), 0, ctx->stream, G, n, rel_tol,
+                           dst, ctx->flags);
     XPCS_LAUNCH_CHECK(ctx, "cholinv");
     if (Rprev) {
         hipLaunchKernelGGL(small_matmul_kernel, dim3(1), dim3(256), 0, ctx->stream, Rprev, dst, n, Rinv);
@@ -1456,9 +1466,9 @@ xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, do
         XPCS_LAUNCH_CHECK(ctx, "jacobi_slots_replay");
         return XPCS_OK;
     }
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, ctx->stream, B, n, lam, log, nsteps,
-                       ctx->flags);
-    XPCS_LAUNCH_CHECK(ctx, "jacobi");
+    hipLaunchKernelGGL(jacobi_slots_wide_kernel, dim3(1), dim3(kSlotThreads), 0, ctx->stream, B, n, lam, log,
+                       nsteps, ctx->flags);
+    XPCS_LAUNCH_CHECK(ctx, "jacobi_slots_wide");
     hipLaunchKernelGGL(jacobi_replay_kernel, dim3((n + kReplayWaves - 1) / kReplayWaves), dim3(64 * kReplayWaves), 0,
                        ctx->stream, log, nsteps, n, P);
     XPCS_LAUNCH_CHECK(ctx, "jacobi_replay");
