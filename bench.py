@@ -200,6 +200,63 @@ def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, seed=4000):
             "g2_finite": ok_p and ok_b}
 
 
+def precision_table(api, torch, dev, steps=3):
+    """BF16 vs FP8 subspace passes on the precision workload: 1024 x 1024 px x
+    20,000 frames, uint8 counts <= 127 (mean 0.02, beta 0.15, tau_c 50), 36 ROIs,
+    k = 128 (q = 1).  Per precision: compress time, the basis' orthonormality and
+    W = X^T U on 16 sampled frames against FP64 (the encoding pass is split-bf16 in
+    both); between the two: singular values, the subspaces (cosine of the largest
+    principal angle over the top 32 and over all k directions) and g2 (fused)."""
+    import numpy as np
+    import oracle as O
+    import synth
+    spec = synth.WORKLOADS["det1024_20k_precision"]
+    M, N, n_roi, k = spec.n_pixels, spec.n_frames, spec.n_roi, spec.ranks[0]
+    labels = synth.workload_labels(spec)
+    frames = synth.speckle_frames_torch(M, N, spec.mu, spec.beta, synth.workload_tau(spec, labels), spec.dtype,
+                                        seed=3000, device=dev, max_count=spec.max_count)
+    labels_d = torch.from_numpy(labels).to(dev)
+    ts = np.sort(np.random.default_rng(11).choice(N, size=16, replace=False))
+    Fs = frames[torch.from_numpy(ts).to(dev)].cpu().numpy().astype(np.float64)
+    ctx = api.Context(0)
+    res, U, sig, g2 = {}, {}, {}, {}
+    for prec in ("bf16", "fp8"):
+        f = api.compress_frames(ctx, frames, labels_d, n_roi, k=k, seed=7, precision=prec)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f = api.compress_frames(ctx, frames, labels_d, n_roi, k=k, seed=7, precision=prec)
+        ctx.sync()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        _, g, _ = api.correlate_two_time(ctx, f, want_c=False)
+        ctx.sync()
+        Uh = f.U.T.contiguous()
+        U[prec], sig[prec], g2[prec] = Uh, f.sigma.cpu().numpy(), g.cpu().numpy()
+        Un = Uh.double().cpu().numpy()
+        Ws = Fs @ Un
+        Wg = (f.V.T.double().cpu().numpy() * sig[prec])[ts]
+        res[prec] = {"compress_ms": ms, "frames_per_s": N / (ms / 1e3),
+                     "u_orthonormality": float((Uh.double().T @ Uh.double() - torch.eye(k, device=dev,
+                                                                                          dtype=torch.float64))
+                                               .abs().max().item()),
+                     "w_rel_err": float(np.linalg.norm(Wg - Ws) / np.linalg.norm(Ws)),
+                     "sigma_first": float(sig[prec][0]), "sigma_last": float(sig[prec][-1])}
+        del f
+    cross = (U["bf16"].double().T @ U["fp8"].double())
+    cos_all = float(torch.linalg.svdvals(cross).min().item())
+    cos_top = float(torch.linalg.svdvals(cross[:32, :32]).min().item())
+    ok = np.isfinite(g2["bf16"]) & np.isfinite(g2["fp8"])
+    ctx.close()
+    del frames
+    torch.cuda.empty_cache()
+    return {"workload": "det1024_20k_precision (1024x1024 px x 20000 frames, u8 <= 127, 36 ROIs, k=128)",
+            "bf16": res["bf16"], "fp8": res["fp8"],
+            "sigma_max_rel_diff": float(np.max(np.abs(sig["fp8"] - sig["bf16"]) / sig["bf16"])),
+            "subspace_cos_min_top32": cos_top, "subspace_cos_min_all": cos_all,
+            "g2_max_rel_diff": float(np.max(np.abs(g2["fp8"][ok] - g2["bf16"][ok]) / np.abs(g2["bf16"][ok])))}
+
+
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summaries.
 
@@ -248,6 +305,8 @@ def main():
     ap.add_argument("--serve-life", type=int, nargs=2, default=[16, 48], metavar=("LO", "HI"),
                     help="stream lifetimes in blocks")
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16 vs FP8 table on the 1024 x 1024 x 20,000 uint8 workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -414,6 +473,14 @@ def main():
             f"{served['arrival_to_done_p99_ms']:.3f} ms; open max {served['open_ms_max']:.1f} ms; "
             f"saturated {served['saturated_frames_per_s']:.0f} frames/s")
 
+    prec_table = None
+    if not args.no_precision:
+        log("precision table: BF16 vs FP8 subspace passes, 1024 x 1024 px x 20,000 uint8 frames, k = 128")
+        prec_table = precision_table(api, torch, dev)
+        log(f"precision table: compress bf16 {prec_table['bf16']['compress_ms']:.2f} ms, "
+            f"fp8 {prec_table['fp8']['compress_ms']:.2f} ms; sigma diff {prec_table['sigma_max_rel_diff']:.2e}; "
+            f"g2 diff {prec_table['g2_max_rel_diff']:.2e}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the first {args.cpu_sample_frames} frames")
@@ -445,6 +512,7 @@ def main():
         "cpu_baseline": cpu,
         "stream": serving,
         "serving": served,
+        "precision": prec_table,
         "kernels": kernels,
         "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
         "parity": parity,

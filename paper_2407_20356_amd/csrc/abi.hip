@@ -116,7 +116,7 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
 
     const int cols = online ? k : ell;
     const int L = (int)up(cols, 16);
-    const int64_t ldt = up(N, 32), ldq = up(M, 64);     // basis rows padded to the projection's K step
+    const int64_t ldt = up(N, 64), ldq = up(M, 64);     // rows padded to the projections' K steps
     const FrameProj plan = plan_proj_frames(M, N, L, n_roi, true);       // final pass: hi + lo + ROI sums
     const FrameProj plan_q = plan_proj_frames(M, N, L, 0, false);        // power pass: hi only
     // workspace layout

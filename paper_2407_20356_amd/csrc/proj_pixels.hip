@@ -91,12 +91,12 @@ __device__ __forceinline__ typename PixPack<T, RB>::type load_pix_partial(const 
 // or all outside the detector; every lane then issues the same vector loads (lanes
 // past M read pixel 0 and their outputs are dropped; frames past N read frame N-1
 // and meet the zero rows of B), which keeps the count of loads in flight fixed.
-template <typename T, int RB, int NCB, bool VEC>
+template <typename T, int RB, int NCB, bool VEC, int KG>
 __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ Y) {
     typedef typename PixPack<T, RB>::type PV;
-    __shared__ unsigned short sb[2][NCB * 16 * kQp];
+    __shared__ unsigned short sb[2][KG][NCB * 16 * kQp];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const int jg = blockIdx.y * 16 * NCB;                  // column-group offset
@@ -112,8 +112,8 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[s][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    const int nsteps = (int)((N + 31) / 32);
-    auto load_step = [&](int64_t tk, PV (&x)[8]) {
+    const int nsteps = (int)((N + 32 * KG - 1) / (32 * KG));
+    auto load_group = [&](int64_t tk, PV (&x)[8]) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t t = tk + 8 * lg + e;
@@ -167,25 +167,36 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
         }
     };
 
-    // One K step in flight beyond the one being multiplied (counts and B's K step
-    // in registers, B written to LDS one step before use).  Loads are issued every
-    // step (the last one repeated at the end) so that their number never varies.
-    Stage16<NCB> st[2];
-    PV xr[2][8];
-    st[0].load(Bg, ldb, 0);
-    load_step(0, xr[0]);
-    st[0].store(sb[0]);
+    // One K step (KG groups of 32 frames) in flight beyond the one being multiplied
+    // (counts and B's K step in registers, B written to LDS one step before use).
+    // Loads are issued every step (the last one repeated at the end) so that their
+    // number never varies; frames past N meet B's zero columns.
+    Stage16<NCB> st[2][KG];
+    PV xr[2][KG][8];
+    auto load_step = [&](int step, int slot) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            const int64_t tk = ((int64_t)step * KG + g) * 32;
+            st[slot][g].load(Bg, ldb, tk);           // tk < ldb: ldb is a multiple of 32 KG
+            load_group(tk, xr[slot][g]);
+        }
+    };
+    load_step(0, 0);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) st[0][g].store(sb[0][g]);
     __syncthreads();
     for (int step0 = 0; step0 < nsteps; step0 += 2) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int step = step0 + j;
             if (step >= nsteps) break;
-            const int sn = step + 1 < nsteps ? step + 1 : step;
-            st[j ^ 1].load(Bg, ldb, (int64_t)sn * 32);
-            load_step((int64_t)sn * 32, xr[j ^ 1]);
-            multiply(xr[j], sb[step & 1]);
-            if (step + 1 < nsteps) st[j ^ 1].store(sb[(step + 1) & 1]);
+            load_step(step + 1 < nsteps ? step + 1 : step, j ^ 1);
+#pragma unroll
+            for (int g = 0; g < KG; ++g) multiply(xr[j][g], sb[step & 1][g]);
+            if (step + 1 < nsteps) {
+#pragma unroll
+                for (int g = 0; g < KG; ++g) st[j ^ 1][g].store(sb[(step + 1) & 1][g]);
+            }
             __syncthreads();
         }
     }
@@ -204,41 +215,43 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
     }
 }
 
+// One-byte counts take two groups of 32 frames per K step, so that a step moves as
+// many bytes as a two-byte step does.
 template <typename T, int RB, int NCB>
 void launch_pp(dim3 grid, hipStream_t st, const void *X, int64_t M, int64_t N, const unsigned short *B,
                int64_t ldb, float *Y, bool vec) {
+    constexpr int KG = sizeof(T) == 1 ? 2 : 1;
     if (vec)
-        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, true>), grid, dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, true, KG>), grid, dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, B, ldb, Y);
     else
-        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, false>), grid, dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, false, KG>), grid, dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, B, ldb, Y);
 }
 
-// Four row blocks per wave up to 6 column blocks, else two (register budget).
+// Four row blocks per wave up to 6 column blocks (9 for one-byte counts, whose
+// loads take half the registers), else two (register budget).
 template <typename T>
 bool dispatch_pp(int ncb, unsigned gy, hipStream_t st, const void *X, int64_t M, int64_t N,
                  const unsigned short *B, int64_t ldb, float *Y, bool vec4, bool vec2) {
-    switch (ncb) {
+    constexpr int kMax4 = sizeof(T) == 1 ? 9 : 6;
 #define XPCS_PP4(n)                                                                             \
-    case n: {                                                                                   \
-        dim3 g((unsigned)((M + 255) / 256), gy);                                                \
-        launch_pp<T, 4, n>(g, st, X, M, N, B, ldb, Y, vec4);                                    \
-        return true;                                                                            \
-    }
+    case n:                                                                                     \
+        if (n <= kMax4) {                                                                       \
+            dim3 g((unsigned)((M + 255) / 256), gy);                                            \
+            launch_pp<T, 4, (n <= kMax4 ? n : 1)>(g, st, X, M, N, B, ldb, Y, vec4);             \
+        } else {                                                                                \
+            dim3 g((unsigned)((M + 127) / 128), gy);                                            \
+            launch_pp<T, 2, n>(g, st, X, M, N, B, ldb, Y, vec2);                                \
+        }                                                                                       \
+        return true;
+    switch (ncb) {
         XPCS_PP4(1) XPCS_PP4(2) XPCS_PP4(3) XPCS_PP4(4) XPCS_PP4(5) XPCS_PP4(6)
-#undef XPCS_PP4
-#define XPCS_PP2(n)                                                                             \
-    case n: {                                                                                   \
-        dim3 g((unsigned)((M + 127) / 128), gy);                                                \
-        launch_pp<T, 2, n>(g, st, X, M, N, B, ldb, Y, vec2);                                    \
-        return true;                                                                            \
-    }
-        XPCS_PP2(7) XPCS_PP2(8) XPCS_PP2(9) XPCS_PP2(10) XPCS_PP2(11) XPCS_PP2(12)
-#undef XPCS_PP2
+        XPCS_PP4(7) XPCS_PP4(8) XPCS_PP4(9) XPCS_PP4(10) XPCS_PP4(11) XPCS_PP4(12)
         default:
             return false;
     }
+#undef XPCS_PP4
 }
 
 }  // namespace
@@ -258,7 +271,9 @@ xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int
                                const unsigned short *B, int64_t ldb, int L, float *Y) {
     Phase phase_(ctx, "proj_pixels");
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
-    if (ldb % 32 || ldb < N) return fail(ctx, XPCS_EINVAL, "internal: sketch row stride must cover N in steps of 32");
+    const int64_t kstep = dtype == XPCS_U8 ? 64 : 32;      // frames per K step
+    if (ldb % kstep || ldb < N)
+        return fail(ctx, XPCS_EINVAL, "internal: sketch row stride must cover N in whole K steps");
     const int ncb_total = L / 16;
     // Column groups of at most 12 blocks (grid.y); all groups have the same size.
     int ngroups = (ncb_total + 11) / 12;
