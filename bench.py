@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--raw-steps", type=int, default=3)
     ap.add_argument("--no-raw", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-frames", type=int, default=1000)
+    ap.add_argument("--cpu-sample-frames", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-stream", action="store_true", help="skip the online-stream latency measurement")
     ap.add_argument("--stream-blocks", type=int, default=40)
