@@ -257,6 +257,33 @@ def precision_table(api, torch, dev, steps=3):
             "g2_max_rel_diff": float(np.max(np.abs(g2["fp8"][ok] - g2["bf16"][ok]) / np.abs(g2["bf16"][ok])))}
 
 
+def g2_only(api, torch, ctx, f, reps=5):
+    """g2 of every ROI without C: the tile pass with C = NULL against the FFT form,
+    on the factors of the benchmark step (times from events on the context's stream)."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+
+    def run(fn):
+        fn()
+        ctx.sync()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync()
+        return sorted(a.elapsed_time(b) for a, b in evs)[reps // 2], out
+
+    t_tile, (_, g_tile, n_tile) = run(lambda: api.correlate_two_time(ctx, f, want_c=False))
+    t_fft, (g_fft, n_fft) = run(lambda: api.g2_from_factors(ctx, f))
+    gt, gf = g_tile.cpu().numpy(), g_fft.cpu().numpy()
+    ok = n_tile.cpu().numpy() > 0
+    return {"tile_ms": t_tile, "fft_ms": t_fft,
+            "npairs_equal": bool(torch.equal(n_tile, n_fft)),
+            "g2_max_rel_diff": float(np.max(np.abs(gf[ok] - gt[ok]) / np.abs(gt[ok])))}
+
+
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summaries.
 
@@ -305,6 +332,7 @@ def main():
     ap.add_argument("--serve-life", type=int, nargs=2, default=[16, 48], metavar=("LO", "HI"),
                     help="stream lifetimes in blocks")
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--no-g2only", action="store_true", help="skip the g2-without-C comparison")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16 vs FP8 table on the 1024 x 1024 x 20,000 uint8 workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -458,6 +486,13 @@ def main():
         raw["gram_int8_TOPs"] = ops / (tot_ms / cnt / 1e3) / 1e12
         raw["gram_frac_of_int8_peak"] = raw["gram_int8_TOPs"] / PEAK_I8_TOPS
 
+    g2o = None
+    if not args.no_g2only:
+        log("g2 without C, every ROI: tile pass (C = NULL) vs FFT form")
+        g2o = g2_only(api, torch, ctx, f)
+        log(f"g2 without C: tile {g2o['tile_ms']:.3f} ms, FFT {g2o['fft_ms']:.3f} ms, "
+            f"max rel diff {g2o['g2_max_rel_diff']:.2e}, npairs equal {g2o['npairs_equal']}")
+
     serving = None
     if not args.no_stream:
         log("online stream: per-push latency at 1024 x 512 px, 36 ROIs, k = 64, window 4096")
@@ -513,6 +548,7 @@ def main():
         "stream": serving,
         "serving": served,
         "precision": prec_table,
+        "g2_without_c": g2o,
         "kernels": kernels,
         "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
         "parity": parity,

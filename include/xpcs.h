@@ -208,6 +208,26 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
 xpcs_status g2_from_two_time(xpcs_ctx *ctx, const void *C, int32_t c_dtype, int64_t n,
                              int64_t ldc, double *g2, int64_t *npairs);
 
+/* g2 of the compressed two-time correlation without forming C~ (Sec. 3.1, Eq. 12
+ * as the mean along the diagonals of C~_R, Sec. 2.1, Eqs. 8-10 per ROI): the same
+ * g2 and npairs as correlate_two_time with C = NULL, computed by FFT in
+ * O(k n log n) per ROI instead of O(k n^2).  With G_R = L_R L_R^T and
+ * Z[t] = sqrt(|R|) (W[t] / S_R[t]) L_R, the diagonal sums of C~_R = Z Z^T are the
+ * summed autocorrelations of Z's k columns and the pair counts the autocorrelation
+ * of the mask of frames with S_R > 0; both come from power spectra of the columns
+ * zero-padded to a power of two L >= 2n (two columns per complex transform).
+ * Arithmetic: FP64 throughout (Z, transforms, sums); npairs is the rounded
+ * transform of the mask, exact for every window allowed here.
+ * f: factors from compress_frames.  roi: ROI index or XPCS_ALL_ROIS.
+ * g2: device, (t1-t0) doubles per ROI (ROI-major for XPCS_ALL_ROIS), NaN where a
+ *     lag has no valid pair; npairs: device int64, same layout, or NULL.
+ * Workspace: about k*n*8 + (k/2+1)*L*16 bytes per ROI, ROIs processed in batches
+ * of at most 2 GiB.
+ * Errors: EINVAL (null factors or g2, window, roi), EUNSUPPORTED (k > 192 or a
+ * window of more than 2^21 frames), EBUDGET, ENOMEM. */
+xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1,
+                            double *g2, int64_t *npairs);
+
 /* ------------------------------------------------------------------ online streams
  * The paper's online strategy (Sec. 2.2): the encoding basis is fixed beforehand
  * (e.g. from compress_frames on an earlier measurement or on the first frames of

@@ -201,6 +201,27 @@ def correlate_two_time(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0:
     return C, g2, npairs
 
 
+def g2_from_factors(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: int = 0,
+                    t1: Optional[int] = None, g2: Optional[torch.Tensor] = None,
+                    npairs: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """g2 of the compressed two-time correlation by FFT (FP64, no C formed).
+
+    Returns (g2, npairs) of shape (nr, nw); the same quantities as correlate_two_time's
+    g2 and npairs, computed in O(k n log n) per ROI.
+    """
+    t1 = f.N if t1 is None else t1
+    nw = t1 - t0
+    nr = f.n_roi if roi == L.XPCS_ALL_ROIS else 1
+    if g2 is None:
+        g2 = torch.empty((nr, max(nw, 0)), dtype=torch.float64, device=ctx.device)
+    if npairs is None:
+        npairs = torch.empty((nr, max(nw, 0)), dtype=torch.int64, device=ctx.device)
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.g2_from_factors(ctx.handle, ctypes.byref(fs), roi, t0, t1, _ptr(g2), _ptr(npairs)))
+    return g2, npairs
+
+
 def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int,
                            roi: int = L.XPCS_ALL_ROIS, t0: int = 0, t1: Optional[int] = None,
                            want_c: bool = True, c_dtype=torch.float32, want_g2: bool = True,

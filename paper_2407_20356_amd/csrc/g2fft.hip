@@ -1,0 +1,391 @@
+// g2 of the compressed two-time correlation without forming C~ (Sec. 3.1, Eq. 12
+// read as the mean along C~'s diagonals; C~ per ROI from Sec. 2.1, Eqs. 8-10).
+//
+// With G_R = U_R^T U_R = L_R L_R^T and Z[t] = sqrt(|R|) (W[t] / S_R[t]) L_R (zero
+// where S_R[t] = 0), C~_R = Z Z^T, so the sum along diagonal tau is
+//   a(tau) = sum_t Z[t] . Z[t + tau] = sum_j (autocorrelation of column j)(tau),
+// and the number of valid pairs is the autocorrelation of the 0/1 mask of frames
+// with S_R > 0.  Autocorrelations come from power spectra: with the columns
+// zero-padded to L >= 2n there is no wrap-around and
+//   a(tau) = Re IDFT( sum_j |DFT z_j|^2 )(tau).
+// Two real columns share one complex transform, x = z_a + i z_b: |DFT x|^2 is
+// |DFT z_a|^2 + |DFT z_b|^2 plus a real odd term, and the inverse transform of a
+// real odd spectrum is imaginary, so the real part above is exact.  The work is
+// O(k n log n) per ROI instead of the tile pass's O(k n^2), and every step runs in
+// FP64, so the result is the same g2 as the tile pass's, without its bf16 terms.
+//
+// Transforms are radix-2 in FP64, length L = L1 * L2 (L1 <= L2 <= 2048), in two
+// passes over HBM (four-step): pass 1 transforms the L1-long columns
+// x[a L2 + c] of CC columns at a time in LDS, multiplies by w_L^(b c) and stores
+// X1[b][c]; pass 2 transforms RB rows X1[b][.] at a time, giving X[b + L1 d].
+// The forward pass 2 accumulates |X|^2 over a ROI's column pairs in registers;
+// the inverse transform of the (data, mask) spectra reuses both passes.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace xpcs {
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftElems = 2048;             // complex elements per LDS tile (32 KB)
+constexpr int kFftPerThread = kFftElems / kFftThreads;
+constexpr int kFftMaxLog = 22;              // L <= 2^22, i.e. windows up to 2^21 frames
+constexpr int kZFrames = 64;                // frames per block of the z kernel
+constexpr int kZChunk = 32;                 // rows of L_R staged at a time
+constexpr int kZMaxK = 192;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 expi_2pi(double num, double den, double sgn) {
+    // exp(sgn * 2 pi i num / den); den is a power of two, so num / den is exact
+    double s, c;
+    sincospi(sgn * 2.0 * (num / den), &s, &c);
+    return make_double2(c, s);
+}
+__device__ __forceinline__ int bitrev(int a, int lg) {
+    return lg == 0 ? 0 : (int)(__builtin_bitreverse32((unsigned)a) >> (32 - lg));
+}
+
+// In-place radix-2 transform of length P = 2^lp over G = 2^lg interleaved
+// sequences in LDS (element a of sequence g at buf[a * G + g]), input in
+// bit-reversed order, output in natural order; tw[m] = exp(sgn 2 pi i m / P).
+// Starts and ends with a barrier.
+__device__ void lds_fft(double2 *buf, const double2 *tw, int lp, int lg) {
+    const int G = 1 << lg;
+    const int nbf = (1 << (lp - 1)) * G;
+    __syncthreads();
+    for (int s = 0; s < lp; ++s) {
+        const int half = 1 << s, tshift = lp - 1 - s;
+        for (int u = threadIdx.x; u < nbf; u += kFftThreads) {
+            const int g = u & (G - 1), v = u >> lg;
+            const int pos = v & (half - 1), grp = v >> s;
+            const int i0 = ((grp << (s + 1)) + pos) * G + g, i1 = i0 + half * G;
+            const double2 w = tw[pos << tshift];
+            const double2 x0 = buf[i0], x1 = cmul(w, buf[i1]);
+            buf[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
+            buf[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void fill_twiddles(double2 *tw, int lp, double sgn) {
+    const int P = 1 << lp;
+    for (int m = threadIdx.x; m < P / 2; m += kFftThreads) tw[m] = expi_2pi((double)m, (double)P, sgn);
+}
+
+// z[(slot k + j) n + t] = sqrt(|R|) sum_a (V[t0+t][a] sigma_a / S[t0+t]) L[a][j]
+// (FP64, zero where S = 0).  Thread (fr, cb) forms frames 4 fr .. 4 fr + 3 and
+// columns cb + 16 j, j < CPT; the block's result is transposed through LDS so
+// that every column is stored as a contiguous run of frames.
+template <int CPT>
+__global__ __launch_bounds__(256) void g2fft_z_kernel(
+    const float *__restrict__ V, const double *__restrict__ sigma, const int64_t *__restrict__ roi_sum,
+    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int64_t t0,
+    int64_t n, double *__restrict__ z) {
+    extern __shared__ double zsm[];
+    const int kc = 16 * CPT;
+    double *wT = zsm;                                 // [kc][kZFrames]
+    double *Lc = zsm + (size_t)kc * kZFrames;         // [kZChunk][kc]
+    const int slot = blockIdx.y, roi = r0 + slot;
+    const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
+    const double sq = sqrt((double)roi_npix[roi]);
+    const int64_t *Sr = roi_sum + (int64_t)roi * N;
+    const double *L = Lr + (int64_t)slot * k * k;
+    for (int idx = threadIdx.x; idx < kc * kZFrames; idx += 256) {
+        const int a = idx / kZFrames, f = idx % kZFrames;
+        const int64_t tl = f0 + f;
+        double w = 0.0;
+        if (tl < n && a < k) {
+            const int64_t sv = Sr[t0 + tl];
+            if (sv > 0) w = sq * (double)V[(int64_t)a * N + t0 + tl] * sigma[a] / (double)sv;
+        }
+        wT[idx] = w;
+    }
+    const int fr = threadIdx.x >> 4, cb = threadIdx.x & 15;
+    double acc[4][CPT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
+    for (int a0 = 0; a0 < k; a0 += kZChunk) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kZChunk * kc; idx += 256) {
+            const int aa = idx / kc, b = idx % kc;
+            Lc[idx] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
+        }
+        __syncthreads();
+        const int na = k - a0 < kZChunk ? k - a0 : kZChunk;
+        for (int aa = 0; aa < na; ++aa) {
+            const double2 x01 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr]);
+            const double2 x23 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr + 2]);
+            const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const double l = Lc[aa * kc + cb + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = fma(x[i], l, acc[i][j]);
+            }
+        }
+    }
+    __syncthreads();                                  // wT is reused for the transposed result
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) wT[(cb + 16 * j) * kZFrames + 4 * fr + i] = acc[i][j];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
+        const int b = idx / kZFrames, f = idx % kZFrames;
+        if (f0 + f < n) z[((int64_t)slot * k + b) * n + f0 + f] = wT[idx];
+    }
+}
+
+// Pass 1.  INV = false: signal s of the batch is column pair p of ROI slot
+// s / (np + 1) (x = z_2p + i z_2p+1, the odd column alone when k is odd) or, for
+// p = np, the ROI's 0/1 frame mask; x[t] = 0 for t >= n.  INV = true: signal s
+// is the real spectrum spec[s][.] and the transform runs with the opposite sign.
+template <bool INV>
+__global__ __launch_bounds__(kFftThreads) void g2fft_pass1_kernel(
+    const double *__restrict__ z, const int64_t *__restrict__ roi_sum, int64_t N, int r0, int64_t t0, int64_t n,
+    int k, int np, const double *__restrict__ spec, int lp1, int lp2, int lcc, double2 *__restrict__ X1) {
+    extern __shared__ double2 fsm[];
+    const int L1 = 1 << lp1, L2 = 1 << lp2, CC = 1 << lcc;
+    const int64_t L = (int64_t)L1 * L2;
+    double2 *buf = fsm, *tw = fsm + (L1 << lcc);
+    const double sgn = INV ? 1.0 : -1.0;
+    fill_twiddles(tw, lp1, sgn);
+    const int c0 = blockIdx.x << lcc;
+    const int s = blockIdx.y;
+    const double *za = nullptr, *zb = nullptr;
+    const int64_t *Sr = nullptr;
+    if (!INV) {
+        const int slot = s / (np + 1), p = s % (np + 1);
+        if (p < np) {
+            za = z + ((int64_t)slot * k + 2 * p) * n;
+            if (2 * p + 1 < k) zb = za + n;
+        } else {
+            Sr = roi_sum + (int64_t)(r0 + slot) * N + t0;
+        }
+    }
+    for (int e = threadIdx.x; e < (L1 << lcc); e += kFftThreads) {
+        const int a = e >> lcc, c = e & (CC - 1);
+        const int64_t t = (int64_t)a * L2 + c0 + c;
+        double2 v = make_double2(0.0, 0.0);
+        if (INV) {
+            v.x = spec[(int64_t)s * L + t];
+        } else if (t < n) {
+            if (za) {
+                v.x = za[t];
+                if (zb) v.y = zb[t];
+            } else {
+                v.x = Sr[t] > 0 ? 1.0 : 0.0;
+            }
+        }
+        buf[(bitrev(a, lp1) << lcc) + c] = v;
+    }
+    lds_fft(buf, tw, lp1, lcc);
+    for (int e = threadIdx.x; e < (L1 << lcc); e += kFftThreads) {
+        const int b = e >> lcc, c = e & (CC - 1);
+        const int64_t m = ((int64_t)b * (c0 + c)) & (L - 1);
+        X1[(int64_t)s * L + (int64_t)b * L2 + c0 + c] = cmul(buf[e], expi_2pi((double)m, (double)L, sgn));
+    }
+}
+
+// Pass 2.  INV = false: block (row chunk, 2 slot + which) transforms the rows of
+// every column-pair signal of the ROI (which = 0) or of its mask signal (which =
+// 1) and writes the summed power spectrum spec[2 slot + which][f].  INV = true:
+// block (row chunk, s) finishes the inverse transform of signal s and writes
+// out[s][tau] = Re(x[tau]) / L for tau < n.
+template <bool INV>
+__global__ __launch_bounds__(kFftThreads) void g2fft_pass2_kernel(const double2 *__restrict__ X1, int np, int lp1,
+                                                                  int lp2, int lrb, int64_t n,
+                                                                  double *__restrict__ out) {
+    extern __shared__ double2 fsm[];
+    const int L1 = 1 << lp1, L2 = 1 << lp2, RB = 1 << lrb;
+    const int64_t L = (int64_t)L1 * L2;
+    const int tile = L2 << lrb;
+    double2 *buf = fsm, *tw = fsm + tile;
+    fill_twiddles(tw, lp2, INV ? 1.0 : -1.0);
+    const int b0 = blockIdx.x << lrb;
+    int s_first, s_count;
+    if (INV) {
+        s_first = blockIdx.y;
+        s_count = 1;
+    } else {
+        const int slot = blockIdx.y >> 1, which = blockIdx.y & 1;
+        s_first = slot * (np + 1) + (which ? np : 0);
+        s_count = which ? 1 : np;
+    }
+    double acc[kFftPerThread];
+#pragma unroll
+    for (int i = 0; i < kFftPerThread; ++i) acc[i] = 0.0;
+    for (int si = 0; si < s_count; ++si) {
+        const double2 *src = X1 + (int64_t)(s_first + si) * L;
+        if (si > 0) __syncthreads();                  // the previous signal's tile has been read
+        for (int e = threadIdx.x; e < tile; e += kFftThreads) {
+            const int g = e >> lp2, c = e & (L2 - 1);
+            buf[(bitrev(c, lp2) << lrb) + g] = src[(int64_t)(b0 + g) * L2 + c];
+        }
+        lds_fft(buf, tw, lp2, lrb);
+#pragma unroll
+        for (int i = 0; i < kFftPerThread; ++i) {
+            const int e = threadIdx.x + i * kFftThreads;
+            if (e < tile) {
+                const double2 x = buf[e];
+                acc[i] = INV ? x.x : fma(x.x, x.x, fma(x.y, x.y, acc[i]));
+            }
+        }
+    }
+    const double invL = 1.0 / (double)L;
+#pragma unroll
+    for (int i = 0; i < kFftPerThread; ++i) {
+        const int e = threadIdx.x + i * kFftThreads;
+        if (e >= tile) continue;
+        const int d = e >> lrb, g = e & (RB - 1);
+        const int64_t f = b0 + g + (int64_t)L1 * d;
+        if (INV) {
+            if (f < n) out[(int64_t)blockIdx.y * n + f] = acc[i] * invL;
+        } else {
+            out[(int64_t)blockIdx.y * L + f] = acc[i];
+        }
+    }
+}
+
+// g2[(r0 + slot) nw + tau] from the two inverse transforms of the ROI: the
+// diagonal sum and the pair count (an integer up to rounding).
+__global__ void g2fft_finish_kernel(const double *__restrict__ sums, int64_t n, int slot0, double *__restrict__ g2,
+                                    int64_t *__restrict__ npairs) {
+    const int slot = blockIdx.y;
+    const int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tau >= n) return;
+    const double a = sums[(int64_t)(2 * slot) * n + tau];
+    const int64_t cnt = llrint(sums[(int64_t)(2 * slot + 1) * n + tau]);
+    const int64_t o = (int64_t)(slot0 + slot) * n + tau;
+    g2[o] = cnt > 0 ? a / (double)cnt : __builtin_nan("");
+    if (npairs) npairs[o] = cnt;
+}
+
+struct FftPlan {
+    int lp1, lp2, lcc, lrb;
+    int64_t L;
+};
+
+FftPlan fft_plan(int64_t n) {
+    int p = 2;
+    while (((int64_t)1 << p) < 2 * n) ++p;
+    FftPlan pl;
+    pl.lp1 = p / 2;
+    pl.lp2 = p - pl.lp1;
+    pl.L = (int64_t)1 << p;
+    int lcc = 0;                                      // columns per pass-1 tile
+    while (lcc < pl.lp2 && (2 << (pl.lp1 + lcc)) <= kFftElems) ++lcc;
+    int lrb = 0;                                      // rows per pass-2 tile
+    while (lrb < pl.lp1 && (2 << (pl.lp2 + lrb)) <= kFftElems) ++lrb;
+    pl.lcc = lcc;
+    pl.lrb = lrb;
+    return pl;
+}
+
+xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
+                           int64_t n, double *z) {
+    const int cpt = (f->k + 15) / 16;
+    const size_t lds = ((size_t)16 * cpt * kZFrames + (size_t)kZChunk * 16 * cpt) * sizeof(double);
+    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)nb);
+#define XPCS_Z(c)                                                                                                \
+    case c:                                                                                                      \
+        hipLaunchKernelGGL(g2fft_z_kernel<c>, grid, dim3(256), lds, ctx->stream, f->V, f->sigma, f->roi_sum,      \
+                           f->roi_npix, Lr, f->N, f->k, r0, t0, n, z);                                           \
+        break;
+    switch (cpt) {
+        XPCS_Z(1) XPCS_Z(2) XPCS_Z(3) XPCS_Z(4) XPCS_Z(5) XPCS_Z(6)
+        XPCS_Z(7) XPCS_Z(8) XPCS_Z(9) XPCS_Z(10) XPCS_Z(11) XPCS_Z(12)
+        default:
+            return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in g2_from_factors");
+    }
+#undef XPCS_Z
+    XPCS_LAUNCH_CHECK(ctx, "g2fft_z");
+    return XPCS_OK;
+}
+
+}  // namespace
+}  // namespace xpcs
+
+using namespace xpcs;
+
+extern "C" {
+
+xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1, double *g2,
+                            int64_t *npairs) {
+    if (!ctx) return XPCS_EINVAL;
+    if (!f || !f->V || !f->sigma || !f->roi_npix || !f->roi_sum || !f->roi_gram)
+        return fail(ctx, XPCS_EINVAL, "factors or one of their buffers is NULL");
+    if (f->N <= 0 || f->M <= 0 || f->k < 1 || f->n_roi < 1) return fail(ctx, XPCS_EINVAL, "bad factor sizes");
+    if (!g2) return fail(ctx, XPCS_EINVAL, "g2 must not be NULL");
+    if (roi != XPCS_ALL_ROIS && (roi < 0 || roi >= f->n_roi))
+        return fail(ctx, XPCS_EINVAL, "roi outside [0, n_roi) and not XPCS_ALL_ROIS");
+    if (t0 < 0 || t1 <= t0 || t1 > f->N) return fail(ctx, XPCS_EINVAL, "window must satisfy 0 <= t0 < t1 <= N");
+    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in g2_from_factors");
+    const int64_t n = t1 - t0;
+    if (n > ((int64_t)1 << (kFftMaxLog - 1))) return fail(ctx, XPCS_EUNSUPPORTED, "window above 2^21 frames");
+    (void)hipSetDevice(ctx->device);
+    ws_begin(ctx);
+    const int r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
+    const int nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
+    const int k = f->k, np = (k + 1) / 2;
+    const FftPlan pl = fft_plan(n);
+    const int64_t L = pl.L;
+    // ROIs per batch: z, the pass-1 output of every signal, spectra and sums
+    const size_t per_roi = (size_t)k * n * 8 + (size_t)(np + 1) * L * 16 + (size_t)2 * L * 8 + (size_t)2 * n * 8;
+    const size_t cap = (size_t)2 << 30;
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nr, cap / per_roi));
+    const size_t b_l = (size_t)nr * k * k * 8;
+    const size_t b_z = (size_t)nb * k * n * 8, b_x = (size_t)nb * (np + 1) * L * 16;
+    const size_t b_s = (size_t)nb * 2 * L * 8, b_o = (size_t)nb * 2 * n * 8;
+    xpcs_status st = ws_reserve(ctx, align_up(b_l, 256) + align_up(b_z, 256) + align_up(b_x, 256) +
+                                         align_up(b_s, 256) + align_up(b_o, 256) + 5 * 256);
+    if (st) return st;
+    auto *Lr = static_cast<double *>(ws_take(ctx, b_l));
+    auto *z = static_cast<double *>(ws_take(ctx, b_z));
+    auto *X1 = static_cast<double2 *>(ws_take(ctx, b_x));
+    auto *spec = static_cast<double *>(ws_take(ctx, b_s));
+    auto *sums = static_cast<double *>(ws_take(ctx, b_o));
+    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * k * k, k, nr, Lr))) return st;
+    const size_t lds1 = ((size_t)(1 << (pl.lp1 + pl.lcc)) + (1 << pl.lp1) / 2) * sizeof(double2);
+    const size_t lds2 = ((size_t)(1 << (pl.lp2 + pl.lrb)) + (1 << pl.lp2) / 2) * sizeof(double2);
+    const unsigned g1x = (unsigned)(1 << (pl.lp2 - pl.lcc)), g2x = (unsigned)(1 << (pl.lp1 - pl.lrb));
+    for (int s0 = 0; s0 < nr; s0 += nb) {
+        const int m = std::min(nb, nr - s0);
+        {
+            Phase phase_(ctx, "g2fft_z");
+            if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
+        }
+        {
+            Phase phase_(ctx, "g2fft_forward");
+            hipLaunchKernelGGL(g2fft_pass1_kernel<false>, dim3(g1x, (unsigned)(m * (np + 1))), dim3(kFftThreads),
+                               lds1, ctx->stream, z, f->roi_sum, f->N, r0 + s0, t0, n, k, np, nullptr, pl.lp1,
+                               pl.lp2, pl.lcc, X1);
+            XPCS_LAUNCH_CHECK(ctx, "g2fft_pass1");
+            hipLaunchKernelGGL(g2fft_pass2_kernel<false>, dim3(g2x, (unsigned)(m * 2)), dim3(kFftThreads), lds2,
+                               ctx->stream, X1, np, pl.lp1, pl.lp2, pl.lrb, n, spec);
+            XPCS_LAUNCH_CHECK(ctx, "g2fft_pass2");
+        }
+        {
+            Phase phase_(ctx, "g2fft_inverse");
+            hipLaunchKernelGGL(g2fft_pass1_kernel<true>, dim3(g1x, (unsigned)(m * 2)), dim3(kFftThreads), lds1,
+                               ctx->stream, nullptr, nullptr, f->N, 0, 0, n, k, np, spec, pl.lp1, pl.lp2, pl.lcc,
+                               X1);
+            XPCS_LAUNCH_CHECK(ctx, "g2fft_pass1_inverse");
+            hipLaunchKernelGGL(g2fft_pass2_kernel<true>, dim3(g2x, (unsigned)(m * 2)), dim3(kFftThreads), lds2,
+                               ctx->stream, X1, np, pl.lp1, pl.lp2, pl.lrb, n, sums);
+            XPCS_LAUNCH_CHECK(ctx, "g2fft_pass2_inverse");
+            hipLaunchKernelGGL(g2fft_finish_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
+                               ctx->stream, sums, n, s0, g2, npairs);
+            XPCS_LAUNCH_CHECK(ctx, "g2fft_finish");
+        }
+    }
+    return XPCS_OK;
+}
+
+}  // extern "C"

@@ -9,6 +9,7 @@ correlates every ROI.  The oracle then checks, from the frames alone,
   * C~ among 16 sampled frames of every ROI (Eqs. 9-10 per ROI), and
   * g2 of every ROI at every lag, through its FFT form of the same C~ (no N x N
     matrix), from W = X^T U of all frames encoded in FP64 chunk by chunk.
+The FFT form of g2 (g2_from_factors) is checked the same way, on both bases.
 Offline basis (the benchmark's own step): the basis is the library's, so the
 checks are properties any correct basis satisfies, written with NumPy here:
 orthonormality, W = X^T U and the C~ identity on sampled frames, exact ROI sums,
@@ -90,11 +91,17 @@ def test_fullsize_online_basis_against_oracle(setup):
         S[:, t0:t0 + Fc.shape[0]] = O.roi_frame_sums(Fc, labels, R)
     np.testing.assert_array_equal(to_np(f.roi_sum), S)
     g2g, npg = to_np(g2), to_np(npairs)
+    say("g2_from_factors (FFT) of every ROI")
+    g2f, npf = api.g2_from_factors(ctx, f)
+    ctx.sync()
+    g2f, npf = to_np(g2f), to_np(npf)
     for r in range(R):
         gref, nref = O.g2_fft_from_factors(W, O.roi_basis_gram(Uo, labels, r), S[r], int(npix[r]))
         np.testing.assert_array_equal(npg[r], nref)
+        np.testing.assert_array_equal(npf[r], nref)
         ok = nref > 0
         np.testing.assert_allclose(g2g[r][ok], gref[ok], rtol=1e-3, err_msg=f"g2 roi {r}")
+        np.testing.assert_allclose(g2f[r][ok], gref[ok], rtol=1e-3, err_msg=f"FFT g2 roi {r}")
 
 
 def test_fullsize_offline_step_properties(setup):
@@ -132,3 +139,8 @@ def test_fullsize_offline_step_properties(setup):
         np.testing.assert_array_equal(to_np(nC), to_np(npairs)[r])
         np.testing.assert_allclose(to_np(g2)[r], to_np(gC), rtol=1e-5)
     assert np.all(to_np(npairs) == (N - np.arange(N))[None, :])
+    say("g2_from_factors (FFT) against the fused g2 of the tile pass")
+    g2f, npf = api.g2_from_factors(ctx, f)
+    ctx.sync()
+    np.testing.assert_array_equal(to_np(npf), to_np(npairs))
+    np.testing.assert_allclose(to_np(g2f), to_np(g2), rtol=1e-3)
