@@ -48,27 +48,69 @@ __device__ __forceinline__ int bitrev(int a, int lg) {
     return lg == 0 ? 0 : (int)(__builtin_bitreverse32((unsigned)a) >> (32 - lg));
 }
 
+// exp(sgn 2 pi i m / 2^(t+1)) * x for the small constant roots (t <= 2, m < 2^t).
+template <int T, int Mi>
+__device__ __forceinline__ double2 root_mul(double2 x, double sgn) {
+    if (Mi == 0) return x;
+    if (T == 1 || Mi == 2) return make_double2(-sgn * x.y, sgn * x.x);        // * (sgn i)
+    constexpr double h = 0.70710678118654752440;                            // 2^-1/2
+    if (Mi == 1) return cmul(x, make_double2(h, sgn * h));
+    return cmul(x, make_double2(-h, sgn * h));                              // Mi == 3
+}
+
+// R consecutive radix-2 stages s .. s+R-1 in registers: a work item owns the 2^R
+// elements pos + j 2^s (j < 2^R) of one 2^(s+R)-element block of one sequence.
+// In stage s+t the pair (j, j + 2^t) takes the twiddle w_(2^(s+t+1))^(pos + m 2^s),
+// m = j mod 2^t, i.e. the table entry for pos times a constant root.
+template <int R>
+__device__ __forceinline__ void fft_stages(double2 *buf, const double2 *tw, int lp, int lg, int s, double sgn) {
+    constexpr int E = 1 << R;
+    const int G = 1 << lg;
+    const int units = (1 << (lp - R)) << lg;
+    const int step = (1 << s) * G;
+    for (int u = threadIdx.x; u < units; u += kFftThreads) {
+        const int g = u & (G - 1), v = u >> lg;
+        const int pos = v & ((1 << s) - 1), grp = v >> s;
+        const int base = ((grp << (s + R)) + pos) * G + g;
+        double2 x[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) x[j] = buf[base + j * step];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const double2 w0 = tw[pos << (lp - 1 - s - t)];
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                if (j & (1 << t)) continue;
+                const int jj = j | (1 << t);
+                double2 w;
+                switch (j & ((1 << t) - 1)) {
+                    case 0: w = w0; break;
+                    case 1: w = t == 1 ? root_mul<1, 1>(w0, sgn) : root_mul<2, 1>(w0, sgn); break;
+                    case 2: w = root_mul<2, 2>(w0, sgn); break;
+                    default: w = root_mul<2, 3>(w0, sgn); break;
+                }
+                const double2 y = cmul(w, x[jj]);
+                x[jj] = make_double2(x[j].x - y.x, x[j].y - y.y);
+                x[j] = make_double2(x[j].x + y.x, x[j].y + y.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) buf[base + j * step] = x[j];
+    }
+    __syncthreads();
+}
+
 // In-place radix-2 transform of length P = 2^lp over G = 2^lg interleaved
 // sequences in LDS (element a of sequence g at buf[a * G + g]), input in
-// bit-reversed order, output in natural order; tw[m] = exp(sgn 2 pi i m / P).
-// Starts and ends with a barrier.
-__device__ void lds_fft(double2 *buf, const double2 *tw, int lp, int lg) {
-    const int G = 1 << lg;
-    const int nbf = (1 << (lp - 1)) * G;
+// bit-reversed order, output in natural order; tw[m] = exp(sgn 2 pi i m / P),
+// m < P/2.  Stages run three at a time in registers.  Starts and ends with a
+// barrier.
+__device__ void lds_fft(double2 *buf, const double2 *tw, int lp, int lg, double sgn) {
     __syncthreads();
-    for (int s = 0; s < lp; ++s) {
-        const int half = 1 << s, tshift = lp - 1 - s;
-        for (int u = threadIdx.x; u < nbf; u += kFftThreads) {
-            const int g = u & (G - 1), v = u >> lg;
-            const int pos = v & (half - 1), grp = v >> s;
-            const int i0 = ((grp << (s + 1)) + pos) * G + g, i1 = i0 + half * G;
-            const double2 w = tw[pos << tshift];
-            const double2 x0 = buf[i0], x1 = cmul(w, buf[i1]);
-            buf[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
-            buf[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
-        }
-        __syncthreads();
-    }
+    int s = 0;
+    for (; s + 3 <= lp; s += 3) fft_stages<3>(buf, tw, lp, lg, s, sgn);
+    if (lp - s == 2) fft_stages<2>(buf, tw, lp, lg, s, sgn);
+    else if (lp - s == 1) fft_stages<1>(buf, tw, lp, lg, s, sgn);
 }
 
 __device__ void fill_twiddles(double2 *tw, int lp, double sgn) {
@@ -91,18 +133,22 @@ __global__ __launch_bounds__(256) void g2fft_z_kernel(
     double *Lc = zsm + (size_t)kc * kZFrames;         // [kZChunk][kc]
     const int slot = blockIdx.y, roi = r0 + slot;
     const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
-    const double sq = sqrt((double)roi_npix[roi]);
+    double *fscale = Lc + (size_t)kZChunk * kc;       // [kZFrames]: sqrt(|R|) / S, 0 where S = 0
     const int64_t *Sr = roi_sum + (int64_t)roi * N;
     const double *L = Lr + (int64_t)slot * k * k;
-    for (int idx = threadIdx.x; idx < kc * kZFrames; idx += 256) {
+    if (threadIdx.x < kZFrames) {
+        const int64_t tl = f0 + threadIdx.x;
+        const int64_t sv = tl < n ? Sr[t0 + tl] : 0;
+        fscale[threadIdx.x] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kc * kZFrames / 256; ++i) {
+        const int idx = threadIdx.x + 256 * i;
         const int a = idx / kZFrames, f = idx % kZFrames;
         const int64_t tl = f0 + f;
-        double w = 0.0;
-        if (tl < n && a < k) {
-            const int64_t sv = Sr[t0 + tl];
-            if (sv > 0) w = sq * (double)V[(int64_t)a * N + t0 + tl] * sigma[a] / (double)sv;
-        }
-        wT[idx] = w;
+        const float v = (tl < n && a < k) ? V[(int64_t)a * N + t0 + tl] : 0.0f;
+        wT[idx] = (a < k) ? (double)v * sigma[a] * fscale[f] : 0.0;
     }
     const int fr = threadIdx.x >> 4, cb = threadIdx.x & 15;
     double acc[4][CPT];
@@ -118,6 +164,7 @@ __global__ __launch_bounds__(256) void g2fft_z_kernel(
         }
         __syncthreads();
         const int na = k - a0 < kZChunk ? k - a0 : kZChunk;
+#pragma unroll 8
         for (int aa = 0; aa < na; ++aa) {
             const double2 x01 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr]);
             const double2 x23 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr + 2]);
@@ -149,13 +196,15 @@ __global__ __launch_bounds__(256) void g2fft_z_kernel(
 template <bool INV>
 __global__ __launch_bounds__(kFftThreads) void g2fft_pass1_kernel(
     const double *__restrict__ z, const int64_t *__restrict__ roi_sum, int64_t N, int r0, int64_t t0, int64_t n,
-    int k, int np, const double *__restrict__ spec, int lp1, int lp2, int lcc, double2 *__restrict__ X1) {
+    int k, int np, const double *__restrict__ spec, int nparts, int lp1, int lp2, int lcc,
+    double2 *__restrict__ X1) {
     extern __shared__ double2 fsm[];
     const int L1 = 1 << lp1, L2 = 1 << lp2, CC = 1 << lcc;
     const int64_t L = (int64_t)L1 * L2;
-    double2 *buf = fsm, *tw = fsm + (L1 << lcc);
+    double2 *buf = fsm, *tw = fsm + (L1 << lcc), *tlo = tw + L1 / 2;
     const double sgn = INV ? 1.0 : -1.0;
     fill_twiddles(tw, lp1, sgn);
+    for (int m = threadIdx.x; m < L2; m += kFftThreads) tlo[m] = expi_2pi((double)m, (double)L, sgn);
     const int c0 = blockIdx.x << lcc;
     const int s = blockIdx.y;
     const double *za = nullptr, *zb = nullptr;
@@ -174,7 +223,16 @@ __global__ __launch_bounds__(kFftThreads) void g2fft_pass1_kernel(
         const int64_t t = (int64_t)a * L2 + c0 + c;
         double2 v = make_double2(0.0, 0.0);
         if (INV) {
-            v.x = spec[(int64_t)s * L + t];
+            // signal s = 2 slot + which: the data spectrum is split in nparts partial sums
+            const int slot = s >> 1;
+            const double *sp = spec + (int64_t)slot * (nparts + 1) * L + t;
+            if (s & 1) {
+                v.x = sp[(int64_t)nparts * L];
+            } else {
+                double acc = 0.0;
+                for (int q = 0; q < nparts; ++q) acc += sp[(int64_t)q * L];
+                v.x = acc;
+            }
         } else if (t < n) {
             if (za) {
                 v.x = za[t];
@@ -185,22 +243,26 @@ __global__ __launch_bounds__(kFftThreads) void g2fft_pass1_kernel(
         }
         buf[(bitrev(a, lp1) << lcc) + c] = v;
     }
-    lds_fft(buf, tw, lp1, lcc);
+    lds_fft(buf, tw, lp1, lcc, sgn);
+    // w_L^(b c) = w_L1^(m >> lp2) w_L^(m mod L2), m = b c mod L; w_L1^h = -w_L1^(h - L1/2) for h >= L1/2
     for (int e = threadIdx.x; e < (L1 << lcc); e += kFftThreads) {
         const int b = e >> lcc, c = e & (CC - 1);
         const int64_t m = ((int64_t)b * (c0 + c)) & (L - 1);
-        X1[(int64_t)s * L + (int64_t)b * L2 + c0 + c] = cmul(buf[e], expi_2pi((double)m, (double)L, sgn));
+        const int mh = (int)(m >> lp2), ml = (int)(m & (L2 - 1));
+        double2 wh = tw[mh & (L1 / 2 - 1)];
+        if (mh >= L1 / 2) wh = make_double2(-wh.x, -wh.y);
+        X1[(int64_t)s * L + (int64_t)b * L2 + c0 + c] = cmul(cmul(buf[e], wh), tlo[ml]);
     }
 }
 
-// Pass 2.  INV = false: block (row chunk, 2 slot + which) transforms the rows of
-// every column-pair signal of the ROI (which = 0) or of its mask signal (which =
-// 1) and writes the summed power spectrum spec[2 slot + which][f].  INV = true:
-// block (row chunk, s) finishes the inverse transform of signal s and writes
-// out[s][tau] = Re(x[tau]) / L for tau < n.
+// Pass 2.  INV = false: block (row chunk, slot (nparts + 1) + q) transforms the
+// rows of column pairs [q ppb, min(np, (q + 1) ppb)) of the ROI (q < nparts) or of
+// its mask signal (q = nparts) and writes their summed power spectrum to
+// out[slot (nparts + 1) + q][f].  INV = true: block (row chunk, s) finishes the
+// inverse transform of signal s and writes out[s][tau] = Re(x[tau]) / L, tau < n.
 template <bool INV>
-__global__ __launch_bounds__(kFftThreads) void g2fft_pass2_kernel(const double2 *__restrict__ X1, int np, int lp1,
-                                                                  int lp2, int lrb, int64_t n,
+__global__ __launch_bounds__(kFftThreads) void g2fft_pass2_kernel(const double2 *__restrict__ X1, int np, int nparts,
+                                                                  int ppb, int lp1, int lp2, int lrb, int64_t n,
                                                                   double *__restrict__ out) {
     extern __shared__ double2 fsm[];
     const int L1 = 1 << lp1, L2 = 1 << lp2, RB = 1 << lrb;
@@ -214,9 +276,9 @@ __global__ __launch_bounds__(kFftThreads) void g2fft_pass2_kernel(const double2 
         s_first = blockIdx.y;
         s_count = 1;
     } else {
-        const int slot = blockIdx.y >> 1, which = blockIdx.y & 1;
-        s_first = slot * (np + 1) + (which ? np : 0);
-        s_count = which ? 1 : np;
+        const int slot = blockIdx.y / (nparts + 1), q = blockIdx.y % (nparts + 1);
+        s_first = slot * (np + 1) + (q < nparts ? q * ppb : np);
+        s_count = q < nparts ? std::min(ppb, np - q * ppb) : 1;
     }
     double acc[kFftPerThread];
 #pragma unroll
@@ -228,7 +290,7 @@ __global__ __launch_bounds__(kFftThreads) void g2fft_pass2_kernel(const double2 
             const int g = e >> lp2, c = e & (L2 - 1);
             buf[(bitrev(c, lp2) << lrb) + g] = src[(int64_t)(b0 + g) * L2 + c];
         }
-        lds_fft(buf, tw, lp2, lrb);
+        lds_fft(buf, tw, lp2, lrb, INV ? 1.0 : -1.0);
 #pragma unroll
         for (int i = 0; i < kFftPerThread; ++i) {
             const int e = threadIdx.x + i * kFftThreads;
@@ -291,7 +353,7 @@ FftPlan fft_plan(int64_t n) {
 xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
                            int64_t n, double *z) {
     const int cpt = (f->k + 15) / 16;
-    const size_t lds = ((size_t)16 * cpt * kZFrames + (size_t)kZChunk * 16 * cpt) * sizeof(double);
+    const size_t lds = ((size_t)16 * cpt * kZFrames + (size_t)kZChunk * 16 * cpt + kZFrames) * sizeof(double);
     dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)nb);
 #define XPCS_Z(c)                                                                                                \
     case c:                                                                                                      \
@@ -337,12 +399,19 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
     const FftPlan pl = fft_plan(n);
     const int64_t L = pl.L;
     // ROIs per batch: z, the pass-1 output of every signal, spectra and sums
-    const size_t per_roi = (size_t)k * n * 8 + (size_t)(np + 1) * L * 16 + (size_t)2 * L * 8 + (size_t)2 * n * 8;
+    // pass 2 splits a ROI's column pairs over nparts blocks per row chunk (partial
+    // spectra summed by the inverse pass 1) so that the grid fills the chip
+    const int rows = 1 << (pl.lp1 - pl.lrb);
+    int ppb = np;
+    while (ppb > 1 && (int64_t)rows * std::min(nr, 64) * ((np + ppb - 1) / ppb) < 4096) ppb = (ppb + 1) / 2;
+    const int nparts = (np + ppb - 1) / ppb;
+    const size_t per_roi = (size_t)k * n * 8 + (size_t)(np + 1) * L * 16 + (size_t)(nparts + 1) * L * 8 +
+                           (size_t)2 * n * 8;
     const size_t cap = (size_t)2 << 30;
     const int nb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nr, cap / per_roi));
     const size_t b_l = (size_t)nr * k * k * 8;
     const size_t b_z = (size_t)nb * k * n * 8, b_x = (size_t)nb * (np + 1) * L * 16;
-    const size_t b_s = (size_t)nb * 2 * L * 8, b_o = (size_t)nb * 2 * n * 8;
+    const size_t b_s = (size_t)nb * (nparts + 1) * L * 8, b_o = (size_t)nb * 2 * n * 8;
     xpcs_status st = ws_reserve(ctx, align_up(b_l, 256) + align_up(b_z, 256) + align_up(b_x, 256) +
                                          align_up(b_s, 256) + align_up(b_o, 256) + 5 * 256);
     if (st) return st;
@@ -352,7 +421,7 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
     auto *spec = static_cast<double *>(ws_take(ctx, b_s));
     auto *sums = static_cast<double *>(ws_take(ctx, b_o));
     if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * k * k, k, nr, Lr))) return st;
-    const size_t lds1 = ((size_t)(1 << (pl.lp1 + pl.lcc)) + (1 << pl.lp1) / 2) * sizeof(double2);
+    const size_t lds1 = ((size_t)(1 << (pl.lp1 + pl.lcc)) + (1 << pl.lp1) / 2 + (1 << pl.lp2)) * sizeof(double2);
     const size_t lds2 = ((size_t)(1 << (pl.lp2 + pl.lrb)) + (1 << pl.lp2) / 2) * sizeof(double2);
     const unsigned g1x = (unsigned)(1 << (pl.lp2 - pl.lcc)), g2x = (unsigned)(1 << (pl.lp1 - pl.lrb));
     for (int s0 = 0; s0 < nr; s0 += nb) {
@@ -362,23 +431,27 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
             if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
         }
         {
-            Phase phase_(ctx, "g2fft_forward");
+            Phase phase_(ctx, "g2fft_pass1");
             hipLaunchKernelGGL(g2fft_pass1_kernel<false>, dim3(g1x, (unsigned)(m * (np + 1))), dim3(kFftThreads),
-                               lds1, ctx->stream, z, f->roi_sum, f->N, r0 + s0, t0, n, k, np, nullptr, pl.lp1,
+                               lds1, ctx->stream, z, f->roi_sum, f->N, r0 + s0, t0, n, k, np, nullptr, 0, pl.lp1,
                                pl.lp2, pl.lcc, X1);
             XPCS_LAUNCH_CHECK(ctx, "g2fft_pass1");
-            hipLaunchKernelGGL(g2fft_pass2_kernel<false>, dim3(g2x, (unsigned)(m * 2)), dim3(kFftThreads), lds2,
-                               ctx->stream, X1, np, pl.lp1, pl.lp2, pl.lrb, n, spec);
+        }
+        {
+            Phase phase_(ctx, "g2fft_pass2");
+            hipLaunchKernelGGL(g2fft_pass2_kernel<false>, dim3(g2x, (unsigned)(m * (nparts + 1))),
+                               dim3(kFftThreads), lds2, ctx->stream, X1, np, nparts, ppb, pl.lp1, pl.lp2, pl.lrb, n,
+                               spec);
             XPCS_LAUNCH_CHECK(ctx, "g2fft_pass2");
         }
         {
             Phase phase_(ctx, "g2fft_inverse");
             hipLaunchKernelGGL(g2fft_pass1_kernel<true>, dim3(g1x, (unsigned)(m * 2)), dim3(kFftThreads), lds1,
-                               ctx->stream, nullptr, nullptr, f->N, 0, 0, n, k, np, spec, pl.lp1, pl.lp2, pl.lcc,
-                               X1);
+                               ctx->stream, nullptr, nullptr, f->N, 0, 0, n, k, np, spec, nparts, pl.lp1, pl.lp2,
+                               pl.lcc, X1);
             XPCS_LAUNCH_CHECK(ctx, "g2fft_pass1_inverse");
             hipLaunchKernelGGL(g2fft_pass2_kernel<true>, dim3(g2x, (unsigned)(m * 2)), dim3(kFftThreads), lds2,
-                               ctx->stream, X1, np, pl.lp1, pl.lp2, pl.lrb, n, sums);
+                               ctx->stream, X1, np, nparts, ppb, pl.lp1, pl.lp2, pl.lrb, n, sums);
             XPCS_LAUNCH_CHECK(ctx, "g2fft_pass2_inverse");
             hipLaunchKernelGGL(g2fft_finish_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0,
                                ctx->stream, sums, n, s0, g2, npairs);
