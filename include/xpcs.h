@@ -228,6 +228,25 @@ xpcs_status g2_from_two_time(xpcs_ctx *ctx, const void *C, int32_t c_dtype, int6
 xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1,
                             double *g2, int64_t *npairs);
 
+/* Relaxation fit of g2 (Sec. 3.1, Eq. 13): g2(tau) = B + beta exp(-2 Gamma tau)
+ * with baseline B, contrast beta and Gamma = 1 / t0 (t0 the relaxation time in
+ * frames), fitted by unweighted least squares to each ROI's g2 over the lags
+ * tau_lo <= tau < tau_hi that have pairs (npairs > 0) and a finite value.
+ * Levenberg-Marquardt in FP64, one workgroup per ROI, at most max_iter steps.
+ * g2: device, n_roi x n doubles (ROI-major, as correlate_two_time writes them).
+ * npairs: device, n_roi x n int64, or NULL (then only finite values count).
+ * p0: device, n_roi x 3 doubles (B, beta, Gamma) to start from, or NULL: then
+ *     B = the last valid g2, beta = max(first - last, 1e-3), Gamma = 1 / mean lag.
+ * params: device, n_roi x 3 doubles (B, beta, Gamma); NaN for a ROI with fewer
+ *     than three valid lags.
+ * status: device, n_roi int32: the number of accepted or rejected steps taken,
+ *     -1 for fewer than three valid lags.
+ * Errors: EINVAL (null g2/params/status, n or n_roi, lag range outside [0, n),
+ * max_iter outside [0, 10000]). */
+xpcs_status fit_relaxation(xpcs_ctx *ctx, const double *g2, const int64_t *npairs, int64_t n, int32_t n_roi,
+                           int64_t tau_lo, int64_t tau_hi, const double *p0, int32_t max_iter, double *params,
+                           int32_t *status);
+
 /* ------------------------------------------------------------------ online streams
  * The paper's online strategy (Sec. 2.2): the encoding basis is fixed beforehand
  * (e.g. from compress_frames on an earlier measurement or on the first frames of

@@ -222,6 +222,35 @@ def g2_from_factors(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: in
     return g2, npairs
 
 
+def fit_relaxation(ctx: Context, g2: torch.Tensor, npairs: Optional[torch.Tensor] = None, tau_lo: int = 1,
+                   tau_hi: Optional[int] = None, p0: Optional[torch.Tensor] = None,
+                   max_iter: int = 200) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Fit g2(tau) = B + beta exp(-2 Gamma tau) per ROI over lags [tau_lo, tau_hi).
+
+    g2: (n_roi, n) float64 device tensor (npairs the matching int64 tensor or None);
+    p0: optional (n_roi, 3) float64 start.  Returns (params (n_roi, 3) = B, beta,
+    Gamma; status (n_roi,) int32 = steps taken, -1 with fewer than three lags).
+    """
+    if g2.dim() == 1:
+        g2 = g2[None]
+        npairs = None if npairs is None else npairs[None]
+    if g2.dtype != torch.float64 or not g2.is_contiguous():
+        raise ValueError("g2 must be a contiguous float64 tensor")
+    n_roi, n = g2.shape
+    tau_hi = n if tau_hi is None else tau_hi
+    if npairs is not None and (npairs.dtype != torch.int64 or tuple(npairs.shape) != (n_roi, n)
+                               or not npairs.is_contiguous()):
+        raise ValueError("npairs must be a contiguous int64 tensor shaped like g2")
+    if p0 is not None and (p0.dtype != torch.float64 or tuple(p0.shape) != (n_roi, 3) or not p0.is_contiguous()):
+        raise ValueError("p0 must be a contiguous (n_roi, 3) float64 tensor")
+    params = torch.empty((n_roi, 3), dtype=torch.float64, device=g2.device)
+    status = torch.empty((n_roi,), dtype=torch.int32, device=g2.device)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.fit_relaxation(ctx.handle, _ptr(g2), _ptr(npairs), n, n_roi, tau_lo, tau_hi, _ptr(p0),
+                                     max_iter, _ptr(params), _ptr(status)))
+    return params, status
+
+
 def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int,
                            roi: int = L.XPCS_ALL_ROIS, t0: int = 0, t1: Optional[int] = None,
                            want_c: bool = True, c_dtype=torch.float32, want_g2: bool = True,
