@@ -32,7 +32,8 @@ constexpr int kFftElems = 2048;             // complex elements per LDS tile (32
 constexpr int kFftPerThread = kFftElems / kFftThreads;
 constexpr int kFftMaxLog = 22;              // L <= 2^22, i.e. windows up to 2^21 frames
 constexpr int kZFrames = 64;                // frames per block of the z kernel
-constexpr int kZChunk = 32;                 // rows of L_R staged at a time
+constexpr int kZChunk = 16;                 // rows of L_R staged at a time
+constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
 constexpr int kZMaxK = 192;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -118,74 +119,88 @@ __device__ void fill_twiddles(double2 *tw, int lp, double sgn) {
     for (int m = threadIdx.x; m < P / 2; m += kFftThreads) tw[m] = expi_2pi((double)m, (double)P, sgn);
 }
 
-// z[(slot k + j) n + t] = sqrt(|R|) sum_a (V[t0+t][a] sigma_a / S[t0+t]) L[a][j]
-// (FP64, zero where S = 0).  Thread (fr, cb) forms frames 4 fr .. 4 fr + 3 and
-// columns cb + 16 j, j < CPT; the block's result is transposed through LDS so
-// that every column is stored as a contiguous run of frames.
-template <int CPT>
+// z[(slot k + j) n + t] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] sigma_a L[a][j]
+// (FP64, zero where S = 0).  W = V diag(sigma) is shared by every ROI, so a block
+// stages a 64-frame slice of it in LDS once and forms Z for kZRois ROIs in turn;
+// lane = frame, wave w owns columns [w CW, (w + 1) CW), rows of L_R are staged
+// kZChunk at a time and read as wave-wide broadcasts, and every column is stored
+// as a contiguous run of 64 frames.
+template <int CW>
 __global__ __launch_bounds__(256) void g2fft_z_kernel(
     const float *__restrict__ V, const double *__restrict__ sigma, const int64_t *__restrict__ roi_sum,
-    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int64_t t0,
-    int64_t n, double *__restrict__ z) {
+    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int nb,
+    int64_t t0, int64_t n, double *__restrict__ z) {
     extern __shared__ double zsm[];
-    const int kc = 16 * CPT;
-    double *wT = zsm;                                 // [kc][kZFrames]
-    double *Lc = zsm + (size_t)kc * kZFrames;         // [kZChunk][kc]
-    const int slot = blockIdx.y, roi = r0 + slot;
+    constexpr int kw = 4 * CW;                        // columns covered (>= k)
+    constexpr int kPre = kZChunk * kw / 256;          // chunk elements per thread
+    double *wT = zsm;                                 // [k][kZFrames]
+    double *Lc = wT + (size_t)k * kZFrames;           // [kZChunk][kw]
+    double *fscale = Lc + (size_t)kZChunk * kw;       // [kZRois][kZFrames]
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
-    double *fscale = Lc + (size_t)kZChunk * kc;       // [kZFrames]: sqrt(|R|) / S, 0 where S = 0
-    const int64_t *Sr = roi_sum + (int64_t)roi * N;
-    const double *L = Lr + (int64_t)slot * k * k;
-    if (threadIdx.x < kZFrames) {
-        const int64_t tl = f0 + threadIdx.x;
-        const int64_t sv = tl < n ? Sr[t0 + tl] : 0;
-        fscale[threadIdx.x] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kc * kZFrames / 256; ++i) {
-        const int idx = threadIdx.x + 256 * i;
+    const int slot0 = blockIdx.y * kZRois;
+    const int nrb = min(nb - slot0, kZRois);
+    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
         const int a = idx / kZFrames, f = idx % kZFrames;
         const int64_t tl = f0 + f;
-        const float v = (tl < n && a < k) ? V[(int64_t)a * N + t0 + tl] : 0.0f;
-        wT[idx] = (a < k) ? (double)v * sigma[a] * fscale[f] : 0.0;
+        wT[idx] = tl < n ? (double)V[(int64_t)a * N + t0 + tl] * sigma[a] : 0.0;
     }
-    const int fr = threadIdx.x >> 4, cb = threadIdx.x & 15;
-    double acc[4][CPT];
+    for (int idx = threadIdx.x; idx < nrb * kZFrames; idx += 256) {
+        const int q = idx / kZFrames, f = idx % kZFrames;
+        const int roi = r0 + slot0 + q;
+        const int64_t tl = f0 + f;
+        const int64_t sv = tl < n ? roi_sum[(int64_t)roi * N + t0 + tl] : 0;
+        fscale[idx] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
+    }
+    // steps = (ROI, chunk of L_R rows); the next step's chunk is loaded into
+    // registers while the current one is used
+    const int nch = (k + kZChunk - 1) / kZChunk, steps = nrb * nch;
+    double pre[kPre];
+    auto load = [&](int st) {
+        const int q = st / nch, a0 = (st % nch) * kZChunk;
+        const double *L = Lr + (int64_t)(slot0 + q) * k * k;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
-    for (int a0 = 0; a0 < k; a0 += kZChunk) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kZChunk * kc; idx += 256) {
-            const int aa = idx / kc, b = idx % kc;
-            Lc[idx] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
+        for (int i = 0; i < kPre; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            const int aa = idx / kw, b = idx % kw;
+            pre[i] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
         }
+    };
+    load(0);
+    double acc[CW];
+    for (int st = 0; st < steps; ++st) {
+        const int q = st / nch, a0 = (st % nch) * kZChunk;
+        __syncthreads();                              // the previous step is done with Lc
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) Lc[threadIdx.x + 256 * i] = pre[i];
         __syncthreads();
-        const int na = k - a0 < kZChunk ? k - a0 : kZChunk;
-#pragma unroll 8
+        if (st + 1 < steps) load(st + 1);
+        if (a0 == 0) {
+#pragma unroll
+            for (int m = 0; m < CW; ++m) acc[m] = 0.0;
+        }
+        const int na = min(kZChunk, k - a0);
+        const double *lw = Lc + wave * CW;
         for (int aa = 0; aa < na; ++aa) {
-            const double2 x01 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr]);
-            const double2 x23 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kZFrames + 4 * fr + 2]);
-            const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+            const double x = wT[(a0 + aa) * kZFrames + lane];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const double l = Lc[aa * kc + cb + 16 * j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = fma(x[i], l, acc[i][j]);
+            for (int m = 0; m < CW; m += 2) {
+                const double2 l = *reinterpret_cast<const double2 *>(lw + aa * kw + m);
+                acc[m] = fma(x, l.x, acc[m]);
+                acc[m + 1] = fma(x, l.y, acc[m + 1]);
             }
         }
-    }
-    __syncthreads();                                  // wT is reused for the transposed result
+        const int64_t t = f0 + lane;
+        if (a0 + kZChunk >= k && t < n) {              // last chunk of this ROI: store its columns
+            const double sc = fscale[q * kZFrames + lane];
+            const int slot = slot0 + q;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) wT[(cb + 16 * j) * kZFrames + 4 * fr + i] = acc[i][j];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
-        const int b = idx / kZFrames, f = idx % kZFrames;
-        if (f0 + f < n) z[((int64_t)slot * k + b) * n + f0 + f] = wT[idx];
+            for (int m = 0; m < CW; ++m) {
+                const int j = wave * CW + m;
+                if (j < k) z[((int64_t)slot * k + j) * n + t] = sc * acc[m];
+            }
+        }
     }
 }
 
@@ -352,17 +367,16 @@ FftPlan fft_plan(int64_t n) {
 
 xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
                            int64_t n, double *z) {
-    const int cpt = (f->k + 15) / 16;
-    const size_t lds = ((size_t)16 * cpt * kZFrames + (size_t)kZChunk * 16 * cpt + kZFrames) * sizeof(double);
-    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)nb);
+    const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
+    const size_t lds = ((size_t)f->k * kZFrames + (size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double);
+    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)((nb + kZRois - 1) / kZRois));
 #define XPCS_Z(c)                                                                                                \
     case c:                                                                                                      \
         hipLaunchKernelGGL(g2fft_z_kernel<c>, grid, dim3(256), lds, ctx->stream, f->V, f->sigma, f->roi_sum,      \
-                           f->roi_npix, Lr, f->N, f->k, r0, t0, n, z);                                           \
+                           f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z);                                       \
         break;
-    switch (cpt) {
-        XPCS_Z(1) XPCS_Z(2) XPCS_Z(3) XPCS_Z(4) XPCS_Z(5) XPCS_Z(6)
-        XPCS_Z(7) XPCS_Z(8) XPCS_Z(9) XPCS_Z(10) XPCS_Z(11) XPCS_Z(12)
+    switch (cw) {
+        XPCS_Z(8) XPCS_Z(16) XPCS_Z(24) XPCS_Z(32) XPCS_Z(40) XPCS_Z(48)
         default:
             return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in g2_from_factors");
     }
