@@ -277,9 +277,11 @@ def g2_only(api, torch, ctx, f, reps=5):
 
     t_tile, (_, g_tile, n_tile) = run(lambda: api.correlate_two_time(ctx, f, want_c=False))
     t_fft, (g_fft, n_fft) = run(lambda: api.g2_from_factors(ctx, f))
+    t_stats, (m_s, s_s, _) = run(lambda: api.two_time_stats(ctx, f))
     gt, gf = g_tile.cpu().numpy(), g_fft.cpu().numpy()
     ok = n_tile.cpu().numpy() > 0
-    return {"tile_ms": t_tile, "fft_ms": t_fft,
+    return {"tile_ms": t_tile, "fft_ms": t_fft, "ttc_stats_ms": t_stats,
+            "ttc_mean_roi0": float(m_s[0]), "ttc_std_roi0": float(s_s[0]),
             "npairs_equal": bool(torch.equal(n_tile, n_fft)),
             "g2_max_rel_diff": float(np.max(np.abs(gf[ok] - gt[ok]) / np.abs(gt[ok])))}
 

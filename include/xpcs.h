@@ -228,6 +228,20 @@ xpcs_status g2_from_two_time(xpcs_ctx *ctx, const void *C, int32_t c_dtype, int6
 xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1,
                             double *g2, int64_t *npairs);
 
+/* Background level of the compressed two-time correlation without forming C~
+ * (Sec. 3.2: a correlation peak counts as observable when it is stronger than
+ * twice the standard deviation of the TTC): mean and population standard
+ * deviation of C~_R over the off-diagonal pairs (t1 != t2) of valid frames
+ * (S_R > 0) in the window [t0, t1).  With Z[t] = sqrt(|R|) (W[t] / S_R[t]) L_R and
+ * C~_R = Z Z^T, the sum of the entries is |sum_t Z[t]|^2 and the sum of their
+ * squares |Z^T Z|_F^2; the diagonal's share is subtracted.  FP64 throughout.
+ * mean, stdev: device, one double per ROI of the call (NaN without pairs);
+ * npairs: device int64 per ROI, the number of entries averaged.
+ * Errors: EINVAL (null factors or outputs, window, roi), EUNSUPPORTED (k > 192),
+ * EBUDGET, ENOMEM. */
+xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1,
+                           double *mean, double *stdev, int64_t *npairs);
+
 /* Relaxation fit of g2 (Sec. 3.1, Eq. 13): g2(tau) = B + beta exp(-2 Gamma tau)
  * with baseline B, contrast beta and Gamma = 1 / t0 (t0 the relaxation time in
  * frames), fitted by unweighted least squares to each ROI's g2 over the lags

@@ -35,6 +35,8 @@ What is computed, and where it comes from:
   on arrival; each frame's correlations with the earlier frames by lag (band
   rows) and g2 by lag over the whole history.
 * Relaxation fit (Sec. 3.1, Eq. 13): g2(tau) = B + beta * exp(-2 Gamma tau).
+* Background level of a TTC (Sec. 3.2): mean and standard deviation of its
+  off-diagonal valid entries.
 """
 
 from __future__ import annotations
@@ -136,6 +138,24 @@ def g2_from_two_time(C: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
         if npairs[tau]:
             g2[tau] = float(d[ok].sum()) / npairs[tau]
     return g2, npairs
+
+
+def two_time_stats(C: np.ndarray) -> Tuple[float, float, int]:
+    """Background level of a two-time matrix (Sec. 3.2: a correlation peak counts as
+    observable when it is stronger than twice the standard deviation of the TTC).
+
+    Reading: mean and (population) standard deviation of C over the valid
+    (non-NaN) entries off the main diagonal -- the diagonal t1 = t2 carries the
+    shot noise of a frame with itself, as g2 at lag 0 does.  Returns
+    (mean, std, number of entries); NaN statistics when there is no such entry.
+    """
+    C = np.asarray(C, dtype=np.float64)
+    off = ~np.eye(C.shape[0], dtype=bool)
+    v = C[off & ~np.isnan(C)]
+    if v.size == 0:
+        return float("nan"), float("nan"), 0
+    m = float(v.mean())
+    return m, float(np.sqrt(((v - m) ** 2).mean())), int(v.size)
 
 
 # ----------------------------------------------------------------------------

@@ -83,6 +83,7 @@ SIGNATURES = {
     "g2_from_two_time": (_ST, [_P, _P, _I32, _I64, _I64, _P, _P]),
     "g2_from_factors": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _P]),
     "fit_relaxation": (_ST, [_P, _P, _P, _I64, _I32, _I64, _I64, _P, _I32, _P, _P]),
+    "two_time_stats": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _P, _P]),
     "xpcs_enable_phase_timing": (_ST, [_P, _I32]),
     "xpcs_phase_times": (_ST, [_P, _I32, _P, _P, _P, ctypes.POINTER(_I32)]),
     "xpcs_stream_open": (_ST, [_P, ctypes.POINTER(XpcsStreamDesc), ctypes.POINTER(_P)]),

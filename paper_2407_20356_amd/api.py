@@ -222,6 +222,22 @@ def g2_from_factors(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: in
     return g2, npairs
 
 
+def two_time_stats(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: int = 0,
+                   t1: Optional[int] = None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Mean and standard deviation of the compressed TTC over off-diagonal valid pairs,
+    per ROI, without forming C.  Returns (mean, std, npairs), each of shape (nr,)."""
+    t1 = f.N if t1 is None else t1
+    nr = f.n_roi if roi == L.XPCS_ALL_ROIS else 1
+    mean = torch.empty((nr,), dtype=torch.float64, device=ctx.device)
+    std = torch.empty((nr,), dtype=torch.float64, device=ctx.device)
+    npairs = torch.empty((nr,), dtype=torch.int64, device=ctx.device)
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.two_time_stats(ctx.handle, ctypes.byref(fs), roi, t0, t1, _ptr(mean), _ptr(std),
+                                     _ptr(npairs)))
+    return mean, std, npairs
+
+
 def fit_relaxation(ctx: Context, g2: torch.Tensor, npairs: Optional[torch.Tensor] = None, tau_lo: int = 1,
                    tau_hi: Optional[int] = None, p0: Optional[torch.Tensor] = None,
                    max_iter: int = 200) -> Tuple[torch.Tensor, torch.Tensor]:

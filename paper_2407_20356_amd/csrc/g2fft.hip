@@ -344,6 +344,66 @@ __global__ void g2fft_finish_kernel(const double *__restrict__ sums, int64_t n, 
     if (npairs) npairs[o] = cnt;
 }
 
+// Mean and standard deviation of C~_R over its off-diagonal valid pairs
+// (t1 != t2, both frames with S_R > 0), from Z alone: with s = sum_t Z[t] and
+// G = Z^T Z, the sum of all entries of C~_R = Z Z^T is |s|^2 and the sum of their
+// squares is |G|_F^2; the diagonal contributes sum_t |Z[t]|^2 and sum_t |Z[t]|^4.
+// One block per ROI; fixed-order reductions in FP64.
+__device__ double block_sum256(double v, double *red) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    __syncthreads();                                  // red is free (previous use finished)
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void ttc_stats_kernel(const double *__restrict__ z, const double *__restrict__ G,
+                                                        const int64_t *__restrict__ roi_sum, int64_t N, int r0,
+                                                        int64_t t0, int64_t n, int k, int slot0,
+                                                        double *__restrict__ mean, double *__restrict__ stdev,
+                                                        int64_t *__restrict__ npairs) {
+    __shared__ double red[4];
+    const int slot = blockIdx.x;
+    const double *zs = z + (int64_t)slot * k * n;
+    const int64_t *Sr = roi_sum + (int64_t)(r0 + slot) * N + t0;
+    double d1 = 0.0, d2 = 0.0, nv = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += 256) {
+        double d = 0.0;
+        for (int j = 0; j < k; ++j) d = fma(zs[(int64_t)j * n + t], zs[(int64_t)j * n + t], d);
+        d1 += d;
+        d2 = fma(d, d, d2);
+        nv += Sr[t] > 0 ? 1.0 : 0.0;
+    }
+    d1 = block_sum256(d1, red);
+    d2 = block_sum256(d2, red);
+    nv = block_sum256(nv, red);
+    double s2 = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double sj = 0.0;
+        for (int64_t t = threadIdx.x; t < n; t += 256) sj += zs[(int64_t)j * n + t];
+        sj = block_sum256(sj, red);
+        s2 = fma(sj, sj, s2);
+    }
+    double g2s = 0.0;
+    const double *Gs = G + (int64_t)slot * k * k;
+    for (int e = threadIdx.x; e < k * k; e += 256) g2s = fma(Gs[e], Gs[e], g2s);
+    g2s = block_sum256(g2s, red);
+    if (threadIdx.x == 0) {
+        const double noff = nv * (nv - 1.0);
+        const int o = slot0 + slot;
+        npairs[o] = (int64_t)noff;
+        if (noff > 0.0) {
+            const double m = (s2 - d1) / noff;
+            const double var = (g2s - d2) / noff - m * m;
+            mean[o] = m;
+            stdev[o] = sqrt(var > 0.0 ? var : 0.0);
+        } else {
+            mean[o] = __builtin_nan("");
+            stdev[o] = __builtin_nan("");
+        }
+    }
+}
+
 struct FftPlan {
     int lp1, lp2, lcc, lrb;
     int64_t L;
@@ -471,6 +531,51 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
                                ctx->stream, sums, n, s0, g2, npairs);
             XPCS_LAUNCH_CHECK(ctx, "g2fft_finish");
         }
+    }
+    return XPCS_OK;
+}
+
+xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1, double *mean,
+                           double *stdev, int64_t *npairs) {
+    if (!ctx) return XPCS_EINVAL;
+    if (!f || !f->V || !f->sigma || !f->roi_npix || !f->roi_sum || !f->roi_gram)
+        return fail(ctx, XPCS_EINVAL, "factors or one of their buffers is NULL");
+    if (f->N <= 0 || f->M <= 0 || f->k < 1 || f->n_roi < 1) return fail(ctx, XPCS_EINVAL, "bad factor sizes");
+    if (!mean || !stdev || !npairs) return fail(ctx, XPCS_EINVAL, "mean, stdev and npairs must not be NULL");
+    if (roi != XPCS_ALL_ROIS && (roi < 0 || roi >= f->n_roi))
+        return fail(ctx, XPCS_EINVAL, "roi outside [0, n_roi) and not XPCS_ALL_ROIS");
+    if (t0 < 0 || t1 <= t0 || t1 > f->N) return fail(ctx, XPCS_EINVAL, "window must satisfy 0 <= t0 < t1 <= N");
+    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in two_time_stats");
+    (void)hipSetDevice(ctx->device);
+    ws_begin(ctx);
+    const int64_t n = t1 - t0;
+    const int r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
+    const int nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
+    const int k = f->k;
+    const size_t per_roi = (size_t)k * n * 8 + (size_t)k * k * 8;
+    const size_t cap = (size_t)1 << 30;
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nr, cap / per_roi));
+    const size_t b_l = (size_t)nr * k * k * 8, b_z = (size_t)nb * k * n * 8, b_g = (size_t)nb * k * k * 8;
+    xpcs_status st = ws_reserve(ctx, align_up(b_l, 256) + align_up(b_z, 256) + align_up(b_g, 256) + 3 * 256);
+    if (st) return st;
+    auto *Lr = static_cast<double *>(ws_take(ctx, b_l));
+    auto *z = static_cast<double *>(ws_take(ctx, b_z));
+    auto *G = static_cast<double *>(ws_take(ctx, b_g));
+    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * k * k, k, nr, Lr))) return st;
+    for (int s0 = 0; s0 < nr; s0 += nb) {
+        const int m = std::min(nb, nr - s0);
+        {
+            Phase phase_(ctx, "g2fft_z");
+            if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
+        }
+        for (int q = 0; q < m; ++q)
+            if ((st = launch_tsgram(ctx, z + (int64_t)q * k * n, true, n, n, k, nullptr, nullptr, 1,
+                                    G + (int64_t)q * k * k)))
+                return st;
+        Phase phase_(ctx, "ttc_stats");
+        hipLaunchKernelGGL(ttc_stats_kernel, dim3((unsigned)m), dim3(256), 0, ctx->stream, z, G, f->roi_sum, f->N,
+                           r0 + s0, t0, n, k, s0, mean, stdev, npairs);
+        XPCS_LAUNCH_CHECK(ctx, "ttc_stats");
     }
     return XPCS_OK;
 }

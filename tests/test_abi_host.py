@@ -119,6 +119,7 @@ def test_null_context_is_rejected_without_a_gpu(lib):
     assert lib.g2_from_two_time(None, None, 10, 1, 1, None, None) == -1
     assert lib.g2_from_factors(None, None, 0, 0, 1, None, None) == -1
     assert lib.fit_relaxation(None, None, None, 1, 1, 0, 1, None, 10, None, None) == -1
+    assert lib.two_time_stats(None, None, 0, 0, 1, None, None, None) == -1
     assert lib.xpcs_sync(None) == -1
     assert lib.xpcs_last_error(None) == b""
     assert lib.xpcs_stream_open(None, None, None) == -1

@@ -288,3 +288,39 @@ def test_special_cases_of_the_model():
     # lag 0 carries shot noise: ~ 1 + beta + 1/mu
     g2, _ = _tiny_g2(14, beta=0.2, tau_c=50.0, mu=0.05)
     assert g2[0] == pytest.approx(1.0 + 0.2 + 1.0 / 0.05, rel=0.05)
+
+
+# --------------------------------------------------------------------------- TTC background level
+
+def test_two_time_stats_hand_worked():
+    # off-diagonal entries 1, 3, 1, 5, 3, 5: mean 3, population variance 16 / 6
+    C = np.array([[9.0, 1.0, 3.0], [1.0, 9.0, 5.0], [3.0, 5.0, 9.0]])
+    m, s, cnt = O.two_time_stats(C)
+    assert cnt == 6 and m == 3.0
+    assert abs(s - math.sqrt(8.0 / 3.0)) < 1e-15
+    m, s, cnt = O.two_time_stats(np.full((4, 4), 2.5))
+    assert (m, s, cnt) == (2.5, 0.0, 12)
+    assert math.isnan(O.two_time_stats(np.ones((1, 1)))[0])
+
+
+def test_two_time_stats_brute_force_and_closed_form():
+    # brute force with a frame without photons (NaN row and column), then the
+    # closed form the library uses: with C = Z Z^T and s = sum of Z's rows,
+    # sum of all entries = |s|^2, sum of squares = |Z^T Z|_F^2, minus the diagonal
+    rng = np.random.default_rng(5)
+    Z = rng.standard_normal((9, 4))
+    C = Z @ Z.T
+    C[3, :] = np.nan
+    C[:, 3] = np.nan
+    vals = [C[i, j] for i in range(9) for j in range(9) if i != j and not math.isnan(C[i, j])]
+    mean = sum(vals) / len(vals)
+    std = math.sqrt(sum((v - mean) ** 2 for v in vals) / len(vals))
+    m, s, cnt = O.two_time_stats(C)
+    assert cnt == len(vals) == 8 * 7
+    assert abs(m - mean) < 1e-12 and abs(s - std) < 1e-12
+    Zv = np.delete(Z, 3, axis=0)
+    d = (Zv * Zv).sum(axis=1)
+    n = Zv.shape[0]
+    m2 = (Zv.sum(axis=0) @ Zv.sum(axis=0) - d.sum()) / (n * (n - 1))
+    q2 = (np.linalg.norm(Zv.T @ Zv) ** 2 - (d * d).sum()) / (n * (n - 1))
+    assert abs(m2 - m) < 1e-12 and abs(math.sqrt(q2 - m2 * m2) - s) < 1e-12
