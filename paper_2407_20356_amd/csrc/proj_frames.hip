@@ -29,6 +29,22 @@ __global__ void proj_frames_reduce_kernel(const float *__restrict__ part, int64_
 
 using proj::pf_rb;
 
+namespace proj {
+bool dispatch_pf_u8_lo_plain(int ncb, int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
+                             const unsigned short *qh, const unsigned short *ql, int64_t ldq, int64_t chunk, int nfb,
+                             int ncols, float *part, bool vec);
+}  // namespace proj
+
+namespace {
+// A residual-term pass over uint8 counts with more operand fragments per K step
+// than this runs as several launches over groups of column blocks (the counts are
+// read once per launch, and a uint8 pass is bound by the MFMA and LDS work per
+// count, not by its bytes): measured at 1024 x 1024 px x 20,000 frames, k = 128,
+// the two launches take 28.9 ms where the single wide one took 31.7 ms.  uint16
+// passes stay single (their count bytes dominate).
+constexpr int kMaxFragsPerLaunch = 13;
+}  // namespace
+
 FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
     FrameProj p;
     const int nib = (n_ind + 15) / 16;
@@ -59,24 +75,56 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
     const int ncb = L / 16, nib = (n_ind + 15) / 16;
     if (nib > 4) return fail(ctx, XPCS_EUNSUPPORTED, "more than 64 ROIs in the fused ROI sums");
     const bool lo = q_lo != nullptr;
-    const int rb = pf_rb(ncb, nib, lo);
-    if (rb * 64 != plan.frames_per_block)
-        return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
-    const int64_t fbf = (int64_t)rb * 64;
-    const int nfb = (int)((N + fbf - 1) / fbf);
-    const int64_t nblocks = (int64_t)nfb * plan.nchunks;
-    if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
     const size_t esz = dtype == XPCS_U8 ? 1 : 2;
     const bool vec = (M % 8 == 0) && ((uintptr_t)frames % (8 * esz) == 0) &&
                      (nib == 0 || (uintptr_t)labels % 16 == 0);
-    const bool ok =
-        dtype == XPCS_U8
-            ? proj::dispatch_pf_u8(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
-                                   plan.chunk, nfb, plan.ncols, part, vec)
-            : proj::dispatch_pf_u16(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
-                                    plan.chunk, nfb, plan.ncols, part, vec);
-    if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
-    XPCS_LAUNCH_CHECK(ctx, "proj_frames");
+    const int frags = ncb * (lo ? 2 : 1) + nib;
+    if (!lo || frags <= kMaxFragsPerLaunch || dtype != XPCS_U8) {
+        const int rb = pf_rb(ncb, nib, lo);
+        if (rb * 64 != plan.frames_per_block)
+            return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
+        const int64_t fbf = (int64_t)rb * 64;
+        const int nfb = (int)((N + fbf - 1) / fbf);
+        const int64_t nblocks = (int64_t)nfb * plan.nchunks;
+        if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
+        const bool ok =
+            dtype == XPCS_U8
+                ? proj::dispatch_pf_u8(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
+                                       plan.chunk, nfb, plan.ncols, part, vec)
+                : proj::dispatch_pf_u16(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq,
+                                        labels, plan.chunk, nfb, plan.ncols, part, vec);
+        if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
+        XPCS_LAUNCH_CHECK(ctx, "proj_frames");
+        return XPCS_OK;
+    }
+    // wide residual-term pass: groups of column blocks, the last one with the
+    // indicator columns; each group writes its own columns of the partial sums
+    const int groups = (frags + kMaxFragsPerLaunch - 1) / kMaxFragsPerLaunch;
+    int c0 = 0;
+    for (int g = 0; g < groups; ++g) {
+        const int last = g == groups - 1;
+        const int ncb_g = last ? ncb - c0 : (ncb - c0 + (groups - g) - 1) / (groups - g);
+        const int nib_g = last ? nib : 0;
+        if (ncb_g < 1 || ncb_g > 6 || 2 * ncb_g + nib_g > kMaxFragsPerLaunch)
+            return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
+        const int rb = pf_rb(ncb_g, nib_g, true);
+        const int64_t fbf = (int64_t)rb * 64;
+        const int nfb = (int)((N + fbf - 1) / fbf);
+        const int64_t nblocks = (int64_t)nfb * plan.nchunks;
+        if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
+        const unsigned short *qh = q_hi + (int64_t)16 * c0 * ldq, *ql = q_lo + (int64_t)16 * c0 * ldq;
+        float *pg = part + 16 * c0;
+        bool ok;
+        if (nib_g)
+            ok = proj::dispatch_pf_u8(ncb_g, nib_g, true, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                      labels, plan.chunk, nfb, plan.ncols, pg, vec);
+        else
+            ok = proj::dispatch_pf_u8_lo_plain(ncb_g, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                               plan.chunk, nfb, plan.ncols, pg, vec);
+        if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
+        XPCS_LAUNCH_CHECK(ctx, "proj_frames");
+        c0 += ncb_g;
+    }
     return XPCS_OK;
 }
 
