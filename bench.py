@@ -377,7 +377,7 @@ def main():
 
     ctx = api.Context(0)
     f = api.Factors.empty(M, N, k, n_roi, dev)
-    C = torch.empty((n_roi, N, N), dtype=torch.float32, device=dev)
+    C = api.empty_two_time(dev, n_roi, N)          # rows padded to whole 128-byte lines (ldc = 10016)
     g2 = torch.empty((n_roi, N), dtype=torch.float64, device=dev)
     npairs = torch.empty((n_roi, N), dtype=torch.int64, device=dev)
 

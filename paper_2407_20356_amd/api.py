@@ -171,6 +171,25 @@ def _alloc_outputs(device, nr, nw, want_c, c_dtype, want_g2):
     return C, g2, npairs
 
 
+def empty_two_time(device, nr: int, nw: int, c_dtype=torch.float32) -> torch.Tensor:
+    """An uninitialised (nr, nw, nw) output whose rows start on 128-byte boundaries:
+    a view of an (nr, nw, ldc) buffer, ldc = nw rounded up to 128 bytes.  Whole-line
+    rows let the tile pass write C without partial cache lines."""
+    per = 128 // torch.empty((), dtype=c_dtype).element_size()
+    ldc = (nw + per - 1) // per * per
+    return torch.empty((nr, nw, ldc), dtype=c_dtype, device=device)[:, :, :nw]
+
+
+def _row_stride(C: Optional[torch.Tensor], nr: int, nw: int) -> int:
+    """Row stride (ldc) of an (nr, nw, nw) output, which may be a view of a wider
+    (nr, nw, ldc) buffer whose rows are padded (e.g. to whole cache lines)."""
+    if C is None:
+        return nw
+    if tuple(C.shape) != (nr, nw, nw) or C.stride(2) != 1 or C.stride(1) < nw or C.stride(0) != nw * C.stride(1):
+        raise ValueError("C must be (n_roi, nw, nw) with unit column stride and ROI stride nw * row stride")
+    return C.stride(1)
+
+
 def _c_code(c_dtype) -> int:
     if c_dtype == torch.float32:
         return L.XPCS_F32
@@ -197,7 +216,7 @@ def correlate_two_time(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0:
     ctx.bind_stream()
     ctx.check(ctx.lib.correlate_two_time(ctx.handle, ctypes.byref(fs), roi, t0, t1, _ptr(C),
                                          _c_code(C.dtype) if C is not None else L.XPCS_F32,
-                                         C.shape[-1] if C is not None else nw, _ptr(g2), _ptr(npairs)))
+                                         _row_stride(C, nr, nw), _ptr(g2), _ptr(npairs)))
     return C, g2, npairs
 
 
@@ -285,7 +304,7 @@ def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.
     ctx.bind_stream()
     ctx.check(ctx.lib.correlate_two_time_raw(
         ctx.handle, _ptr(frames), _frame_dtype(frames), M, N, _ptr(roi_label), n_roi, roi, t0, t1, _ptr(C),
-        _c_code(C.dtype) if C is not None else L.XPCS_F32, C.shape[-1] if C is not None else nw,
+        _c_code(C.dtype) if C is not None else L.XPCS_F32, _row_stride(C, nr, nw),
         _ptr(g2), _ptr(npairs), _ptr(gram)))
     return C, g2, npairs, gram
 

@@ -279,3 +279,33 @@ def test_deterministic(ctx):
         outs.append((to_np(f.U), to_np(f.V), to_np(C), to_np(g2)))
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_padded_row_stride_output_equals_contiguous(ctx):
+    """C written into an (n_roi, nw, ldc) buffer with rows padded to 128 bytes (the
+    benchmark's layout) holds exactly the contiguous result, for the compressed and
+    the raw path, FP32 and FP64, and the padding columns are left untouched."""
+    import torch
+    from paper_2407_20356_amd import api
+    F = synth.speckle_frames_numpy(48 * 40, 300, 0.2, 0.2, 20.0, "u8", seed=13)
+    labels = synth.annular_labels(48, 40, 3, r_in=2.0)
+    Fd, Ld = to_dev(F), to_dev(labels)
+    f = api.compress_frames(ctx, Fd, Ld, 3, k=16, seed=4)
+    for dt in (torch.float32, torch.float64):
+        say(f"padded row stride, {dt}")
+        Cp = api.empty_two_time(ctx.device, 3, 290, dt)
+        assert Cp.stride(1) == (320 if dt == torch.float32 else 304)
+        Cp.as_strided((3, 290, Cp.stride(1)), Cp.stride()).fill_(-5.0)
+        C0, g0, n0 = api.correlate_two_time(ctx, f, t0=10, t1=300, c_dtype=dt)
+        _, g1, n1 = api.correlate_two_time(ctx, f, t0=10, t1=300, C=Cp,
+                                           g2=torch.empty_like(g0), npairs=torch.empty_like(n0))
+        R0, _, _, _ = api.correlate_two_time_raw(ctx, Fd, Ld, 3, t0=10, t1=300, c_dtype=dt)
+        Rp = api.empty_two_time(ctx.device, 3, 290, dt)
+        api.correlate_two_time_raw(ctx, Fd, Ld, 3, t0=10, t1=300, C=Rp, g2=torch.empty_like(g0),
+                                   npairs=torch.empty_like(n0))
+        ctx.sync()
+        np.testing.assert_array_equal(np.nan_to_num(to_np(Cp), nan=-7.0), np.nan_to_num(to_np(C0), nan=-7.0))
+        np.testing.assert_array_equal(to_np(g1), to_np(g0))
+        np.testing.assert_array_equal(np.nan_to_num(to_np(Rp), nan=-7.0), np.nan_to_num(to_np(R0), nan=-7.0))
+        pad = to_np(Cp.as_strided((3, 290, Cp.stride(1)), Cp.stride()))[:, :, 290:]
+        assert np.all(pad == -5.0)
