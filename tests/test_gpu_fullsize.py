@@ -1,6 +1,7 @@
 """Parity at the full benchmark size, in the launch configuration bench.py times:
 262,144 px x 10,000 frames (uint16, mu = 0.1, beta = 0.2, tau_c split 200 / 20 by
-ROI), 36 annular ROIs, k = 64, every ROI's C in FP32 with g2 fused.
+ROI), 36 annular ROIs, k = 64 (and k = 128 for the offline step), every ROI's C in FP32 with g2 fused,
+written with rows padded to whole 128-byte lines as the benchmark writes it.
 
 Online basis (Sec. 2.2): the oracle builds the basis from a 512-frame stretch of
 the synthetic series, the library compresses all 10,000 frames with it and
@@ -57,6 +58,16 @@ def _host_chunks(frames, chunk=500):
         yield t0, frames[t0:t0 + chunk].view(torch.int16).cpu().numpy().view(np.uint16)
 
 
+def _correlate_padded(ctx, f, N, R):
+    """correlate_two_time into C with rows padded to 128 bytes, as the benchmark does."""
+    import torch
+    from paper_2407_20356_amd import api
+    C = api.empty_two_time(ctx.device, R, N)
+    g2 = torch.empty((R, N), dtype=torch.float64, device=ctx.device)
+    npairs = torch.empty((R, N), dtype=torch.int64, device=ctx.device)
+    return api.correlate_two_time(ctx, f, C=C, g2=g2, npairs=npairs)
+
+
 def test_fullsize_online_basis_against_oracle(setup):
     import torch
     from paper_2407_20356_amd import api
@@ -68,7 +79,7 @@ def test_fullsize_online_basis_against_oracle(setup):
     Ud = torch.from_numpy(np.ascontiguousarray(U32.T)).to(frames.device)
     say("compress (online basis) + correlate all ROIs, C f32 + fused g2")
     f = api.compress_frames(ctx, frames, labels_d, R, k=k, basis=Ud)
-    C, g2, npairs = api.correlate_two_time(ctx, f)
+    C, g2, npairs = _correlate_padded(ctx, f, N, R)
     ctx.sync()
     Uo = U32.astype(np.float64)
     npix = O.roi_pixel_counts(labels, R)
@@ -104,14 +115,15 @@ def test_fullsize_online_basis_against_oracle(setup):
         np.testing.assert_allclose(g2f[r][ok], gref[ok], rtol=1e-3, err_msg=f"FFT g2 roi {r}")
 
 
-def test_fullsize_offline_step_properties(setup):
+@pytest.mark.parametrize("k", [64, 128])
+def test_fullsize_offline_step_properties(setup, k):
     import torch
     from paper_2407_20356_amd import api
     ctx, frames, labels, labels_d = setup
-    M, N, R, k = SPEC.n_pixels, SPEC.n_frames, SPEC.n_roi, 64
-    say("compress (offline, k=64, oversample 16, q=1) + correlate all ROIs, as the benchmark step")
+    M, N, R = SPEC.n_pixels, SPEC.n_frames, SPEC.n_roi
+    say(f"compress (offline, k={k}, oversample 16, q=1) + correlate all ROIs, as the benchmark step")
     f = api.compress_frames(ctx, frames, labels_d, R, k=k, seed=7)
-    C, g2, npairs = api.correlate_two_time(ctx, f)
+    C, g2, npairs = _correlate_padded(ctx, f, N, R)
     ctx.sync()
     U = to_np(f.U).T.astype(np.float64)
     assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-5
