@@ -136,3 +136,38 @@ def test_stream_g2_divides_by_history_length(monkeypatch):
         return np.where(ok, band, 0.0).sum(axis=1) / band.shape[1], npairs
     monkeypatch.setattr(O, "stream_g2", wrong)
     _expect_pin_failure(spins.test_full_window_g2_equals_diagonal_mean_of_full_matrix)
+
+
+def test_ttc_stats_include_the_diagonal(monkeypatch):
+    def wrong(C):
+        C = np.asarray(C, dtype=np.float64)
+        v = C[~np.isnan(C)]
+        return float(v.mean()), float(v.std()), int(v.size)
+    monkeypatch.setattr(OX, "two_time_stats", wrong)
+    monkeypatch.setattr(O, "two_time_stats", wrong)
+    _expect_pin_failure(pins.test_two_time_stats_hand_worked)
+
+
+def test_ttc_stats_sample_std(monkeypatch):
+    orig = OX.two_time_stats
+
+    def wrong(C):
+        m, s, n = orig(C)
+        return m, (s * np.sqrt(n / (n - 1)) if n > 1 else s), n
+    monkeypatch.setattr(OX, "two_time_stats", wrong)
+    monkeypatch.setattr(O, "two_time_stats", wrong)
+    _expect_pin_failure(pins.test_two_time_stats_hand_worked)
+
+
+def test_relaxation_fit_drops_the_factor_two(monkeypatch):
+    from scipy.optimize import least_squares
+
+    def wrong(g2, taus, p0=None):
+        taus = np.asarray(taus, dtype=np.float64)
+        y = np.asarray(g2, dtype=np.float64)
+        p0 = p0 or (float(y[-1]), float(max(y[0] - y[-1], 1e-3)), 1.0 / max(taus.mean(), 1.0))
+        sol = least_squares(lambda p: p[0] + p[1] * np.exp(-p[2] * taus) - y, np.asarray(p0), method="lm")
+        return tuple(float(x) for x in sol.x)
+    monkeypatch.setattr(OX, "siegert_fit", wrong)
+    monkeypatch.setattr(O, "siegert_fit", wrong)
+    _expect_pin_failure(pins.test_siegert_relation_recovered)
