@@ -148,6 +148,16 @@ __device__ __forceinline__ void write_diag_partials(double *g2_part, int *g2_cnt
 // chunk (every realistic case: with counts <= 40 a chunk holds 1.3 M pixels);
 // WIDE = true the others, folding int32 chunk sums into int64.  Both are
 // launched; each block leaves at once when its ROI belongs to the other.
+// Raw-Gram operand stages: kRawKs pixels (bytes) of 256 rows per stage, LDS row
+// pitch kRawRp (16 bytes of padding against bank conflicts), two buffers.
+constexpr int kRawKs = 128;
+constexpr int kRawRp = kRawKs + 16;
+constexpr int kRawParts = kRawKs / 16;                   // 16-byte pieces per row
+constexpr int kRawPer = 2 * kTile * kRawParts / 256;     // pieces per thread
+constexpr int kRawBufBytes = 2 * kTile * kRawRp;
+constexpr int kRawLdsBytes = 2 * kRawBufBytes > kHalf * kPitch * 8 ? 2 * kRawBufBytes : kHalf * kPitch * 8;
+constexpr int kRawLdsDoubles = kRawLdsBytes / 8;
+
 __device__ __forceinline__ int64_t raw_chunk_pixels(const int *__restrict__ amax, int64_t qlen) {
     const int am = *amax;
     // int32 accumulation is exact while (pixels per chunk) * amax^2 < 2^31.
@@ -162,7 +172,9 @@ __device__ __forceinline__ void raw_gram_tile(
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int slot,
     int64_t ntiles, int64_t kc, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
     int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
-    __shared__ double stage[kHalf * kPitch];
+    // the operand stages (two buffers of 256 rows x kRawKs bytes) share the LDS of
+    // the epilogue's staging buffer
+    __shared__ __attribute__((aligned(16))) double stage[kRawLdsDoubles];
     const int roi = r0 + slot;
     const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
     const bool diag = bi == bj;
@@ -172,16 +184,6 @@ __device__ __forceinline__ void raw_gram_tile(
 
     const int64_t q0 = off[roi], qlen = off[roi + 1] - off[roi];
 
-    const int8_t *arow[4], *brow[4];
-    bool aok[4], bok[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        int64_t ta = i0 + 64 * wr + 16 * b + lr, tb = j0 + 64 * wc + 16 * b + lr;
-        aok[b] = ta < nw;
-        bok[b] = tb < nw;
-        arow[b] = xs + (aok[b] ? ta : 0) * ldx + q0 + 16 * lg;
-        brow[b] = xs + (bok[b] ? tb : 0) * ldx + q0 + 16 * lg;
-    }
     // int32 MFMA accumulators; the wide variant folds them into int64 per chunk.
     i32x4 acc[4][4];
     int64_t wide[WIDE ? 4 : 1][WIDE ? 4 : 1][WIDE ? 4 : 1];
@@ -198,22 +200,74 @@ __device__ __forceinline__ void raw_gram_tile(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (i32x4){0, 0, 0, 0};
 
-    if (!skip) {
-        for (int64_t c0 = 0; c0 < qlen; c0 += kc) {
-            const int64_t c1 = c0 + kc < qlen ? c0 + kc : qlen;
-            for (int64_t k = c0; k < c1; k += 64) {
+    // Stages of kRawKs pixels: the tile's rows (128 of the row block, 128 of the
+    // column block; 128 in all on the diagonal) are loaded once per block into
+    // registers one stage ahead, written to the other LDS buffer after the current
+    // stage's MFMAs, one barrier per stage.  Chunks of kc pixels (int32
+    // exactness) are whole stages; pixels past a chunk's end load as zero.
+    int8_t *ops = reinterpret_cast<int8_t *>(stage);
+    const int64_t kcs = WIDE ? kc : (qlen + kRawKs - 1) / kRawKs * kRawKs;   // pixels per chunk, in stages
+    const int spc = (int)((kcs + kRawKs - 1) / kRawKs);
+    const int nchunk = (int)((qlen + kcs - 1) / kcs);
+    const int nstage = nchunk * spc;
+    const int jrow0 = diag ? 0 : kTile;
+    i32x4 nxt[kRawPer];
+    auto fetch = [&](int st) {
+        const int64_t c = st / spc;
+        const int64_t k = c * kcs + (int64_t)(st % spc) * kRawKs;
+        const int64_t c1 = (c + 1) * kcs < qlen ? (c + 1) * kcs : qlen;
+#pragma unroll
+        for (int q = 0; q < kRawPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            const int row = u / kRawParts, part = u % kRawParts;
+            const int64_t t = row < kTile ? i0 + row : j0 + (row - kTile);
+            const int64_t kk = k + 16 * part;
+            i32x4 v = {0, 0, 0, 0};
+            if (t < nw && kk < c1 && !(diag && row >= kTile))
+                v = *reinterpret_cast<const i32x4 *>(xs + t * ldx + q0 + kk);
+            nxt[q] = v;
+        }
+    };
+    auto put = [&](int buf) {
+        int8_t *dst = ops + buf * kRawBufBytes;
+#pragma unroll
+        for (int q = 0; q < kRawPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            const int row = u / kRawParts, part = u % kRawParts;
+            *reinterpret_cast<i32x4 *>(dst + row * kRawRp + 16 * part) = nxt[q];
+        }
+    };
+    if (nstage > 0) {
+        fetch(0);
+        put(0);
+        __syncthreads();
+    }
+    for (int st = 0; st < nstage; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nstage) fetch(st + 1);
+        if (!skip) {
+            const int8_t *src = ops + buf * kRawBufBytes;
+#pragma unroll
+            for (int h = 0; h < kRawKs / 64; ++h) {
                 i32x4 av[4], bv[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    av[b] = aok[b] ? *reinterpret_cast<const i32x4 *>(arow[b] + k) : (i32x4){0, 0, 0, 0};
-                    bv[b] = bok[b] ? *reinterpret_cast<const i32x4 *>(brow[b] + k) : (i32x4){0, 0, 0, 0};
+                    const int rb = jrow0 + 64 * wc + 16 * b + lr;
+                    bv[b] = *reinterpret_cast<const i32x4 *>(src + rb * kRawRp + 64 * h + 16 * lg);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int ra = 64 * wr + 16 * a + lr;
+                    av[a] = *reinterpret_cast<const i32x4 *>(src + ra * kRawRp + 64 * h + 16 * lg);
                 }
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b) acc[a][b] = mfma_i8(av[a], bv[b], acc[a][b]);
             }
-            if constexpr (WIDE) {
+        }
+        if constexpr (WIDE) {
+            if (st % spc == spc - 1) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -224,6 +278,8 @@ __device__ __forceinline__ void raw_gram_tile(
                     }
             }
         }
+        if (st + 1 < nstage) put(buf ^ 1);
+        __syncthreads();
     }
     auto gval = [&](int a, int b, int e) -> int64_t {
         if constexpr (WIDE)
