@@ -260,6 +260,7 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
         for (int e = 0; e < 4; ++e) px[ps][e] = live[ps] ? perm[q + e] : -1;
     }
     const int64_t tend = tb + kGatherT < nw ? tb + kGatherT : nw;
+#pragma unroll 4
     for (int64_t tl = tb; tl < tend; ++tl) {
         const T *fr = frames + (t0 + tl) * M;
 #pragma unroll
