@@ -349,46 +349,85 @@ __global__ void g2fft_finish_kernel(const double *__restrict__ sums, int64_t n, 
 // G = Z^T Z, the sum of all entries of C~_R = Z Z^T is |s|^2 and the sum of their
 // squares is |G|_F^2; the diagonal contributes sum_t |Z[t]|^2 and sum_t |Z[t]|^4.
 // One block per ROI; fixed-order reductions in FP64.
-__device__ double block_sum256(double v, double *red) {
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
-    __syncthreads();                                  // red is free (previous use finished)
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+constexpr int kStatFrames = 256;                  // frames per block of the partial-sum kernel
+
+// Per (frame chunk, ROI) partial sums: column sums s_j over the chunk's frames
+// (a wave-wide reduction per column, four waves combined in LDS), and the
+// chunk's sum of |Z[t]|^2, sum of |Z[t]|^4 and count of valid frames.
+__global__ __launch_bounds__(256) void ttc_partial_kernel(const double *__restrict__ z,
+                                                          const int64_t *__restrict__ roi_sum, int64_t N, int r0,
+                                                          int64_t t0, int64_t n, int k, double *__restrict__ ps,
+                                                          double *__restrict__ pd) {
+    __shared__ double red[4][kZMaxK + 3];
+    const int slot = blockIdx.y, chunk = blockIdx.x, nch = gridDim.x;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const double *zs = z + (int64_t)slot * k * n;
+    const int64_t t = (int64_t)chunk * kStatFrames + threadIdx.x;
+    const bool in = t < n;
+    double d = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double v = in ? zs[(int64_t)j * n + t] : 0.0;
+        d = fma(v, v, d);
+        double w = v;
+        for (int off = kWave / 2; off > 0; off >>= 1) w += __shfl_xor(w, off, kWave);
+        if (lane == 0) red[wv][j] = w;
+    }
+    double x[3] = {d, d * d, (in && roi_sum[(int64_t)(r0 + slot) * N + t0 + t] > 0) ? 1.0 : 0.0};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double w = x[q];
+        for (int off = kWave / 2; off > 0; off >>= 1) w += __shfl_xor(w, off, kWave);
+        if (lane == 0) red[wv][kZMaxK + q] = w;
+    }
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    for (int j = threadIdx.x; j < k; j += 256)
+        ps[((int64_t)slot * nch + chunk) * k + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+    if (threadIdx.x < 3)
+        pd[((int64_t)slot * nch + chunk) * 3 + threadIdx.x] =
+            red[0][kZMaxK + threadIdx.x] + red[1][kZMaxK + threadIdx.x] + red[2][kZMaxK + threadIdx.x] +
+            red[3][kZMaxK + threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void ttc_stats_kernel(const double *__restrict__ z, const double *__restrict__ G,
-                                                        const int64_t *__restrict__ roi_sum, int64_t N, int r0,
-                                                        int64_t t0, int64_t n, int k, int slot0,
+// Mean and standard deviation of C~_R over its off-diagonal valid pairs
+// (t1 != t2, both frames with S_R > 0), from Z alone: with s = sum_t Z[t] and
+// G = Z^T Z, the sum of all entries of C~_R = Z Z^T is |s|^2 and the sum of their
+// squares is |G|_F^2; the diagonal contributes sum_t |Z[t]|^2 and sum_t |Z[t]|^4.
+// One block per ROI over the chunk partials, in a fixed order.
+__global__ __launch_bounds__(256) void ttc_stats_kernel(const double *__restrict__ ps, const double *__restrict__ pd,
+                                                        const double *__restrict__ G, int nch, int k, int slot0,
                                                         double *__restrict__ mean, double *__restrict__ stdev,
                                                         int64_t *__restrict__ npairs) {
-    __shared__ double red[4];
+    __shared__ double red[2][4];
     const int slot = blockIdx.x;
-    const double *zs = z + (int64_t)slot * k * n;
-    const int64_t *Sr = roi_sum + (int64_t)(r0 + slot) * N + t0;
-    double d1 = 0.0, d2 = 0.0, nv = 0.0;
-    for (int64_t t = threadIdx.x; t < n; t += 256) {
-        double d = 0.0;
-        for (int j = 0; j < k; ++j) d = fma(zs[(int64_t)j * n + t], zs[(int64_t)j * n + t], d);
-        d1 += d;
-        d2 = fma(d, d, d2);
-        nv += Sr[t] > 0 ? 1.0 : 0.0;
-    }
-    d1 = block_sum256(d1, red);
-    d2 = block_sum256(d2, red);
-    nv = block_sum256(nv, red);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     double s2 = 0.0;
-    for (int j = 0; j < k; ++j) {
+    for (int j = threadIdx.x; j < k; j += 256) {
         double sj = 0.0;
-        for (int64_t t = threadIdx.x; t < n; t += 256) sj += zs[(int64_t)j * n + t];
-        sj = block_sum256(sj, red);
+        for (int c = 0; c < nch; ++c) sj += ps[((int64_t)slot * nch + c) * k + j];
         s2 = fma(sj, sj, s2);
     }
     double g2s = 0.0;
     const double *Gs = G + (int64_t)slot * k * k;
     for (int e = threadIdx.x; e < k * k; e += 256) g2s = fma(Gs[e], Gs[e], g2s);
-    g2s = block_sum256(g2s, red);
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        s2 += __shfl_xor(s2, off, kWave);
+        g2s += __shfl_xor(g2s, off, kWave);
+    }
+    if (lane == 0) {
+        red[0][wv] = s2;
+        red[1][wv] = g2s;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        s2 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        g2s = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        double d1 = 0.0, d2 = 0.0, nv = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            const double *p = pd + ((int64_t)slot * nch + c) * 3;
+            d1 += p[0];
+            d2 += p[1];
+            nv += p[2];
+        }
         const double noff = nv * (nv - 1.0);
         const int o = slot0 + slot;
         npairs[o] = (int64_t)noff;
@@ -446,6 +485,12 @@ xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *L
 }
 
 }  // namespace
+}  // namespace xpcs
+
+namespace xpcs {
+// Batched Gram launcher of the small-step library (defined with launch_tsgram).
+xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
+                                  int nbatch, int64_t bstride, double *G);
 }  // namespace xpcs
 
 using namespace xpcs;
@@ -552,15 +597,20 @@ xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, in
     const int r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
     const int nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
     const int k = f->k;
-    const size_t per_roi = (size_t)k * n * 8 + (size_t)k * k * 8;
+    const int nch = (int)((n + kStatFrames - 1) / kStatFrames);
+    const size_t per_roi = (size_t)k * n * 8 + (size_t)k * k * 8 + (size_t)nch * (k + 3) * 8;
     const size_t cap = (size_t)1 << 30;
     const int nb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nr, cap / per_roi));
     const size_t b_l = (size_t)nr * k * k * 8, b_z = (size_t)nb * k * n * 8, b_g = (size_t)nb * k * k * 8;
-    xpcs_status st = ws_reserve(ctx, align_up(b_l, 256) + align_up(b_z, 256) + align_up(b_g, 256) + 3 * 256);
+    const size_t b_ps = (size_t)nb * nch * k * 8, b_pd = (size_t)nb * nch * 3 * 8;
+    xpcs_status st = ws_reserve(ctx, align_up(b_l, 256) + align_up(b_z, 256) + align_up(b_g, 256) +
+                                         align_up(b_ps, 256) + align_up(b_pd, 256) + 5 * 256);
     if (st) return st;
     auto *Lr = static_cast<double *>(ws_take(ctx, b_l));
     auto *z = static_cast<double *>(ws_take(ctx, b_z));
     auto *G = static_cast<double *>(ws_take(ctx, b_g));
+    auto *ps = static_cast<double *>(ws_take(ctx, b_ps));
+    auto *pd = static_cast<double *>(ws_take(ctx, b_pd));
     if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * k * k, k, nr, Lr))) return st;
     for (int s0 = 0; s0 < nr; s0 += nb) {
         const int m = std::min(nb, nr - s0);
@@ -568,13 +618,13 @@ xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, in
             Phase phase_(ctx, "g2fft_z");
             if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
         }
-        for (int q = 0; q < m; ++q)
-            if ((st = launch_tsgram(ctx, z + (int64_t)q * k * n, true, n, n, k, nullptr, nullptr, 1,
-                                    G + (int64_t)q * k * k)))
-                return st;
+        if ((st = launch_tsgram_batched(ctx, z, true, n, n, k, m, (int64_t)k * n, G))) return st;
         Phase phase_(ctx, "ttc_stats");
-        hipLaunchKernelGGL(ttc_stats_kernel, dim3((unsigned)m), dim3(256), 0, ctx->stream, z, G, f->roi_sum, f->N,
-                           r0 + s0, t0, n, k, s0, mean, stdev, npairs);
+        hipLaunchKernelGGL(ttc_partial_kernel, dim3((unsigned)nch, (unsigned)m), dim3(256), 0, ctx->stream, z,
+                           f->roi_sum, f->N, r0 + s0, t0, n, k, ps, pd);
+        XPCS_LAUNCH_CHECK(ctx, "ttc_partial");
+        hipLaunchKernelGGL(ttc_stats_kernel, dim3((unsigned)m), dim3(256), 0, ctx->stream, ps, pd, G, nch, k, s0,
+                           mean, stdev, npairs);
         XPCS_LAUNCH_CHECK(ctx, "ttc_stats");
     }
     return XPCS_OK;

@@ -191,7 +191,12 @@ constexpr int kGramMfmaThreads = 512;     // 8 waves: two per SIMD
 constexpr int kGramMfmaWaves = kGramMfmaThreads / 64;
 template <typename TA, int NCB>
 __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda,
-                                                          int ncols, int pw, double *__restrict__ part) {
+                                                          int ncols, int pw, double *__restrict__ part,
+                                                          int64_t bstride) {
+    // blockIdx.y selects one matrix of a batch (A + y * bstride), partials after
+    // the previous matrices' gridDim.x parts
+    A += (int64_t)blockIdx.y * bstride;
+    part += (int64_t)blockIdx.y * gridDim.x * pw * pw;
     constexpr int NT = NCB * (NCB + 1) / 2;
     constexpr int W = NCB * 16;
     __shared__ double red[W * W];
@@ -1350,10 +1355,12 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     dim3 grid(nparts, nseg);
     // without segments and up to 80 columns: the FP64 MFMA kernel
     if (!seg_off && !row_idx && nseg == 1 && ncols <= 80) {
+        const int nbatch = 1;
+        const int64_t bstride = 0;
         const int ncb = (ncols + 15) / 16;
 #define XPCS_TSGM(T, C)                                                                                       \
-    hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts), dim3(kGramMfmaThreads), 0, ctx->stream,         \
-                       static_cast<const T *>(A), rows, lda, ncols, pw, part)
+    hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride)
 #define XPCS_TSGM_T(T)                \
     switch (ncb) {                    \
         case 1: XPCS_TSGM(T, 1); break; \
@@ -1396,6 +1403,54 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     XPCS_LAUNCH_CHECK(ctx, "tsgram");
     hipLaunchKernelGGL(tsgram_reduce_kernel, dim3((ncols * ncols + 31) / 32, nseg), dim3(256), 0, ctx->stream,
                        part, nparts, ncols, pw, G);
+    XPCS_LAUNCH_CHECK(ctx, "tsgram_reduce");
+    return XPCS_OK;
+}
+
+// Grams of nbatch tall matrices A + b * bstride (rows x ncols, column stride lda):
+// G + b * ncols^2.  One launch of the FP64 MFMA kernel for up to 80 columns,
+// otherwise one Gram after the other.
+xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
+                                  int nbatch, int64_t bstride, double *G) {
+    if (ncols > 80 || nbatch == 1) {
+        xpcs_status st;
+        const size_t esz = a_f64 ? 8 : 4;
+        for (int b = 0; b < nbatch; ++b)
+            if ((st = launch_tsgram(ctx, static_cast<const char *>(A) + (size_t)b * bstride * esz, a_f64, rows, lda,
+                                    ncols, nullptr, nullptr, 1, G + (int64_t)b * ncols * ncols)))
+                return st;
+        return XPCS_OK;
+    }
+    Phase phase_(ctx, "tsgram");
+    const int pw = (ncols + 3) / 4 * 4;
+    int nparts = (int)(rows / 64);
+    if (nparts > 256 / nbatch + 1) nparts = 256 / nbatch + 1;
+    if (nparts < 1) nparts = 1;
+    xpcs_status st;
+    double *part = static_cast<double *>(scratch_get(ctx, (size_t)nbatch * nparts * pw * pw * sizeof(double), &st));
+    if (!part) return st;
+    const int ncb = (ncols + 15) / 16;
+#define XPCS_TSGB(T, C)                                                                                          \
+    hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride)
+#define XPCS_TSGB_T(T)                 \
+    switch (ncb) {                     \
+        case 1: XPCS_TSGB(T, 1); break; \
+        case 2: XPCS_TSGB(T, 2); break; \
+        case 3: XPCS_TSGB(T, 3); break; \
+        case 4: XPCS_TSGB(T, 4); break; \
+        default: XPCS_TSGB(T, 5); break; \
+    }
+    if (a_f64) {
+        XPCS_TSGB_T(double)
+    } else {
+        XPCS_TSGB_T(float)
+    }
+#undef XPCS_TSGB_T
+#undef XPCS_TSGB
+    XPCS_LAUNCH_CHECK(ctx, "tsgram_mfma");
+    hipLaunchKernelGGL(tsgram_reduce_kernel, dim3((ncols * ncols + 31) / 32, nbatch), dim3(256), 0, ctx->stream, part,
+                       nparts, ncols, pw, G);
     XPCS_LAUNCH_CHECK(ctx, "tsgram_reduce");
     return XPCS_OK;
 }
