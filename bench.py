@@ -9,7 +9,9 @@ FP32 and g2 fused into the same pass, on the 512 x 512 px x 10,000-frame,
 it.  Inputs are generated on the device before timing; nothing is copied
 from the host inside the timed region.
 
-Prints one JSON line (see the README of the measurement in the design doc).
+Prints one JSON line: the metric and its value (frames/s of the compressed
+step), the roofline object of the dominant kernel, the CPU oracle baseline, and
+the raw path, stream, serving, precision and g2-without-C measurements.
 """
 
 from __future__ import annotations
@@ -344,7 +346,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built.", file=sys.stderr)
+              "a design only and not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
