@@ -22,7 +22,8 @@ LIB = os.path.join(PKG, "libxpcs.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# Packed FP32 instructions are disabled for all device code (see the design notes).
+# Packed FP32 instructions are disabled for all device code: the compiler would otherwise form
+# them from plain float code, and the kernels are validated without them.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-parameter"]
