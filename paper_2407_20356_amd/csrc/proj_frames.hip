@@ -5,24 +5,30 @@
 namespace xpcs {
 namespace {
 
-__global__ void proj_frames_reduce_kernel(const float *__restrict__ part, int64_t nch, int64_t N, int ncols,
-                                          int L, int n_ind, double *__restrict__ Z, int64_t ldz,
-                                          int64_t *__restrict__ S) {
+// Z[j][t] (or the exact ROI sum of an indicator column) = sum over pixel chunks c
+// of part[c][t][j]: a wave takes 64 consecutive outputs and the chunks c = wave
+// (mod 4); the four wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void proj_frames_reduce_kernel(const float *__restrict__ part, int64_t nch,
+                                                                 int64_t N, int ncols, int L, int n_ind,
+                                                                 double *__restrict__ Z, int64_t ldz,
+                                                                 int64_t *__restrict__ S) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t total = N * ncols;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = idx / ncols;
-        const int j = (int)(idx % ncols);
-        const bool isq = j < L;
-        const bool isind = S && j >= L && j - L < n_ind;
-        if (!isq && !isind) continue;
-        double s = 0.0;
-        for (int64_t c = 0; c < nch; ++c) s += (double)part[(c * N + t) * ncols + j];
-        if (isq)
-            Z[(int64_t)j * ldz + t] = s;
-        else
-            S[(int64_t)(j - L) * N + t] = (int64_t)__builtin_rint(s);
-    }
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (idx < total)
+        for (int64_t c = wv; c < nch; c += 4) s += (double)part[c * total + idx];
+    red[wv][lane] = s;
+    __syncthreads();
+    if (wv != 0 || idx >= total) return;
+    s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    const int64_t t = idx / ncols;
+    const int j = (int)(idx % ncols);
+    if (j < L)
+        Z[(int64_t)j * ldz + t] = s;
+    else if (S && j - L < n_ind)
+        S[(int64_t)(j - L) * N + t] = (int64_t)__builtin_rint(s);
 }
 
 }  // namespace
@@ -54,6 +60,9 @@ FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
     const int64_t nfb = (N + fbf - 1) / fbf;
     int64_t want = (2048 + nfb - 1) / nfb;                 // blocks ~ 2048
     if (want < 8) want = 8;
+    // few frames (an online push): at most 256 pixel chunks, so that the partial
+    // sums stay small next to the counts and their reduction stays short
+    if (want > 256) want = 256;
     int64_t chunk = (M + want - 1) / want;
     chunk = (chunk + 63) / 64 * 64;                        // a multiple of either K step
     if (chunk < 256) chunk = 256;
@@ -131,11 +140,11 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
 xpcs_status launch_proj_frames_reduce(xpcs_ctx *ctx, const float *part, const FrameProj &plan, int64_t N,
                                       int L, int n_ind, double *Z, int64_t ldz, int64_t *S) {
     Phase phase_(ctx, "proj_frames_reduce");
-    int64_t total = N * plan.ncols;
-    int grid = (int)((total + 255) / 256);
-    if (grid > 8192) grid = 8192;
-    hipLaunchKernelGGL(proj_frames_reduce_kernel, dim3(grid), dim3(256), 0, ctx->stream, part, plan.nchunks, N,
-                       plan.ncols, L, n_ind, Z, ldz, S);
+    const int64_t total = N * plan.ncols;
+    const int64_t grid = (total + 63) / 64;
+    if (grid > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection reduction too large");
+    hipLaunchKernelGGL(proj_frames_reduce_kernel, dim3((unsigned)grid), dim3(256), 0, ctx->stream, part,
+                       plan.nchunks, N, plan.ncols, L, n_ind, Z, ldz, S);
     XPCS_LAUNCH_CHECK(ctx, "proj_frames_reduce");
     return XPCS_OK;
 }
