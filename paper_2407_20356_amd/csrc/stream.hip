@@ -231,6 +231,8 @@ __global__ __launch_bounds__(256, 2) void stream_tile_kernel(
         const int64_t f = e < kTile ? t0 + e : s0 + (e - kTile);
         s_ok[e] = (f >= 0 && f < end) ? (int)valid[zbase + f % cap] : -1;   // -1: no such frame
     }
+    // every frame of the tile exists and has photons: the diagonal sums need no checks
+    const bool all_ok = __syncthreads_and(s_ok[threadIdx.x] == 1);
 
     i32x4 nxt[kZPer];
     auto fetch = [&](int k0) {
@@ -321,12 +323,18 @@ __global__ __launch_bounds__(256, 2) void stream_tile_kernel(
                 int lo = kHalf * h, hi = kHalf * h + kHalf;
                 if (lo < d) lo = d;                       // c = r - d >= 0
                 if (hi > kTile + d) hi = kTile + d;       // c < 128
-                for (int rr = lo; rr < hi; ++rr) {
-                    if (s_ok[rr] < 0 || s_ok[kTile + rr - d] < 0) continue;
-                    const float v = stage[(rr - kHalf * h) * kPitch + rr - d];
-                    if (v == v) {
-                        dsum += (double)v;
-                        dcnt += 1;
+                if (all_ok) {
+#pragma unroll 8
+                    for (int rr = lo; rr < hi; ++rr) dsum += (double)stage[(rr - kHalf * h) * kPitch + rr - d];
+                    dcnt += hi > lo ? hi - lo : 0;
+                } else {
+                    for (int rr = lo; rr < hi; ++rr) {
+                        if (s_ok[rr] < 0 || s_ok[kTile + rr - d] < 0) continue;
+                        const float v = stage[(rr - kHalf * h) * kPitch + rr - d];
+                        if (v == v) {
+                            dsum += (double)v;
+                            dcnt += 1;
+                        }
                     }
                 }
             }
