@@ -487,12 +487,6 @@ xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *L
 }  // namespace
 }  // namespace xpcs
 
-namespace xpcs {
-// Batched Gram launcher of the small-step library (defined with launch_tsgram).
-xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
-                                  int nbatch, int64_t bstride, double *G);
-}  // namespace xpcs
-
 using namespace xpcs;
 
 extern "C" {

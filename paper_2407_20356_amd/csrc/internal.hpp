@@ -218,6 +218,10 @@ xpcs_status launch_proj_frames_reduce(xpcs_ctx *ctx, const float *part, const Fr
 xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda,
                           int ncols, const int32_t *row_idx, const int64_t *seg_off, int nseg,
                           double *G);
+// Grams of nbatch tall matrices A + b * bstride (rows x ncols, column stride lda):
+// G + b * ncols^2; one launch of the FP64 MFMA kernel for up to 80 columns.
+xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
+                                  int nbatch, int64_t bstride, double *G);
 // Cholesky of G (n x n) with pivots below rel_tol*max(diag) dropped, and the
 // inverse of the factor: A * Rinv has orthonormal (or zero) columns.  Rinv is
 // upper triangular, column-major n x n.  Optionally Rinv <- Rprev * Rinv.
