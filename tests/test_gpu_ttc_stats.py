@@ -61,3 +61,33 @@ def test_ttc_stats_rejects_bad_arguments(ctx):
     for kw in (dict(t0=5, t1=5), dict(t0=0, t1=101), dict(roi=2)):
         with pytest.raises(api.XpcsError, match="EINVAL"):
             api.two_time_stats(ctx, f, **kw)
+
+
+def test_ttc_stats_and_fft_g2_edge_cases(ctx):
+    """k = 1; a one-frame window (no off-diagonal pair: NaN statistics, g2 of lag 0
+    only); a ROI whose frames all lack photons (NaN everywhere, no pairs)."""
+    from paper_2407_20356_amd import api
+    labels = synth.annular_labels(32, 40, 3, r_in=2.0)
+    F = synth.speckle_frames_numpy(32 * 40, 200, 0.3, 0.2, 20.0, "u8", seed=73)
+    F[:, labels == 2] = 0                              # ROI 2 never sees a photon
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 3, k=1, oversample=7, seed=6)
+    say("k=1: two_time_stats and g2_from_factors, full window and one frame")
+    mean, std, npairs = api.two_time_stats(ctx, f)
+    g2, npg = api.g2_from_factors(ctx, f)
+    m1, s1, n1 = api.two_time_stats(ctx, f, t0=50, t1=51)
+    g21, np1 = api.g2_from_factors(ctx, f, t0=50, t1=51)
+    ctx.sync()
+    mean, std, npairs, g2, npg = to_np(mean), to_np(std), to_np(npairs), to_np(g2), to_np(npg)
+    W = to_np(f.V).T.astype(np.float64) * to_np(f.sigma)
+    G, S, npix = to_np(f.roi_gram), to_np(f.roi_sum), to_np(f.roi_npix)
+    for r in range(2):
+        Cref = O.compressed_two_time_from_factors(W, G[r], S[r], int(npix[r]))
+        m, s, cnt = O.two_time_stats(Cref)
+        assert npairs[r] == cnt and abs(mean[r] - m) <= 1e-10 * abs(m) and abs(std[r] - s) <= 1e-8 * s
+        gref, nref = O.g2_fft_from_factors(W, G[r], S[r], int(npix[r]))
+        np.testing.assert_array_equal(npg[r], nref)
+        np.testing.assert_allclose(g2[r][nref > 0], gref[nref > 0], rtol=1e-9)
+    assert npairs[2] == 0 and np.isnan(mean[2]) and np.isnan(std[2])
+    assert np.all(npg[2] == 0) and np.all(np.isnan(g2[2]))
+    assert np.all(to_np(n1) == 0) and np.all(np.isnan(to_np(m1)))
+    assert to_np(np1)[0, 0] == 1 and np.all(to_np(np1)[2] == 0)
