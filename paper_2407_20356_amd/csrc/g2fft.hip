@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "zrows.hpp"
 
 namespace xpcs {
 namespace {
@@ -31,9 +32,6 @@ constexpr int kFftThreads = 256;
 constexpr int kFftElems = 2048;             // complex elements per LDS tile (32 KB)
 constexpr int kFftPerThread = kFftElems / kFftThreads;
 constexpr int kFftMaxLog = 22;              // L <= 2^22, i.e. windows up to 2^21 frames
-constexpr int kZFrames = 64;                // frames per block of the z kernel
-constexpr int kZChunk = 16;                 // rows of L_R staged at a time
-constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
 constexpr int kZMaxK = 192;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -117,91 +115,6 @@ __device__ void lds_fft(double2 *buf, const double2 *tw, int lp, int lg, double 
 __device__ void fill_twiddles(double2 *tw, int lp, double sgn) {
     const int P = 1 << lp;
     for (int m = threadIdx.x; m < P / 2; m += kFftThreads) tw[m] = expi_2pi((double)m, (double)P, sgn);
-}
-
-// z[(slot k + j) n + t] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] sigma_a L[a][j]
-// (FP64, zero where S = 0).  W = V diag(sigma) is shared by every ROI, so a block
-// stages a 64-frame slice of it in LDS once and forms Z for kZRois ROIs in turn;
-// lane = frame, wave w owns columns [w CW, (w + 1) CW), rows of L_R are staged
-// kZChunk at a time and read as wave-wide broadcasts, and every column is stored
-// as a contiguous run of 64 frames.
-template <int CW>
-__global__ __launch_bounds__(256) void g2fft_z_kernel(
-    const float *__restrict__ V, const double *__restrict__ sigma, const int64_t *__restrict__ roi_sum,
-    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int nb,
-    int64_t t0, int64_t n, double *__restrict__ z) {
-    extern __shared__ double zsm[];
-    constexpr int kw = 4 * CW;                        // columns covered (>= k)
-    constexpr int kPre = kZChunk * kw / 256;          // chunk elements per thread
-    double *wT = zsm;                                 // [k][kZFrames]
-    double *Lc = wT + (size_t)k * kZFrames;           // [kZChunk][kw]
-    double *fscale = Lc + (size_t)kZChunk * kw;       // [kZRois][kZFrames]
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
-    const int slot0 = blockIdx.y * kZRois;
-    const int nrb = min(nb - slot0, kZRois);
-    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
-        const int a = idx / kZFrames, f = idx % kZFrames;
-        const int64_t tl = f0 + f;
-        wT[idx] = tl < n ? (double)V[(int64_t)a * N + t0 + tl] * sigma[a] : 0.0;
-    }
-    for (int idx = threadIdx.x; idx < nrb * kZFrames; idx += 256) {
-        const int q = idx / kZFrames, f = idx % kZFrames;
-        const int roi = r0 + slot0 + q;
-        const int64_t tl = f0 + f;
-        const int64_t sv = tl < n ? roi_sum[(int64_t)roi * N + t0 + tl] : 0;
-        fscale[idx] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
-    }
-    // steps = (ROI, chunk of L_R rows); the next step's chunk is loaded into
-    // registers while the current one is used
-    const int nch = (k + kZChunk - 1) / kZChunk, steps = nrb * nch;
-    double pre[kPre];
-    auto load = [&](int st) {
-        const int q = st / nch, a0 = (st % nch) * kZChunk;
-        const double *L = Lr + (int64_t)(slot0 + q) * k * k;
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int idx = threadIdx.x + 256 * i;
-            const int aa = idx / kw, b = idx % kw;
-            pre[i] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
-        }
-    };
-    load(0);
-    double acc[CW];
-    for (int st = 0; st < steps; ++st) {
-        const int q = st / nch, a0 = (st % nch) * kZChunk;
-        __syncthreads();                              // the previous step is done with Lc
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) Lc[threadIdx.x + 256 * i] = pre[i];
-        __syncthreads();
-        if (st + 1 < steps) load(st + 1);
-        if (a0 == 0) {
-#pragma unroll
-            for (int m = 0; m < CW; ++m) acc[m] = 0.0;
-        }
-        const int na = min(kZChunk, k - a0);
-        const double *lw = Lc + wave * CW;
-        for (int aa = 0; aa < na; ++aa) {
-            const double x = wT[(a0 + aa) * kZFrames + lane];
-#pragma unroll
-            for (int m = 0; m < CW; m += 2) {
-                const double2 l = *reinterpret_cast<const double2 *>(lw + aa * kw + m);
-                acc[m] = fma(x, l.x, acc[m]);
-                acc[m + 1] = fma(x, l.y, acc[m + 1]);
-            }
-        }
-        const int64_t t = f0 + lane;
-        if (a0 + kZChunk >= k && t < n) {              // last chunk of this ROI: store its columns
-            const double sc = fscale[q * kZFrames + lane];
-            const int slot = slot0 + q;
-#pragma unroll
-            for (int m = 0; m < CW; ++m) {
-                const int j = wave * CW + m;
-                if (j < k) z[((int64_t)slot * k + j) * n + t] = sc * acc[m];
-            }
-        }
-    }
 }
 
 // Pass 1.  INV = false: signal s of the batch is column pair p of ROI slot
@@ -464,26 +377,6 @@ FftPlan fft_plan(int64_t n) {
     return pl;
 }
 
-xpcs_status launch_g2fft_z(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
-                           int64_t n, double *z) {
-    const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
-    const size_t lds = ((size_t)f->k * kZFrames + (size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double);
-    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)((nb + kZRois - 1) / kZRois));
-#define XPCS_Z(c)                                                                                                \
-    case c:                                                                                                      \
-        hipLaunchKernelGGL(g2fft_z_kernel<c>, grid, dim3(256), lds, ctx->stream, f->V, f->sigma, f->roi_sum,      \
-                           f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z);                                       \
-        break;
-    switch (cw) {
-        XPCS_Z(8) XPCS_Z(16) XPCS_Z(24) XPCS_Z(32) XPCS_Z(40) XPCS_Z(48)
-        default:
-            return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in g2_from_factors");
-    }
-#undef XPCS_Z
-    XPCS_LAUNCH_CHECK(ctx, "g2fft_z");
-    return XPCS_OK;
-}
-
 }  // namespace
 }  // namespace xpcs
 
@@ -541,7 +434,8 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
         const int m = std::min(nb, nr - s0);
         {
             Phase phase_(ctx, "g2fft_z");
-            if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
+            if ((st = launch_z_rows(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z, nullptr, nullptr, 0, nullptr)))
+                return st;
         }
         {
             Phase phase_(ctx, "g2fft_pass1");
@@ -610,7 +504,8 @@ xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, in
         const int m = std::min(nb, nr - s0);
         {
             Phase phase_(ctx, "g2fft_z");
-            if ((st = launch_g2fft_z(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z))) return st;
+            if ((st = launch_z_rows(ctx, f, Lr + (int64_t)s0 * k * k, r0 + s0, m, t0, n, z, nullptr, nullptr, 0, nullptr)))
+                return st;
         }
         if ((st = launch_tsgram_batched(ctx, z, true, n, n, k, m, (int64_t)k * n, G))) return st;
         Phase phase_(ctx, "ttc_stats");

@@ -8,124 +8,161 @@
 // three BF16 MFMA products (hi.hi + hi.lo + lo.hi) with FP32 accumulation,
 // accurate to ~2^-16 relative per term; the symmetric form needs one operand.
 #include "internal.hpp"
+#include "zrows.hpp"
 
 namespace xpcs {
 namespace {
 
-constexpr int kPrepFrames = 64;     // frames per block
-constexpr int kPrepMaxK = 192;
-constexpr int kPrepChunk = 32;      // rows of L staged at a time
+constexpr int kZFrames = 64;                // frames per block
+constexpr int kZChunk = 16;                 // rows of L_R staged at a time
+constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
+constexpr int kZMaxK = 192;
 
-// Thread (fr, cb) = (tid / 16, tid % 16) forms z for frames 4 fr .. 4 fr + 3 and
-// columns cb + 16 j, j < CPT: a 4 x CPT register block, so that each pair of LDS
-// reads feeds 4 * CPT / (1 + CPT / 2) FMAs.  w / S (transposed, [a][frame]) and a
-// chunk of L's rows live in LDS.
-template <int CPT>
-__global__ __launch_bounds__(256) void lowrank_prep_kernel(
+// Z[t][j] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] sigma_a L[a][j] in FP64 (zero
+// where S = 0).  W = V diag(sigma) is shared by every ROI, so a block stages a
+// 64-frame slice of it in LDS once and forms Z for kZRois ROIs in turn; lane =
+// frame, wave w owns columns [w CW, (w + 1) CW), rows of L_R are staged kZChunk at
+// a time (prefetched into registers across steps) and read as wave-wide
+// broadcasts.  BF = false stores every column as a contiguous run of 64 frames
+// (FP64); BF = true stores each frame's CW columns as 16-byte pieces of bf16 hi
+// and lo.
+template <int CW, bool BF>
+__global__ __launch_bounds__(256) void z_rows_kernel(
     const float *__restrict__ V, const double *__restrict__ sigma, const int64_t *__restrict__ roi_sum,
-    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int64_t t0,
-    int64_t nw, int kp, unsigned short *__restrict__ z_hi, unsigned short *__restrict__ z_lo,
-    unsigned char *__restrict__ valid) {
-    extern __shared__ double sm[];
-    const int kc = 16 * CPT;                          // columns covered (>= k)
-    double *wT = sm;                                  // [kc][kPrepFrames]
-    double *Lc = sm + (size_t)kc * kPrepFrames;       // [kPrepChunk][kc]
-    const int slot = blockIdx.y, roi = r0 + slot;
-    const int64_t f0 = (int64_t)blockIdx.x * kPrepFrames;
-    const double sq = sqrt((double)roi_npix[roi]);
-    const int64_t *Sr = roi_sum + (int64_t)roi * N;
-    const double *L = Lr + (int64_t)slot * k * k;     // row-major lower factor of this ROI
-    for (int idx = threadIdx.x; idx < kc * kPrepFrames; idx += 256) {
-        const int a = idx / kPrepFrames, f = idx % kPrepFrames;
+    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int nb,
+    int64_t t0, int64_t n, double *__restrict__ z, unsigned short *__restrict__ z_hi,
+    unsigned short *__restrict__ z_lo, int kp, unsigned char *__restrict__ valid) {
+    extern __shared__ double zsm[];
+    constexpr int kw = 4 * CW;                        // columns covered (>= k)
+    constexpr int kPre = kZChunk * kw / 256;          // chunk elements per thread
+    double *wT = zsm;                                 // [k][kZFrames]
+    double *Lc = wT + (size_t)k * kZFrames;           // [kZChunk][kw]
+    double *fscale = Lc + (size_t)kZChunk * kw;       // [kZRois][kZFrames]
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
+    const int slot0 = blockIdx.y * kZRois;
+    const int nrb = min(nb - slot0, kZRois);
+    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
+        const int a = idx / kZFrames, f = idx % kZFrames;
         const int64_t tl = f0 + f;
-        double w = 0.0;
-        if (tl < nw && a < k) {
-            const int64_t sv = Sr[t0 + tl];
-            if (sv > 0) w = (double)V[(int64_t)a * N + t0 + tl] * sigma[a] / (double)sv;
-        }
-        wT[idx] = w;
+        wT[idx] = tl < n ? (double)V[(int64_t)a * N + t0 + tl] * sigma[a] : 0.0;
     }
-    const int fr = threadIdx.x >> 4, cb = threadIdx.x & 15;
-    double acc[4][CPT];
+    for (int idx = threadIdx.x; idx < nrb * kZFrames; idx += 256) {
+        const int q = idx / kZFrames, f = idx % kZFrames;
+        const int roi = r0 + slot0 + q;
+        const int64_t tl = f0 + f;
+        const int64_t sv = tl < n ? roi_sum[(int64_t)roi * N + t0 + tl] : 0;
+        fscale[idx] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
+    }
+    // steps = (ROI, chunk of L_R rows); the next step's chunk is loaded into
+    // registers while the current one is used
+    const int nch = (k + kZChunk - 1) / kZChunk, steps = nrb * nch;
+    double pre[kPre];
+    auto load = [&](int st) {
+        const int q = st / nch, a0 = (st % nch) * kZChunk;
+        const double *L = Lr + (int64_t)(slot0 + q) * k * k;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
-    for (int a0 = 0; a0 < k; a0 += kPrepChunk) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kPrepChunk * kc; idx += 256) {
-            const int aa = idx / kc, b = idx % kc;
-            Lc[idx] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
+        for (int i = 0; i < kPre; ++i) {
+            const int idx = threadIdx.x + 256 * i;
+            const int aa = idx / kw, b = idx % kw;
+            pre[i] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
         }
+    };
+    load(0);
+    double acc[CW];
+    for (int st = 0; st < steps; ++st) {
+        const int q = st / nch, a0 = (st % nch) * kZChunk;
+        __syncthreads();                              // the previous step is done with Lc
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) Lc[threadIdx.x + 256 * i] = pre[i];
         __syncthreads();
-        const int na = k - a0 < kPrepChunk ? k - a0 : kPrepChunk;
+        if (st + 1 < steps) load(st + 1);
+        if (a0 == 0) {
+#pragma unroll
+            for (int m = 0; m < CW; ++m) acc[m] = 0.0;
+        }
+        const int na = min(kZChunk, k - a0);
+        const double *lw = Lc + wave * CW;
         for (int aa = 0; aa < na; ++aa) {
-            const double2 x01 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kPrepFrames + 4 * fr]);
-            const double2 x23 = *reinterpret_cast<const double2 *>(&wT[(a0 + aa) * kPrepFrames + 4 * fr + 2]);
-            const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+            const double x = wT[(a0 + aa) * kZFrames + lane];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const double l = Lc[aa * kc + cb + 16 * j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = fma(x[i], l, acc[i][j]);
+            for (int m = 0; m < CW; m += 2) {
+                const double2 l = *reinterpret_cast<const double2 *>(lw + aa * kw + m);
+                acc[m] = fma(x, l.x, acc[m]);
+                acc[m + 1] = fma(x, l.y, acc[m + 1]);
             }
         }
-    }
-    const int64_t base = (int64_t)slot * nw * kp;
+        const int64_t t = f0 + lane;
+        if (a0 + kZChunk >= k && t < n) {              // last chunk of this ROI: store its columns
+            const double sc = fscale[q * kZFrames + lane];
+            const int slot = slot0 + q;
+            if constexpr (BF) {
+                // CW consecutive columns of this frame as 16-byte pieces of hi and lo
+                unsigned short *hrow = z_hi + ((int64_t)slot * n + t) * kp + wave * CW;
+                unsigned short *lrow = z_lo + ((int64_t)slot * n + t) * kp + wave * CW;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t tl = f0 + 4 * fr + i;
-        if (tl >= nw) continue;
+                for (int m0 = 0; m0 < CW; m0 += 8) {
+                    u16x8 h, l;
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int b = cb + 16 * j;
-            if (b < kp) {
-                unsigned short zh = 0, zl = 0;
-                if (b < k) {
-                    const double zv = sq * acc[i][j];
-                    zh = f32_to_bf16_bits((float)zv);
-                    zl = f32_to_bf16_bits((float)(zv - (double)bf16_bits_to_f32(zh)));
+                    for (int e = 0; e < 8; ++e) {
+                        const double zv = sc * acc[m0 + e];
+                        const unsigned short hb = f32_to_bf16_bits((float)zv);
+                        h[e] = hb;
+                        l[e] = f32_to_bf16_bits((float)(zv - (double)bf16_bits_to_f32(hb)));
+                    }
+                    *reinterpret_cast<u16x8 *>(hrow + m0) = h;
+                    *reinterpret_cast<u16x8 *>(lrow + m0) = l;
                 }
-                z_hi[base + tl * kp + b] = zh;
-                z_lo[base + tl * kp + b] = zl;
+                if (wave == 0) valid[(int64_t)slot * n + t] = sc > 0.0 ? 1 : 0;
+            } else {
+#pragma unroll
+                for (int m = 0; m < CW; ++m) {
+                    const int j = wave * CW + m;
+                    if (j < k) z[((int64_t)slot * k + j) * n + t] = sc * acc[m];
+                }
             }
         }
-        // K padding beyond the covered columns (kp may exceed 16 * CPT)
-        for (int b = kc + cb; b < kp; b += 16) {
-            z_hi[base + tl * kp + b] = 0;
-            z_lo[base + tl * kp + b] = 0;
-        }
-    }
-    for (int f = threadIdx.x; f < kPrepFrames; f += 256) {
-        const int64_t tl = f0 + f;
-        if (tl < nw) valid[(int64_t)slot * nw + tl] = Sr[t0 + tl] > 0 ? 1 : 0;
     }
 }
 
 }  // namespace
 
+xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
+                          int64_t n, double *z64, unsigned short *z_hi, unsigned short *z_lo, int kp,
+                          unsigned char *valid) {
+    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
+    const bool bf = z64 == nullptr;
+    if (bf && (!z_hi || !z_lo || !valid || kp != 32 * ((f->k + 31) / 32)))
+        return fail(ctx, XPCS_EINVAL, "internal: split-bf16 Z rows need hi, lo, valid and kp = k rounded to 32");
+    const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
+    const size_t lds = ((size_t)f->k * kZFrames + (size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double);
+    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)((nb + kZRois - 1) / kZRois));
+#define XPCS_Z(c)                                                                                                \
+    case c:                                                                                                      \
+        if (bf)                                                                                                  \
+            hipLaunchKernelGGL((z_rows_kernel<c, true>), grid, dim3(256), lds, ctx->stream, f->V, f->sigma,       \
+                               f->roi_sum, f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z64, z_hi, z_lo, kp, valid); \
+        else                                                                                                     \
+            hipLaunchKernelGGL((z_rows_kernel<c, false>), grid, dim3(256), lds, ctx->stream, f->V, f->sigma,      \
+                               f->roi_sum, f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z64, z_hi, z_lo, kp, valid); \
+        break;
+    switch (cw) {
+        XPCS_Z(8) XPCS_Z(16) XPCS_Z(24) XPCS_Z(32) XPCS_Z(40) XPCS_Z(48)
+        default:
+            return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
+    }
+#undef XPCS_Z
+    XPCS_LAUNCH_CHECK(ctx, "z_rows");
+    return XPCS_OK;
+}
+
+
 xpcs_status launch_lowrank_prep(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nr, int64_t t0,
                                 int64_t nw, int kp, unsigned short *z_hi, unsigned short *z_lo,
                                 unsigned char *valid) {
     Phase phase_(ctx, "lowrank_prep");
-    if (f->k > kPrepMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
-    const int cpt = (f->k + 15) / 16;
-    const size_t lds = ((size_t)16 * cpt * kPrepFrames + (size_t)kPrepChunk * 16 * cpt) * sizeof(double);
-    dim3 grid((unsigned)((nw + kPrepFrames - 1) / kPrepFrames), (unsigned)nr);
-#define XPCS_PREP(c)                                                                                            \
-    case c:                                                                                                     \
-        hipLaunchKernelGGL(lowrank_prep_kernel<c>, grid, dim3(256), lds, ctx->stream, f->V, f->sigma, f->roi_sum, \
-                           f->roi_npix, Lr, f->N, f->k, r0, t0, nw, kp, z_hi, z_lo, valid);                      \
-        break;
-    switch (cpt) {
-        XPCS_PREP(1) XPCS_PREP(2) XPCS_PREP(3) XPCS_PREP(4) XPCS_PREP(5) XPCS_PREP(6)
-        XPCS_PREP(7) XPCS_PREP(8) XPCS_PREP(9) XPCS_PREP(10) XPCS_PREP(11) XPCS_PREP(12)
-        default:
-            return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
-    }
-#undef XPCS_PREP
-    XPCS_LAUNCH_CHECK(ctx, "lowrank_prep");
-    return XPCS_OK;
+    return launch_z_rows(ctx, f, Lr, r0, nr, t0, nw, nullptr, z_hi, z_lo, kp, valid);
 }
 
 }  // namespace xpcs
