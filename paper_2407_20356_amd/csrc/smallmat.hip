@@ -192,17 +192,21 @@ constexpr int kGramMfmaWaves = kGramMfmaThreads / 64;
 template <typename TA, int NCB>
 __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda,
                                                           int ncols, int pw, double *__restrict__ part,
-                                                          int64_t bstride) {
-    // blockIdx.y selects one matrix of a batch (A + y * bstride), partials after
-    // the previous matrices' gridDim.x parts
+                                                          int64_t bstride, const int32_t *__restrict__ row_idx,
+                                                          const int64_t *__restrict__ seg_off) {
+    // blockIdx.y selects one matrix of a batch (A + y * bstride) or, with seg_off,
+    // one segment of the gathered row list row_idx (-1 entries count as zero
+    // rows); partials follow the previous matrices' / segments' gridDim.x parts
     A += (int64_t)blockIdx.y * bstride;
     part += (int64_t)blockIdx.y * gridDim.x * pw * pw;
+    const int64_t r_begin = seg_off ? seg_off[blockIdx.y] : 0;
+    const int64_t r_end = seg_off ? seg_off[blockIdx.y + 1] : rows;
     constexpr int NT = NCB * (NCB + 1) / 2;
     constexpr int W = NCB * 16;
     __shared__ double red[W * W];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cl = lane & 15, kq = lane >> 4;
-    const int64_t ngroups = (rows + 15) / 16;
+    const int64_t ngroups = (r_end - r_begin + 15) / 16;
     const int64_t per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * per_blk;
     const int64_t g1 = g0 + per_blk < ngroups ? g0 + per_blk : ngroups;
@@ -210,13 +214,19 @@ __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA 
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     auto load = [&](int64_t g, TA (&x)[NCB][4]) {
-        const int64_t r = g * 16 + 4 * kq;
+        const int64_t r = r_begin + g * 16 + 4 * kq;
+        int64_t rowj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t pos = r + j;
+            rowj[j] = pos < r_end ? (row_idx ? (int64_t)row_idx[pos] : pos) : -1;
+        }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int c = 16 * cb + cl;
-            const TA *src = A + (int64_t)(c < ncols ? c : 0) * lda + r;
+            const TA *src = A + (int64_t)(c < ncols ? c : 0) * lda;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) x[cb][j] = (c < ncols && r + j < rows) ? src[j] : (TA)0;
+            for (int j = 0; j < 4; ++j) x[cb][j] = (c < ncols && rowj[j] >= 0) ? src[rowj[j]] : (TA)0;
         }
     };
     TA cur[NCB][4], nxt[NCB][4];
@@ -1353,14 +1363,14 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     const size_t lds_sums = (size_t)nblk * 16 * sizeof(double);     // one 4x4 block per owned block id
     const size_t lds = lds_tile > lds_sums ? lds_tile : lds_sums;
     dim3 grid(nparts, nseg);
-    // without segments and up to 80 columns: the FP64 MFMA kernel
-    if (!seg_off && !row_idx && nseg == 1 && ncols <= 80) {
-        const int nbatch = 1;
+    // up to 80 columns: the FP64 MFMA kernel (one matrix, or one segment per blockIdx.y)
+    if (ncols <= 80 && (seg_off || (!row_idx && nseg == 1))) {
+        const int nbatch = seg_off ? nseg : 1;
         const int64_t bstride = 0;
         const int ncb = (ncols + 15) / 16;
 #define XPCS_TSGM(T, C)                                                                                       \
     hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
-                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride)
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, row_idx, seg_off)
 #define XPCS_TSGM_T(T)                \
     switch (ncb) {                    \
         case 1: XPCS_TSGM(T, 1); break; \
@@ -1432,7 +1442,7 @@ xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int6
     const int ncb = (ncols + 15) / 16;
 #define XPCS_TSGB(T, C)                                                                                          \
     hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
-                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride)
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, nullptr, nullptr)
 #define XPCS_TSGB_T(T)                 \
     switch (ncb) {                     \
         case 1: XPCS_TSGB(T, 1); break; \
