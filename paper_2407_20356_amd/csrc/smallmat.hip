@@ -1475,7 +1475,10 @@ xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol
         dst = static_cast<double *>(scratch_get(ctx, (size_t)n * n * sizeof(double), &st));
         if (!dst) return st;
     }
-    if (n <= 128)
+    if (n <= 96)        // fewer owned elements per thread: each step's loop is shorter
+        hipLaunchKernelGGL((cholinv_reg_kernel<96, 1024>), dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst,
+                           ctx->flags);
+    else if (n <= 128)
         hipLaunchKernelGGL((cholinv_reg_kernel<128, 1024>), dim3(1), dim3(1024), 0, ctx->stream, G, n, rel_tol, dst,
                            ctx->flags);
     else if (n <= 160)
