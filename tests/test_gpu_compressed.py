@@ -309,3 +309,49 @@ def test_padded_row_stride_output_equals_contiguous(ctx):
         np.testing.assert_array_equal(np.nan_to_num(to_np(Rp), nan=-7.0), np.nan_to_num(to_np(R0), nan=-7.0))
         pad = to_np(Cp.as_strided((3, 290, Cp.stride(1)), Cp.stride()))[:, :, 290:]
         assert np.all(pad == -5.0)
+
+
+def test_roi_without_pixels(ctx):
+    """A ROI id that no pixel carries (say a q ring beyond the detector edge): |R| = 0
+    and S_R = 0 in every frame, so C of that ROI is NaN throughout, its g2 has no
+    pairs and its TTC statistics are NaN, on the compressed, FFT and raw paths; the
+    other ROIs of the same calls match the oracle."""
+    import torch
+    from paper_2407_20356_amd import api
+    H, W, n_roi, k = 40, 40, 4, 16
+    labels = synth.annular_labels(H, W, 3, r_in=2.0)
+    labels = np.where(labels == 2, 3, labels).astype(np.int32)     # ROI 2 keeps no pixel
+    F = synth.speckle_frames_numpy(H * W, 300, 0.2, 0.2, 20.0, "u8", seed=8)
+    U0, _, _ = O.exact_basis(F, k)
+    U0 = U0.astype(np.float32).astype(np.float64)
+    say("ROI without pixels: online basis, compressed C + g2, FFT g2, TTC statistics")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), n_roi, k=k, basis=to_dev(U0.T.astype(np.float32)))
+    ctx.sync()
+    fn = _factors_np(f)
+    np.testing.assert_array_equal(fn["npix"], O.roi_pixel_counts(labels, n_roi))
+    assert fn["npix"][2] == 0 and not fn["S"][2].any() and not fn["G"][2].any()
+    Crefs = _oracle_compressed(F, U0, labels, n_roi)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, Crefs)
+    assert np.isnan(C[2]).all() and not npairs[2].any() and np.isnan(g2[2]).all()
+    g2f, nf = api.g2_from_factors(ctx, f)
+    mean, std, ns = api.two_time_stats(ctx, f)
+    ctx.sync()
+    g2f, nf, mean, std, ns = to_np(g2f), to_np(nf), to_np(mean), to_np(std), to_np(ns)
+    np.testing.assert_array_equal(nf, npairs)
+    for r in (0, 1, 3):
+        gref, nref = O.g2_from_two_time(Crefs[r])
+        np.testing.assert_allclose(g2f[r][nref > 0], gref[nref > 0], rtol=1e-4)
+        m, s, cnt = O.two_time_stats(Crefs[r])
+        assert ns[r] == cnt and abs(mean[r] - m) <= 1e-4 * abs(m) and abs(std[r] - s) <= 1e-4 * s
+    assert np.isnan(g2f[2]).all() and ns[2] == 0 and np.isnan(mean[2]) and np.isnan(std[2])
+    say("ROI without pixels: raw path")
+    Cr, g2r, npr, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), n_roi, c_dtype=torch.float64)
+    ctx.sync()
+    Cr, g2r, npr = to_np(Cr), to_np(g2r), to_np(npr)
+    for r in range(n_roi):
+        Rref = O.raw_two_time(F, labels, r)
+        np.testing.assert_allclose(Cr[r], Rref, rtol=1e-15, atol=0, equal_nan=True)
+        gref, nref = O.g2_from_two_time(Rref)
+        np.testing.assert_array_equal(npr[r], nref)
+    assert np.isnan(Cr[2]).all() and not npr[2].any()

@@ -85,7 +85,10 @@ def test_fit_of_raw_g2_end_to_end(ctx):
     g, params = to_np(g2), to_np(params)
     taus = np.arange(1, 60)
     for r in range(2):
-        ref = O.siegert_fit(g[r, 1:60], taus)
+        # the oracle fits the g2 of its own raw two-time matrix (Eqs. 1, 12)
+        gref, _ = O.g2_from_two_time(O.raw_two_time(F, labels, r))
+        np.testing.assert_allclose(g[r], gref, rtol=1e-12, err_msg=f"raw g2 roi {r}")
+        ref = O.siegert_fit(gref[1:60], taus)
         np.testing.assert_allclose(params[r], ref, rtol=1e-5, err_msg=f"roi {r}")
         # the AR(1) model's field correlation time: Gamma = 1 / tau_c (loose: a finite series)
         assert abs(params[r, 2] * tau_c - 1.0) < 0.25

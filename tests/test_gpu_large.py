@@ -1,16 +1,19 @@
 """The large workload's shape, through the C ABI: 1536 x 2048 px (3.1 M), uint8 counts
 (mean 0.01, beta 0.2, tau_c 50), 64 annular ROIs, the online strategy (Sec. 2.2).
 
-The basis comes from a 4,096-frame prefix (offline, k = 184 with 8 oversampling
-columns: the widest sketch the FP64 small steps hold, 192); then the frames are
-pushed through an online stream in 1,024-frame blocks with a window of 8,192 lags,
-and g2 is taken over the whole history without materialising C.  8,192 frames of
+An offline basis is computed from a 4,096-frame prefix (k = 184 with 8 oversampling
+columns: the widest sketch the FP64 small steps hold, 192) and checked for
+orthonormality.  The stream then runs on an unrelated basis made on the host
+(the ROI indicators plus Gaussian columns, orthonormalised in FP64: Sec. 2.2's
+online strategy with a basis that does not come from the data), so that the oracle's inputs are the frames, the
+labels and that basis only: the frames are pushed in 1,024-frame blocks with a
+window of 8,192 lags, and g2 is taken over the whole history without materialising C.  8,192 frames of
 the 100,000-frame series are used (25.8 GB on the device); every kernel runs at the
 workload's real per-frame shape.
 
 Checks (the oracle cannot encode the whole series on the host in a test's time,
 so sampled outputs and properties):
-  * the basis is orthonormal;
+  * the offline basis is orthonormal;
   * the band rows of 16 sampled frames against the oracle's C~ of the same frames
     (W = X^T U in FP64 from the host copy of those frames, G_R and S_R by the oracle);
   * the stream's g2 over the history equals the FFT g2 of the same frames encoded
@@ -27,6 +30,25 @@ from tests.gpu_util import assert_two_time_close, say, to_np
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
 SPEC = synth.WORKLOADS["large_3mpx_100k"]
+
+
+def _unrelated_basis(labels, n_roi, k, seed):
+    """M x k with orthonormal columns that does not come from the data: the n_roi
+    normalised ROI indicators (disjoint supports), so that every ROI's mean
+    intensity is kept and C~ stays near 1 as with a basis fitted to the data, then
+    k - n_roi Gaussian columns with those directions projected out, Cholesky QR
+    twice, all in FP64."""
+    M = labels.shape[0]
+    ind = np.zeros((M, n_roi))
+    for r in range(n_roi):
+        px = labels == r
+        assert px.any()
+        ind[px, r] = 1.0 / np.sqrt(px.sum())
+    G = np.random.default_rng(seed).standard_normal((M, k - n_roi))
+    for _ in range(2):
+        G -= ind @ (ind.T @ G)
+        G = G @ np.linalg.inv(np.linalg.cholesky(G.T @ G)).T
+    return np.concatenate([ind, G], axis=1)
 N_USED, PREFIX, BLOCK, WINDOW, K, OVERSAMPLE = 8192, 4096, 1024, 8192, 184, 8
 
 
@@ -44,9 +66,14 @@ def test_large_shape_stream_against_oracle_and_fft_g2():
     say(f"offline basis from the {PREFIX}-frame prefix, k={K}, oversample {OVERSAMPLE}")
     fb = api.compress_frames(ctx, frames[:PREFIX], Ld, R, k=K, oversample=OVERSAMPLE, seed=11)
     ctx.sync()
-    U = fb.U
-    Uh = to_np(U).T.astype(np.float64)                     # (M, k)
-    assert np.abs(Uh.T @ Uh - np.eye(K)).max() <= 1e-5
+    Ub = to_np(fb.U).T.astype(np.float64)                  # (M, k)
+    assert np.abs(Ub.T @ Ub - np.eye(K)).max() <= 1e-5
+    del fb, Ub
+    say(f"unrelated basis on the host: {R} ROI indicators + {K - R} Gaussian columns of {M} px, FP64")
+    U32 = _unrelated_basis(labels, R, K, seed=5001).astype(np.float32)
+    U = torch.from_numpy(np.ascontiguousarray(U32.T)).to(dev)
+    Uh = U32.astype(np.float64)                            # the basis exactly as the library gets it
+    del U32
     say(f"stream: {N_USED // BLOCK} pushes of {BLOCK} frames, window {WINDOW}, {R} ROIs")
     s = api.Stream(ctx, Ld, R, U, window=WINDOW, max_block=BLOCK)
     band = None
