@@ -41,3 +41,19 @@ def assert_two_time_close(C, Cref, rtol=1e-3, small=0.1, what="C"):
         if den > 0:
             assert num / den <= rtol, f"{what}: small-entry Frobenius rel err {num / den:.3e}"
     return worst
+
+
+def check_homomorphic_identity(C, F, labels, n_roi, U):
+    """C~ of a basis U (M x k, orthonormal columns) equals the two-time correlation
+    of the decompressed data U U^T X (Eqs. 8-10), formed here with plain NumPy: the
+    check for a basis the library computed, which the oracle never takes as input."""
+    Xd = U @ (U.T @ F.astype(np.float64).T)              # decompressed, pixels x frames
+    for r in range(n_roi):
+        m = labels == r
+        S = F[:, m].astype(np.int64).sum(axis=1).astype(np.float64)
+        G = Xd[m].T @ Xd[m]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Cd = m.sum() * G / np.outer(S, S)
+        Cd[S == 0, :] = np.nan
+        Cd[:, S == 0] = np.nan
+        assert_two_time_close(C[r], Cd, what=f"identity roi {r}")

@@ -18,7 +18,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import assert_two_time_close, say, to_dev, to_np
+from tests.gpu_util import assert_two_time_close, check_homomorphic_identity, say, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -151,20 +151,6 @@ def _check_basis_properties(F, labels, n_roi, fn, k, ey_factor=1.05, sigma1_rtol
     return W
 
 
-def _check_homomorphic_identity(C, F, labels, n_roi, U):
-    """C~ equals the two-time correlation of the decompressed data U U^T X (Eqs. 8-10)."""
-    Xd = U @ (U.T @ F.astype(np.float64).T)              # decompressed, pixels x frames
-    for r in range(n_roi):
-        m = labels == r
-        S = F[:, m].astype(np.int64).sum(axis=1).astype(np.float64)
-        G = Xd[m].T @ Xd[m]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            Cd = m.sum() * G / np.outer(S, S)
-        Cd[S == 0, :] = np.nan
-        Cd[:, S == 0] = np.nan
-        assert_two_time_close(C[r], Cd, what=f"identity roi {r}")
-
-
 @pytest.mark.parametrize("power_iters", [1, 0])
 def test_offline_basis_single_roi(ctx, power_iters):
     from paper_2407_20356_amd import api
@@ -181,7 +167,7 @@ def test_offline_basis_single_roi(ctx, power_iters):
     _check_basis_properties(F, labels, 1, fn, k, ey_factor=1.05 if power_iters else 1.10,
                             sigma1_rtol=1e-3 if power_iters else None)
     C, g2, npairs = _gpu_correlate(ctx, f)
-    _check_homomorphic_identity(C, F, labels, 1, fn["U"])
+    check_homomorphic_identity(C, F, labels, 1, fn["U"])
     # how far the bf16 power pass moves the result from the FP64 pipeline (reported)
     Uo, so, _ = O.randomized_basis(F, k, 16, power_iters, seed=7)
     Co = O.compressed_two_time(F, Uo, labels, 0)
@@ -246,7 +232,7 @@ def test_offline_basis_multi_roi_u16(ctx):
     fn = _factors_np(f)
     _check_basis_properties(F, labels, 8, fn, k)
     C, g2, npairs = _gpu_correlate(ctx, f)
-    _check_homomorphic_identity(C, F, labels, 8, fn["U"])
+    check_homomorphic_identity(C, F, labels, 8, fn["U"])
 
 
 def test_large_counts_split_exactly(ctx):
