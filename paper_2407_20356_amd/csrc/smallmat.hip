@@ -189,14 +189,26 @@ __global__ __launch_bounds__(256 * GramShape<BPT>::kGroups) void tsgram_kernel(c
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kGramMfmaThreads = 512;     // 8 waves: two per SIMD
 constexpr int kGramMfmaWaves = kGramMfmaThreads / 64;
+// Four consecutive rows of one column in 16-byte loads (p 16-byte aligned).
+__device__ __forceinline__ void load_rows4(const float *p, float (&x)[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+}
+__device__ __forceinline__ void load_rows4(const double *p, double (&x)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+}
+
 template <typename TA, int NCB>
 __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA *__restrict__ A, int64_t rows, int64_t lda,
                                                           int ncols, int pw, double *__restrict__ part,
                                                           int64_t bstride, const int32_t *__restrict__ row_idx,
-                                                          const int64_t *__restrict__ seg_off) {
+                                                          const int64_t *__restrict__ seg_off, bool vec) {
     // blockIdx.y selects one matrix of a batch (A + y * bstride) or, with seg_off,
     // one segment of the gathered row list row_idx (-1 entries count as zero
-    // rows); partials follow the previous matrices' / segments' gridDim.x parts
+    // rows); partials follow the previous matrices' / segments' gridDim.x parts.
+    // vec: no row list or segments, A, lda and bstride allow 16-byte loads of four
+    // rows starting at a multiple of 4
     A += (int64_t)blockIdx.y * bstride;
     part += (int64_t)blockIdx.y * gridDim.x * pw * pw;
     const int64_t r_begin = seg_off ? seg_off[blockIdx.y] : 0;
@@ -215,6 +227,19 @@ __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA 
     for (int t = 0; t < NT; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     auto load = [&](int64_t g, TA (&x)[NCB][4]) {
         const int64_t r = r_begin + g * 16 + 4 * kq;
+        if (vec && r + 4 <= r_end) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int c = 16 * cb + cl;
+                if (c < ncols) {
+                    load_rows4(A + (int64_t)c * lda + r, x[cb]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x[cb][j] = (TA)0;
+                }
+            }
+            return;
+        }
         int64_t rowj[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1368,9 +1393,10 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
         const int nbatch = seg_off ? nseg : 1;
         const int64_t bstride = 0;
         const int ncb = (ncols + 15) / 16;
+        const bool vec = !row_idx && !seg_off && lda % 4 == 0 && (uintptr_t)A % 16 == 0;
 #define XPCS_TSGM(T, C)                                                                                       \
     hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
-                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, row_idx, seg_off)
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, row_idx, seg_off, vec)
 #define XPCS_TSGM_T(T)                \
     switch (ncb) {                    \
         case 1: XPCS_TSGM(T, 1); break; \
@@ -1440,9 +1466,10 @@ xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int6
     double *part = static_cast<double *>(scratch_get(ctx, (size_t)nbatch * nparts * pw * pw * sizeof(double), &st));
     if (!part) return st;
     const int ncb = (ncols + 15) / 16;
+    const bool vec = lda % 4 == 0 && bstride % 4 == 0 && (uintptr_t)A % 16 == 0;
 #define XPCS_TSGB(T, C)                                                                                          \
     hipLaunchKernelGGL((tsgram_mfma_kernel<T, C>), dim3(nparts, nbatch), dim3(kGramMfmaThreads), 0, ctx->stream, \
-                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, nullptr, nullptr)
+                       static_cast<const T *>(A), rows, lda, ncols, pw, part, bstride, nullptr, nullptr, vec)
 #define XPCS_TSGB_T(T)                 \
     switch (ncb) {                     \
         case 1: XPCS_TSGB(T, 1); break; \
