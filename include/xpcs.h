@@ -193,7 +193,10 @@ xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi
  *   C_R[t1][t2] = |R| * G_R[t1][t2] / (S_R[t1] S_R[t2]),  G_R = X_R^T X_R exact.
  * The ROI pixels are gathered once into int8 and G_R runs on int8 MFMA with
  * int32 accumulation (int64 across pixel chunks), so G_R is exact; this needs
- * every count <= 127, otherwise the device flag XPCS_ERANGE is raised.
+ * every count <= 127.  A larger count raises the device flag XPCS_ERANGE
+ * (reported by xpcs_sync) and, in the same call, makes every entry of C NaN and
+ * every npairs 0 (g2 NaN), so that no inexact value leaves the call looking valid;
+ * gram_out then holds the Gram of the counts clamped to 127 and is not exact.
  * Arguments as correlate_two_time; gram_out (device int64, same layout as C with
  * row stride t1-t0, or NULL) receives the exact G_R. */
 xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M,

@@ -170,7 +170,7 @@ template <typename OutT, bool WIDE>
 __device__ __forceinline__ void raw_gram_tile(
     int bi, int bj, int64_t tile_id, const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int slot,
-    int64_t ntiles, int64_t kc, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
+    int64_t ntiles, int64_t kc, bool over, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
     int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
     // the operand stages (two buffers of 256 rows x kRawKs bytes) share the LDS of
     // the epilogue's staging buffer
@@ -339,7 +339,9 @@ __device__ __forceinline__ void raw_gram_tile(
                         const int rl = 16 * a + 4 * lg + e;
                         const double si = srow[4 * a + e];
                         double v;
-                        if (si > 0.0 && sj > 0.0)
+                        // a count above 127 was clamped on its way to int8: no value of this
+                        // Gram is exact, so C is NaN throughout and g2 has no pairs
+                        if (si > 0.0 && sj > 0.0 && !over)
                             v = (npix * (double)gval(a, b, e)) / (si * sj);
                         else
                             v = __builtin_nan("");
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
     if (qlen > kc) return;
     int bi, bj;
     tile_coords(blockIdx.x, nb, bi, bj);
-    raw_gram_tile<OutT, false>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x, kc, C, ldc,
+    raw_gram_tile<OutT, false>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x, kc, *amax > 127, C, ldc,
                                c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
 }
 
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(256, 2) void raw_gram_wide_kernel(
     for (int bj = bi; bj < nb; ++bj) {
         const int64_t D = bj - bi;
         const int64_t tile_id = D * nb - D * (D - 1) / 2 + bi;
-        raw_gram_tile<OutT, true>(bi, bj, tile_id, xs, ldx, off, roi_npix, S, nw, r0, slot, ntiles, kc, C, ldc,
+        raw_gram_tile<OutT, true>(bi, bj, tile_id, xs, ldx, off, roi_npix, S, nw, r0, slot, ntiles, kc, *amax > 127, C, ldc,
                                   c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
     }
 }

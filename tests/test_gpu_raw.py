@@ -89,12 +89,15 @@ def test_raw_rejects_counts_above_127(ctx):
     F = np.full((20, 64), 3, dtype=np.uint16)
     F[7, 5] = 300
     labels = np.zeros(64, dtype=np.int32)
-    say("raw count > 127 raises ERANGE at sync")
-    api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 1)
+    say("raw count > 127 raises ERANGE at sync; C is NaN and g2 has no pairs")
+    C, g2, npairs, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 1)
     with pytest.raises(api.XpcsError) as ei:
         ctx.sync()
     assert ei.value.status == -3
     ctx.sync()   # the flag is cleared
+    assert np.isnan(to_np(C)).all()
+    assert np.isnan(to_np(g2)).all()
+    assert (to_np(npairs) == 0).all()
 
 
 def test_bad_label_is_reported(ctx):
