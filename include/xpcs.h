@@ -188,6 +188,25 @@ xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi
                                int64_t t1, void *C, int32_t c_dtype, int64_t ldc, double *g2,
                                int64_t *npairs);
 
+/* correlate_two_time for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results, but every temporary buffer lives in a
+ * static scratch array of the library (32 MiB, one copy per device, held until
+ * the process ends) instead of the context's workspace, and the call makes no
+ * hipMalloc, hipFree or other allocation (phase timing is suspended for it).
+ * The caller passes the factors and the outputs.  Scratch needed: about
+ * n_roi_call * (4 * nw * k32 + 8 * k^2 + nw) bytes (k32 = k rounded up to 32)
+ * plus, with g2, 3060 bytes per 128 x 128 tile on and above the diagonal of each
+ * ROI's window; a call needing more is refused with EUNSUPPORTED (split the ROIs
+ * or the window).  Every call on a device shares that device's scratch: calls
+ * that overlap on one device (different streams or host threads) race, so
+ * serialise them.
+ * Errors: as correlate_two_time, plus EUNSUPPORTED (scratch too small) and
+ * EDEVICE (no static scratch on the device). */
+xpcs_status correlate_two_time_noalloc(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0,
+                                       int64_t t1, void *C, int32_t c_dtype, int64_t ldc, double *g2,
+                                       int64_t *npairs);
+
 /* Two-time correlation from the raw frames (Sec. 2.1, Eqs. 1-2 per ROI), the path
  * the compressed correlation replaces:
  *   C_R[t1][t2] = |R| * G_R[t1][t2] / (S_R[t1] S_R[t2]),  G_R = X_R^T X_R exact.

@@ -78,6 +78,8 @@ SIGNATURES = {
                               ctypes.POINTER(XpcsCompressOpts), ctypes.POINTER(XpcsFactors)]),
     "correlate_two_time": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _I32, _I64,
                                  _P, _P]),
+    "correlate_two_time_noalloc": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _I32, _I64,
+                                         _P, _P]),
     "correlate_two_time_raw": (_ST, [_P, _P, _I32, _I64, _I64, _P, _I32, _I32, _I64, _I64, _P, _I32,
                                      _I64, _P, _P, _P]),
     "g2_from_two_time": (_ST, [_P, _P, _I32, _I64, _I64, _P, _P]),

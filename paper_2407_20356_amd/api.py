@@ -220,6 +220,22 @@ def correlate_two_time(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0:
     return C, g2, npairs
 
 
+def correlate_two_time_noalloc(ctx: Context, f: Factors, C: Optional[torch.Tensor],
+                               g2: Optional[torch.Tensor], npairs: Optional[torch.Tensor],
+                               roi: int = L.XPCS_ALL_ROIS, t0: int = 0, t1: Optional[int] = None):
+    """correlate_two_time with every temporary in the library's static scratch (no
+    device allocation by the library or here): the caller passes the outputs
+    (C: (nr, nw, nw) or None, g2/npairs: (nr, nw) or None)."""
+    t1 = f.N if t1 is None else t1
+    nr = f.n_roi if roi == L.XPCS_ALL_ROIS else 1
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.correlate_two_time_noalloc(ctx.handle, ctypes.byref(fs), roi, t0, t1, _ptr(C),
+                                                 _c_code(C.dtype) if C is not None else L.XPCS_F32,
+                                                 _row_stride(C, nr, t1 - t0), _ptr(g2), _ptr(npairs)))
+    return C, g2, npairs
+
+
 def g2_from_factors(ctx: Context, f: Factors, roi: int = L.XPCS_ALL_ROIS, t0: int = 0,
                     t1: Optional[int] = None, g2: Optional[torch.Tensor] = None,
                     npairs: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor]:

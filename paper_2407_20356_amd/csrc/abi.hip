@@ -46,6 +46,68 @@ size_t g2_part_bytes(int64_t nw, int nr) {
 }
 size_t g2_cnt_bytes(int64_t nw, int nr) { return (size_t)n_tiles_upper(nw) * nr * kDiag * sizeof(int); }
 
+// Buffers of one compressed correlation call, carved in order from one region
+// (the context's workspace, or the static scratch of the call that allocates nothing).
+struct CorrPlan {
+    int64_t nw = 0;
+    int r0 = 0, nr = 0, kp = 0;
+    size_t b_op = 0, b_l = 0, b_valid = 0, b_part = 0, b_cnt = 0;
+    size_t bytes = 0;
+};
+
+xpcs_status corr_plan(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1, void *C,
+                      int32_t c_dtype, int64_t ldc, double *g2, CorrPlan &p) {
+    if (!f || !f->V || !f->sigma || !f->roi_npix || !f->roi_sum || !f->roi_gram)
+        return fail(ctx, XPCS_EINVAL, "factors or one of their buffers is NULL");
+    if (f->N <= 0 || f->M <= 0 || f->k < 1 || f->n_roi < 1) return fail(ctx, XPCS_EINVAL, "bad factor sizes");
+    xpcs_status st = check_window(ctx, f->N, f->n_roi, roi, t0, t1, C, c_dtype, ldc);
+    if (st) return st;
+    if (!C && !g2) return fail(ctx, XPCS_EINVAL, "nothing to compute: C and g2 are both NULL");
+    if (f->k > kMaxEll) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192");
+    p.nw = t1 - t0;
+    p.r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
+    p.nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
+    p.kp = (int)up(f->k, 32);
+    p.b_op = (size_t)p.nr * p.nw * p.kp * 2;
+    p.b_l = (size_t)p.nr * f->k * f->k * sizeof(double);
+    p.b_valid = (size_t)p.nr * p.nw;
+    p.b_part = g2 ? g2_part_bytes(p.nw, p.nr) : 0;
+    p.b_cnt = g2 ? g2_cnt_bytes(p.nw, p.nr) : 0;
+    p.bytes = 2 * align_up(p.b_op, 256) + align_up(p.b_l, 256) + align_up(p.b_valid, 256) + align_up(p.b_part, 256) +
+              align_up(p.b_cnt, 256);
+    return XPCS_OK;
+}
+
+// G_R = L_R L_R^T for the ROIs of the call, Z rows, then the tiles and the g2 reduction.
+xpcs_status corr_run(xpcs_ctx *ctx, const xpcs_factors *f, const CorrPlan &p, int64_t t0, void *C, int32_t c_dtype,
+                     int64_t ldc, double *g2, int64_t *npairs, char *base) {
+    size_t used = 0;
+    auto take = [&](size_t b) {
+        char *q = base + used;
+        used += align_up(b, 256);
+        return q;
+    };
+    auto *z_hi = reinterpret_cast<unsigned short *>(take(p.b_op));
+    auto *z_lo = reinterpret_cast<unsigned short *>(take(p.b_op));
+    auto *Lr = reinterpret_cast<double *>(take(p.b_l));
+    auto *valid = reinterpret_cast<unsigned char *>(take(p.b_valid));
+    TileOut o;
+    o.C = C;
+    o.c_dtype = c_dtype;
+    o.ldc = ldc;
+    o.c_roi_stride = p.nw * ldc;
+    if (g2) {
+        o.g2_part = reinterpret_cast<double *>(take(p.b_part));
+        o.g2_cnt = reinterpret_cast<int *>(take(p.b_cnt));
+    }
+    xpcs_status st;
+    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)p.r0 * f->k * f->k, f->k, p.nr, Lr))) return st;
+    if ((st = launch_lowrank_prep(ctx, f, Lr, p.r0, p.nr, t0, p.nw, p.kp, z_hi, z_lo, valid))) return st;
+    if ((st = launch_lowrank_tiles(ctx, z_hi, z_lo, p.kp, valid, p.nw, p.nr, o))) return st;
+    if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, p.nw, p.nr, g2, npairs))) return st;
+    return XPCS_OK;
+}
+
 struct Orth {
     // Orthonormalise the first `ell` columns of a tall column-major matrix with
     // Cholesky QR (FP64 Gram and factor): once when the result only feeds a bf16
@@ -267,43 +329,34 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
 xpcs_status correlate_two_time(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1, void *C,
                                int32_t c_dtype, int64_t ldc, double *g2, int64_t *npairs) {
     if (!ctx) return XPCS_EINVAL;
-    if (!f || !f->V || !f->sigma || !f->roi_npix || !f->roi_sum || !f->roi_gram)
-        return fail(ctx, XPCS_EINVAL, "factors or one of their buffers is NULL");
-    if (f->N <= 0 || f->M <= 0 || f->k < 1 || f->n_roi < 1) return fail(ctx, XPCS_EINVAL, "bad factor sizes");
-    xpcs_status st = check_window(ctx, f->N, f->n_roi, roi, t0, t1, C, c_dtype, ldc);
+    CorrPlan plan;
+    xpcs_status st = corr_plan(ctx, f, roi, t0, t1, C, c_dtype, ldc, g2, plan);
     if (st) return st;
-    if (!C && !g2) return fail(ctx, XPCS_EINVAL, "nothing to compute: C and g2 are both NULL");
-    if (f->k > kMaxEll) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192");
     (void)hipSetDevice(ctx->device);
     ws_begin(ctx);
-    const int64_t nw = t1 - t0;
-    const int r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
-    const int nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
-    const int kp = (int)up(f->k, 32);
-    const size_t b_op = (size_t)nr * nw * kp * 2;
-    const size_t b_l = (size_t)nr * f->k * f->k * sizeof(double);
-    size_t need = 2 * (align_up(b_op, 256) + 256) + align_up(b_l, 256) + 256 + align_up((size_t)nr * nw, 256) + 256;
-    if (g2) need += align_up(g2_part_bytes(nw, nr), 256) + align_up(g2_cnt_bytes(nw, nr), 256) + 512;
-    if ((st = ws_reserve(ctx, need))) return st;
-    auto *z_hi = static_cast<unsigned short *>(ws_take(ctx, b_op));
-    auto *z_lo = static_cast<unsigned short *>(ws_take(ctx, b_op));
-    auto *Lr = static_cast<double *>(ws_take(ctx, b_l));
-    auto *valid = static_cast<unsigned char *>(ws_take(ctx, (size_t)nr * nw));
-    TileOut o;
-    o.C = C;
-    o.c_dtype = c_dtype;
-    o.ldc = ldc;
-    o.c_roi_stride = nw * ldc;
-    if (g2) {
-        o.g2_part = static_cast<double *>(ws_take(ctx, g2_part_bytes(nw, nr)));
-        o.g2_cnt = static_cast<int *>(ws_take(ctx, g2_cnt_bytes(nw, nr)));
-    }
-    // G_R = L_R L_R^T for the ROIs of this call, then Z and the tiles
-    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)r0 * f->k * f->k, f->k, nr, Lr))) return st;
-    if ((st = launch_lowrank_prep(ctx, f, Lr, r0, nr, t0, nw, kp, z_hi, z_lo, valid))) return st;
-    if ((st = launch_lowrank_tiles(ctx, z_hi, z_lo, kp, valid, nw, nr, o))) return st;
-    if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, nw, nr, g2, npairs))) return st;
-    return XPCS_OK;
+    if ((st = ws_reserve(ctx, plan.bytes))) return st;
+    return corr_run(ctx, f, plan, t0, C, c_dtype, ldc, g2, npairs, static_cast<char *>(ws_take(ctx, plan.bytes)));
+}
+
+xpcs_status correlate_two_time_noalloc(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t t0, int64_t t1,
+                                       void *C, int32_t c_dtype, int64_t ldc, double *g2, int64_t *npairs) {
+    if (!ctx) return XPCS_EINVAL;
+    CorrPlan plan;
+    xpcs_status st = corr_plan(ctx, f, roi, t0, t1, C, c_dtype, ldc, g2, plan);
+    if (st) return st;
+    if (plan.bytes > kStaticScratchBytes)
+        return fail(ctx, XPCS_EUNSUPPORTED,
+                    "correlate_two_time_noalloc needs " + std::to_string(plan.bytes) +
+                        " bytes of scratch; the static scratch holds " + std::to_string(kStaticScratchBytes) +
+                        " (fewer ROIs per call or a shorter window)");
+    if (!ctx->static_scratch) return fail(ctx, XPCS_EDEVICE, "no static scratch on this device");
+    (void)hipSetDevice(ctx->device);
+    // phase timing would create events; it is suspended for this call
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    st = corr_run(ctx, f, plan, t0, C, c_dtype, ldc, g2, npairs, static_cast<char *>(ctx->static_scratch));
+    ctx->timing = timing;
+    return st;
 }
 
 xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M, int64_t N,

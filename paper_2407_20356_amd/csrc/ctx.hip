@@ -2,9 +2,35 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace xpcs {
+
+// Scratch of the entry points that allocate nothing.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is looked up once per
+// device (with that device current) and only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`; the caller has made `device` current.
+hipError_t static_scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 xpcs_status fail(xpcs_ctx *ctx, xpcs_status st, const std::string &msg) {
     if (ctx) ctx->last_error = msg;
@@ -130,11 +156,15 @@ xpcs_status xpcs_create(int device, size_t hbm_budget_bytes, xpcs_ctx **out) {
     if (!out) return XPCS_EINVAL;
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return XPCS_EINVAL;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev || device >= kMaxDevices)
+        return XPCS_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return XPCS_EDEVICE;
+    void *sptr = nullptr;
+    if (static_scratch_address(device, &sptr) != hipSuccess) return XPCS_EDEVICE;
     xpcs_ctx *ctx = new xpcs_ctx();
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
+    ctx->static_scratch = sptr;
     void *p = nullptr;
     if (hipMalloc(&p, kNumFlags * sizeof(int)) != hipSuccess) {
         delete ctx;

@@ -78,6 +78,7 @@ struct xpcs_ctx {
     bool timing = false;                         // phase timing enabled
     std::vector<xpcs::PhaseRecord> phases;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;          // reusable events
+    void *static_scratch = nullptr;              // this device's copy of the library's static scratch array
 };
 
 namespace xpcs {
@@ -99,6 +100,9 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // stream runs in order, so a launcher may reuse what an earlier launcher's
 // kernels used.  Returns NULL (with the status set) when it cannot grow.
 void *scratch_get(xpcs_ctx *ctx, size_t bytes, xpcs_status *st);
+// Size of the file-scope device array behind the entry points that allocate
+// nothing (each device holds its own copy for the life of the process).
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
 // Zero `bytes` of device memory with a kernel (safe inside captured graphs).
 xpcs_status launch_zero(xpcs_ctx *ctx, void *p, size_t bytes);
 
