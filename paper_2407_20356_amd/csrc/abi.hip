@@ -13,7 +13,6 @@ using namespace xpcs;
 namespace {
 
 constexpr int kRawPad = 64;          // int8 MFMA K granularity: ROI ranges padded to 64 pixels
-constexpr int kMaxEll = 192;
 
 inline int64_t up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -51,7 +50,7 @@ size_t g2_cnt_bytes(int64_t nw, int nr) { return (size_t)n_tiles_upper(nw) * nr 
 struct CorrPlan {
     int64_t nw = 0;
     int r0 = 0, nr = 0, kp = 0;
-    size_t b_op = 0, b_l = 0, b_valid = 0, b_part = 0, b_cnt = 0;
+    size_t b_op = 0, b_l = 0, b_valid = 0, b_part = 0, b_cnt = 0, b_chol = 0;
     size_t bytes = 0;
 };
 
@@ -63,7 +62,7 @@ xpcs_status corr_plan(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t
     xpcs_status st = check_window(ctx, f->N, f->n_roi, roi, t0, t1, C, c_dtype, ldc);
     if (st) return st;
     if (!C && !g2) return fail(ctx, XPCS_EINVAL, "nothing to compute: C and g2 are both NULL");
-    if (f->k > kMaxEll) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192");
+    if (f->k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 1024");
     p.nw = t1 - t0;
     p.r0 = roi == XPCS_ALL_ROIS ? 0 : roi;
     p.nr = roi == XPCS_ALL_ROIS ? f->n_roi : 1;
@@ -73,8 +72,9 @@ xpcs_status corr_plan(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, int64_t
     p.b_valid = (size_t)p.nr * p.nw;
     p.b_part = g2 ? g2_part_bytes(p.nw, p.nr) : 0;
     p.b_cnt = g2 ? g2_cnt_bytes(p.nw, p.nr) : 0;
+    p.b_chol = chol_batched_work_bytes(f->k, p.nr);
     p.bytes = 2 * align_up(p.b_op, 256) + align_up(p.b_l, 256) + align_up(p.b_valid, 256) + align_up(p.b_part, 256) +
-              align_up(p.b_cnt, 256);
+              align_up(p.b_cnt, 256) + align_up(p.b_chol, 256);
     return XPCS_OK;
 }
 
@@ -100,8 +100,10 @@ xpcs_status corr_run(xpcs_ctx *ctx, const xpcs_factors *f, const CorrPlan &p, in
         o.g2_part = reinterpret_cast<double *>(take(p.b_part));
         o.g2_cnt = reinterpret_cast<int *>(take(p.b_cnt));
     }
+    void *chol_work = p.b_chol ? take(p.b_chol) : nullptr;
     xpcs_status st;
-    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)p.r0 * f->k * f->k, f->k, p.nr, Lr))) return st;
+    if ((st = launch_chol_batched(ctx, f->roi_gram + (int64_t)p.r0 * f->k * f->k, f->k, p.nr, Lr, chol_work)))
+        return st;
     if ((st = launch_lowrank_prep(ctx, f, Lr, p.r0, p.nr, t0, p.nw, p.kp, z_hi, z_lo, valid))) return st;
     if ((st = launch_lowrank_tiles(ctx, z_hi, z_lo, p.kp, valid, p.nw, p.nr, o))) return st;
     if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, p.nw, p.nr, g2, npairs))) return st;
@@ -165,13 +167,13 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     int ell = k + (opts->oversample > 0 ? opts->oversample : 0);
     ell += ell & 1;                                 // the eigensolver pairs columns
     if (online) {
-        if (k > kMaxEll) return fail(ctx, XPCS_EUNSUPPORTED, "online basis wider than 192");
+        if (k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "online basis wider than 1024");
         if (k > M) return fail(ctx, XPCS_EINVAL, "k larger than M");
     } else {
         if (opts->power_iters < 0 || opts->power_iters > 1)
             return fail(ctx, XPCS_EUNSUPPORTED, "power_iters must be 0 or 1");
         if (ell > M || ell > N) return fail(ctx, XPCS_EINVAL, "k + oversample exceeds min(M, N)");
-        if (ell > kMaxEll) return fail(ctx, XPCS_EUNSUPPORTED, "k + oversample above 192");
+        if (ell > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "k + oversample above 1024");
     }
     (void)hipSetDevice(ctx->device);
     ws_begin(ctx);
@@ -187,12 +189,12 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     const size_t b_om = (size_t)L * ldt * 2, b_y = (size_t)L * M * 4, b_q16 = (size_t)L * ldq * 2;
     const size_t b_z = (size_t)L * N * 8;
     const size_t b_part = (size_t)std::max(plan.nchunks * plan.ncols, plan_q.nchunks * plan_q.ncols) * N * 4;
-    const size_t b_small = (size_t)kMaxEll * kMaxEll * 8;
+    const size_t b_small = (size_t)std::max(ell, k) * std::max(ell, k) * 8;
     add(b_om); add(b_y); add(b_y); add(b_q16); add(b_q16); add(b_z); add(b_z); add(b_part);
     for (int i = 0; i < 6; ++i) add(b_small);
     add(jacobi_rot_bytes(ell > 2 ? ell : 2));
     add((size_t)(n_roi + 1) * 8); add((size_t)(M + n_roi) * 4); add((size_t)(M + n_roi) * 4);
-    add((size_t)kMaxEll * 8 * 2);
+    add((size_t)std::max(ell, k) * 8); add((size_t)std::max(ell, k) * 8);
     if ((st = ws_reserve(ctx, need))) return st;
     unsigned short *om = static_cast<unsigned short *>(ws_take(ctx, b_om));
     float *Ya = static_cast<float *>(ws_take(ctx, b_y));
@@ -212,8 +214,8 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     int64_t *off = static_cast<int64_t *>(ws_take(ctx, (size_t)(n_roi + 1) * 8));
     int32_t *perm = static_cast<int32_t *>(ws_take(ctx, (size_t)(M + n_roi) * 4));
     int32_t *qroi = static_cast<int32_t *>(ws_take(ctx, (size_t)(M + n_roi) * 4));
-    double *lam = static_cast<double *>(ws_take(ctx, (size_t)kMaxEll * 8));
-    double *scale = static_cast<double *>(ws_take(ctx, (size_t)kMaxEll * 8));
+    double *lam = static_cast<double *>(ws_take(ctx, (size_t)std::max(ell, k) * 8));
+    double *scale = static_cast<double *>(ws_take(ctx, (size_t)std::max(ell, k) * 8));
 
     if ((st = launch_roi_count(ctx, roi_label, M, n_roi, out->roi_npix))) return st;
 

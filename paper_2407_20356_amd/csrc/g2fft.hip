@@ -32,7 +32,6 @@ constexpr int kFftThreads = 256;
 constexpr int kFftElems = 2048;             // complex elements per LDS tile (32 KB)
 constexpr int kFftPerThread = kFftElems / kFftThreads;
 constexpr int kFftMaxLog = 22;              // L <= 2^22, i.e. windows up to 2^21 frames
-constexpr int kZMaxK = 192;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -271,7 +270,7 @@ __global__ __launch_bounds__(256) void ttc_partial_kernel(const double *__restri
                                                           const int64_t *__restrict__ roi_sum, int64_t N, int r0,
                                                           int64_t t0, int64_t n, int k, double *__restrict__ ps,
                                                           double *__restrict__ pd) {
-    __shared__ double red[4][kZMaxK + 3];
+    __shared__ double red[4][kMaxRank + 3];
     const int slot = blockIdx.y, chunk = blockIdx.x, nch = gridDim.x;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     const double *zs = z + (int64_t)slot * k * n;
@@ -290,15 +289,15 @@ __global__ __launch_bounds__(256) void ttc_partial_kernel(const double *__restri
     for (int q = 0; q < 3; ++q) {
         double w = x[q];
         for (int off = kWave / 2; off > 0; off >>= 1) w += __shfl_xor(w, off, kWave);
-        if (lane == 0) red[wv][kZMaxK + q] = w;
+        if (lane == 0) red[wv][kMaxRank + q] = w;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < k; j += 256)
         ps[((int64_t)slot * nch + chunk) * k + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
     if (threadIdx.x < 3)
         pd[((int64_t)slot * nch + chunk) * 3 + threadIdx.x] =
-            red[0][kZMaxK + threadIdx.x] + red[1][kZMaxK + threadIdx.x] + red[2][kZMaxK + threadIdx.x] +
-            red[3][kZMaxK + threadIdx.x];
+            red[0][kMaxRank + threadIdx.x] + red[1][kMaxRank + threadIdx.x] + red[2][kMaxRank + threadIdx.x] +
+            red[3][kMaxRank + threadIdx.x];
 }
 
 // Mean and standard deviation of C~_R over its off-diagonal valid pairs
@@ -394,7 +393,7 @@ xpcs_status g2_from_factors(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, i
     if (roi != XPCS_ALL_ROIS && (roi < 0 || roi >= f->n_roi))
         return fail(ctx, XPCS_EINVAL, "roi outside [0, n_roi) and not XPCS_ALL_ROIS");
     if (t0 < 0 || t1 <= t0 || t1 > f->N) return fail(ctx, XPCS_EINVAL, "window must satisfy 0 <= t0 < t1 <= N");
-    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in g2_from_factors");
+    if (f->k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 1024 in g2_from_factors");
     const int64_t n = t1 - t0;
     if (n > ((int64_t)1 << (kFftMaxLog - 1))) return fail(ctx, XPCS_EUNSUPPORTED, "window above 2^21 frames");
     (void)hipSetDevice(ctx->device);
@@ -478,7 +477,7 @@ xpcs_status two_time_stats(xpcs_ctx *ctx, const xpcs_factors *f, int32_t roi, in
     if (roi != XPCS_ALL_ROIS && (roi < 0 || roi >= f->n_roi))
         return fail(ctx, XPCS_EINVAL, "roi outside [0, n_roi) and not XPCS_ALL_ROIS");
     if (t0 < 0 || t1 <= t0 || t1 > f->N) return fail(ctx, XPCS_EINVAL, "window must satisfy 0 <= t0 < t1 <= N");
-    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in two_time_stats");
+    if (f->k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 1024 in two_time_stats");
     (void)hipSetDevice(ctx->device);
     ws_begin(ctx);
     const int64_t n = t1 - t0;

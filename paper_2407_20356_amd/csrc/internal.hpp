@@ -24,6 +24,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
+// Widest sketch (k + oversampling) and rank the library accepts; ranks above 192
+// take the blocked small-matrix kernels.
+constexpr int kMaxRank = 1024;
 
 // Round-to-nearest-even float -> bf16 bit pattern (NaN stays a quiet NaN).
 __device__ __forceinline__ unsigned short f32_to_bf16_bits(float x) {
@@ -232,8 +235,11 @@ xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int6
 xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol,
                            const double *Rprev, double *Rinv);
 // Cholesky factors of nb symmetric PSD n x n matrices (row-major lower L, dropped
-// pivots give zero columns): G[b] ~= L[b] L[b]^T.
-xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L);
+// pivots give zero columns): G[b] ~= L[b] L[b]^T.  Above 192 the factorization is
+// blocked and needs chol_batched_work_bytes(n, nb) of temporaries: `work`, or the
+// context's scratch when `work` is NULL.
+size_t chol_batched_work_bytes(int n, int nb);
+xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L, void *work = nullptr);
 // out[:, j] = sum_i A[:, i] T[i][j] (A column-major rows x n, fp32 or fp64; T
 // column-major n x m fp64, optionally scaled per output column by colscale[j]).
 // Writes any of: fp32 out32 (stride ld32), fp64 out64 (stride ld64), bf16 hi/lo
@@ -247,9 +253,10 @@ struct TsOut {
 };
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
                          const double *T, int m, const double *colscale, const TsOut &out);
-// Symmetric eigendecomposition of B (n x n, n even, n <= 192) by parallel-order
-// cyclic Jacobi: eigenvalues lam[n] (unsorted), eigenvectors P (row-major n x n,
-// column j = vector j).  `rot` holds the rotation log (see workspace sizing).
+// Symmetric eigendecomposition of B (n x n, n even) by cyclic Jacobi (parallel
+// order on chip up to 192, block Jacobi above): eigenvalues lam[n] (unsorted),
+// eigenvectors P (row-major n x n, column j = vector j).  `rot` holds the rotation
+// log, or the block method's matrices (jacobi_rot_bytes(n) bytes).
 size_t jacobi_rot_bytes(int n);
 xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *rot);
 // Order by decreasing eigenvalue, pick the first k, fix signs and build the
@@ -267,6 +274,18 @@ xpcs_status launch_basis_to_bf16(xpcs_ctx *ctx, const float *U, int64_t M, int k
                                  int Lpad, unsigned short *hi, unsigned short *lo);
 // Diagonal identity: T[i][j] = (i == j) for an n x n column-major matrix.
 xpcs_status launch_identity(xpcs_ctx *ctx, double *T, int n);
+
+// ---------------------------------------------------------------- the same steps above 192 (bigmat.hip)
+size_t chol_blocked_work_bytes(int n, int nb);
+xpcs_status launch_chol_blocked(xpcs_ctx *ctx, const double *G, int n, int nb, double rel_tol, double *L,
+                                void *work);
+size_t cholinv_blocked_work_bytes(int n);
+xpcs_status launch_cholinv_blocked(xpcs_ctx *ctx, const double *G, int n, double rel_tol, double *Rinv,
+                                   void *work);
+size_t jacobi_block_work_bytes(int n);
+xpcs_status launch_jacobi_block(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *work);
+xpcs_status launch_panel_gram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
+                              const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G);
 
 // ---------------------------------------------------------------- compressed TTC prep (lowrank.hip)
 // Per ROI r (Lr = Cholesky factor of G_R, row-major lower, nr x k x k) and frame t of

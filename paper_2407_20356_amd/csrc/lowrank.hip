@@ -16,7 +16,7 @@ namespace {
 constexpr int kZFrames = 64;                // frames per block
 constexpr int kZChunk = 16;                 // rows of L_R staged at a time
 constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
-constexpr int kZMaxK = 192;
+constexpr int kZMaxK = 192;                 // widest rank of the on-chip Z-row kernel
 
 // Z[t][j] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] sigma_a L[a][j] in FP64 (zero
 // where S = 0).  W = V diag(sigma) is shared by every ROI, so a block stages a
@@ -126,13 +126,123 @@ __global__ __launch_bounds__(256) void z_rows_kernel(
     }
 }
 
+
+// Z rows for ranks above kZMaxK, where W's slice no longer fits LDS: one ROI per
+// blockIdx.y, 64 frames per block (lane = frame), and per blockIdx.z a group of 256
+// output columns (wave w: columns 64 w .. 64 w + 63 of the group).  The inner
+// dimension runs in chunks of 16 rows of L_R, each chunk staging its 16 rows of W
+// (source column a at W[a ldw + w_t0 + t], times wscale[a] when given) and of L_R.
+// Rows go to z64 (FP64, column-major per slot) or to split-bf16 rows at
+// ((slot rows_cap + (ring0 + t) mod ring_cap) kp) with valid[] beside them.
+constexpr int kZwCols = 256;
+constexpr int kZwChunk = 16;
+template <typename TS>
+__global__ __launch_bounds__(256) void z_rows_wide_kernel(
+    const TS *__restrict__ W, const double *__restrict__ wscale, int64_t ldw, int64_t w_t0,
+    const int64_t *__restrict__ S, int64_t s_stride, int64_t s_t0, const int64_t *__restrict__ npix, int r0,
+    const double *__restrict__ Lr, int k, int64_t n, double *__restrict__ z64, unsigned short *__restrict__ z_hi,
+    unsigned short *__restrict__ z_lo, int kp, unsigned char *__restrict__ valid, int64_t rows_cap, int64_t ring0,
+    int64_t ring_cap) {
+    __shared__ double wT[kZwChunk][kZFrames];
+    __shared__ double Lc[kZwChunk][kZwCols];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int slot = blockIdx.y, roi = r0 + slot;
+    const int j0 = blockIdx.z * kZwCols;
+    const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
+    const double *L = Lr + (int64_t)slot * k * k;
+    double acc[64];
+#pragma unroll
+    for (int m = 0; m < 64; ++m) acc[m] = 0.0;
+    for (int a0 = 0; a0 < k; a0 += kZwChunk) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kZwChunk * kZFrames; idx += 256) {
+            const int aa = idx / kZFrames, f = idx % kZFrames;
+            const int a = a0 + aa;
+            const int64_t t = f0 + f;
+            double v = 0.0;
+            if (a < k && t < n) {
+                v = (double)W[(int64_t)a * ldw + w_t0 + t];
+                if (wscale) v *= wscale[a];
+            }
+            wT[aa][f] = v;
+        }
+        for (int idx = threadIdx.x; idx < kZwChunk * kZwCols; idx += 256) {
+            const int aa = idx / kZwCols, b = idx % kZwCols;
+            Lc[aa][b] = (a0 + aa < k && j0 + b < k) ? L[(int64_t)(a0 + aa) * k + j0 + b] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int aa = 0; aa < kZwChunk; ++aa) {
+            const double x = wT[aa][lane];
+            const double *lw = &Lc[aa][64 * wave];
+#pragma unroll
+            for (int m = 0; m < 64; m += 2) {
+                const double2 l = *reinterpret_cast<const double2 *>(lw + m);
+                acc[m] = fma(x, l.x, acc[m]);
+                acc[m + 1] = fma(x, l.y, acc[m + 1]);
+            }
+        }
+    }
+    const int64_t t = f0 + lane;
+    if (t >= n) return;
+    const int64_t sv = S[(int64_t)roi * s_stride + s_t0 + t];
+    const double sc = sv > 0 ? sqrt((double)npix[roi]) / (double)sv : 0.0;
+    const int jw = j0 + 64 * wave;
+    if (z64) {
+#pragma unroll
+        for (int m = 0; m < 64; ++m)
+            if (jw + m < k) z64[((int64_t)slot * k + jw + m) * n + t] = sc * acc[m];
+        return;
+    }
+    const int64_t row = (int64_t)slot * rows_cap + (ring0 + t) % ring_cap;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) {
+        const int j = jw + m;
+        if (j < kp) {
+            const double zv = j < k ? sc * acc[m] : 0.0;
+            const unsigned short hb = f32_to_bf16_bits((float)zv);
+            z_hi[row * kp + j] = hb;
+            z_lo[row * kp + j] = f32_to_bf16_bits((float)(zv - (double)bf16_bits_to_f32(hb)));
+        }
+    }
+    if (blockIdx.z == 0 && wave == 0) valid[row] = sv > 0 ? 1 : 0;
+}
+
 }  // namespace
+
+
+xpcs_status launch_z_rows_wide(xpcs_ctx *ctx, const void *W, bool w_f64, const double *wscale, int64_t ldw,
+                               int64_t w_t0, const int64_t *S, int64_t s_stride, int64_t s_t0, const int64_t *npix,
+                               int r0, const double *Lr, int k, int nb, int64_t n, double *z64,
+                               unsigned short *z_hi, unsigned short *z_lo, int kp, unsigned char *valid,
+                               int64_t rows_cap, int64_t ring0, int64_t ring_cap) {
+    if (n <= 0 || nb <= 0) return XPCS_OK;
+    // the split-bf16 form writes the padded columns k .. kp - 1 too
+    const int cols = z64 ? k : kp;
+    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)nb, (unsigned)((cols + kZwCols - 1) / kZwCols));
+    if (w_f64)
+        hipLaunchKernelGGL(z_rows_wide_kernel<double>, grid, dim3(256), 0, ctx->stream, static_cast<const double *>(W),
+                           wscale, ldw, w_t0, S, s_stride, s_t0, npix, r0, Lr, k, n, z64, z_hi, z_lo, kp, valid,
+                           rows_cap, ring0, ring_cap);
+    else
+        hipLaunchKernelGGL(z_rows_wide_kernel<float>, grid, dim3(256), 0, ctx->stream, static_cast<const float *>(W),
+                           wscale, ldw, w_t0, S, s_stride, s_t0, npix, r0, Lr, k, n, z64, z_hi, z_lo, kp, valid,
+                           rows_cap, ring0, ring_cap);
+    XPCS_LAUNCH_CHECK(ctx, "z_rows_wide");
+    return XPCS_OK;
+}
 
 xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr, int r0, int nb, int64_t t0,
                           int64_t n, double *z64, unsigned short *z_hi, unsigned short *z_lo, int kp,
                           unsigned char *valid) {
-    if (f->k > kZMaxK) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
     const bool bf = z64 == nullptr;
+    if (f->k > kZMaxK) {
+        if (bf && (!z_hi || !z_lo || !valid || kp != 32 * ((f->k + 31) / 32)))
+            return fail(ctx, XPCS_EINVAL, "internal: split-bf16 Z rows need hi, lo, valid and kp = k rounded to 32");
+        return launch_z_rows_wide(ctx, f->V, false, f->sigma, f->N, t0, f->roi_sum, f->N, t0, f->roi_npix, r0, Lr,
+                                  f->k, nb, n, z64, z_hi, z_lo, kp, valid, n, 0, n);
+    }
     if (bf && (!z_hi || !z_lo || !valid || kp != 32 * ((f->k + 31) / 32)))
         return fail(ctx, XPCS_EINVAL, "internal: split-bf16 Z rows need hi, lo, valid and kp = k rounded to 32");
     const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
@@ -150,7 +260,7 @@ xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr
     switch (cw) {
         XPCS_Z(8) XPCS_Z(16) XPCS_Z(24) XPCS_Z(32) XPCS_Z(40) XPCS_Z(48)
         default:
-            return fail(ctx, XPCS_EUNSUPPORTED, "rank above 192 in the compressed correlation");
+            return fail(ctx, XPCS_EINVAL, "internal: no Z-row kernel for this rank");
     }
 #undef XPCS_Z
     XPCS_LAUNCH_CHECK(ctx, "z_rows");

@@ -367,21 +367,29 @@ xpcs_status launch_proj_pixels_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t 
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
     if (ldb % 32 || ldb < N) return fail(ctx, XPCS_EINVAL, "internal: sketch row stride must cover N in steps of 32");
     const int ncb_total = L / 16;
-    int ngroups = (ncb_total + 5) / 6;                 // column groups of at most 6 blocks (grid.y)
-    while (ncb_total % ngroups) ++ngroups;
-    const int ncb = ncb_total / ngroups;
+    // column groups of at most 6 blocks (grid.y of one launch per group size): the
+    // sizes differ by at most one, the larger groups first
+    const int ngroups = (ncb_total + 5) / 6;
+    const int sz = ncb_total / ngroups, nbig = ncb_total % ngroups;
     const bool vec = (M % 4 == 0) && ((uintptr_t)frames % 4 == 0);
-    dim3 grid((unsigned)((M + 255) / 256), (unsigned)ngroups);
-    switch (ncb) {
-        case 1: launch_pp_f8<1>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        case 2: launch_pp_f8<2>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        case 3: launch_pp_f8<3>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        case 4: launch_pp_f8<4>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        case 5: launch_pp_f8<5>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        case 6: launch_pp_f8<6>(grid, ctx->stream, frames, M, N, B, ldb, Y, vec); break;
-        default: return fail(ctx, XPCS_EUNSUPPORTED, "too many sketch columns for the fp8 pass");
+    for (int part = 0; part < 2; ++part) {
+        const int ncb = part == 0 ? sz + 1 : sz, gy = part == 0 ? nbig : ngroups - nbig;
+        if (gy == 0) continue;
+        const int c0 = part == 0 ? 0 : nbig * (sz + 1);
+        const uint8_t *Bp = B + (int64_t)16 * c0 * ldb;
+        float *Yp = Y + (int64_t)16 * c0 * M;
+        dim3 grid((unsigned)((M + 255) / 256), (unsigned)gy);
+        switch (ncb) {
+            case 1: launch_pp_f8<1>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            case 2: launch_pp_f8<2>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            case 3: launch_pp_f8<3>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            case 4: launch_pp_f8<4>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            case 5: launch_pp_f8<5>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            case 6: launch_pp_f8<6>(grid, ctx->stream, frames, M, N, Bp, ldb, Yp, vec); break;
+            default: return fail(ctx, XPCS_EUNSUPPORTED, "too many sketch columns for the fp8 pass");
+        }
+        XPCS_LAUNCH_CHECK(ctx, "proj_pixels_f8");
     }
-    XPCS_LAUNCH_CHECK(ctx, "proj_pixels_f8");
     return XPCS_OK;
 }
 
@@ -390,34 +398,44 @@ xpcs_status launch_proj_frames_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t 
     Phase phase_(ctx, "proj_frames");
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
     if (ldq % 64 || ldq < M) return fail(ctx, XPCS_EINVAL, "internal: basis row stride must cover M in steps of 64");
-    const int ncb = L / 16;
-    const int rb = pf_rb(ncb, 0, false);
-    if (rb * 64 != plan.frames_per_block || plan.ncols != L)
+    const int ncb_total = L / 16;
+    if (plan.ncols != L) return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
+    if (ncb_total <= 12 && pf_rb(ncb_total, 0, false) * 64 != plan.frames_per_block)
         return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
-    const int64_t fbf = (int64_t)rb * 64;
-    const int nfb = (int)((N + fbf - 1) / fbf);
-    const int64_t nblocks = (int64_t)nfb * plan.nchunks;
-    if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
     const bool vec = (M % 8 == 0) && ((uintptr_t)frames % 8 == 0);
-    const int nb = (int)nblocks;
-#define XPCS_PF8(R, C) launch_pf_f8<R, C>(nb, ctx->stream, frames, M, N, q8, ldq, plan.chunk, nfb, L, part, vec)
-    switch (ncb) {
-        case 1: XPCS_PF8(4, 1); break;
-        case 2: XPCS_PF8(4, 2); break;
-        case 3: XPCS_PF8(4, 3); break;
-        case 4: XPCS_PF8(4, 4); break;
-        case 5: XPCS_PF8(4, 5); break;
-        case 6: XPCS_PF8(4, 6); break;
-        case 7: XPCS_PF8(4, 7); break;
-        case 8: XPCS_PF8(4, 8); break;
-        case 9: XPCS_PF8(2, 9); break;
-        case 10: XPCS_PF8(2, 10); break;
-        case 11: XPCS_PF8(2, 11); break;
-        case 12: XPCS_PF8(2, 12); break;
-        default: return fail(ctx, XPCS_EUNSUPPORTED, "too many basis columns for the fp8 pass");
-    }
+    // more than 12 column blocks: one launch per group of at most 12 (sizes differing by at
+    // most one), each writing its own columns of the partial sums
+    const int ngroups = (ncb_total + 11) / 12;
+    int c0 = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        const int ncb = ncb_total / ngroups + (g < ncb_total % ngroups ? 1 : 0);
+        const int64_t fbf = (int64_t)pf_rb(ncb, 0, false) * 64;
+        const int nfb = (int)((N + fbf - 1) / fbf);
+        const int64_t nblocks = (int64_t)nfb * plan.nchunks;
+        if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
+        const int nb = (int)nblocks;
+        const uint8_t *qg = q8 + (int64_t)16 * c0 * ldq;
+        float *pg = part + 16 * c0;
+#define XPCS_PF8(R, C) launch_pf_f8<R, C>(nb, ctx->stream, frames, M, N, qg, ldq, plan.chunk, nfb, L, pg, vec)
+        switch (ncb) {
+            case 1: XPCS_PF8(4, 1); break;
+            case 2: XPCS_PF8(4, 2); break;
+            case 3: XPCS_PF8(4, 3); break;
+            case 4: XPCS_PF8(4, 4); break;
+            case 5: XPCS_PF8(4, 5); break;
+            case 6: XPCS_PF8(4, 6); break;
+            case 7: XPCS_PF8(4, 7); break;
+            case 8: XPCS_PF8(4, 8); break;
+            case 9: XPCS_PF8(2, 9); break;
+            case 10: XPCS_PF8(2, 10); break;
+            case 11: XPCS_PF8(2, 11); break;
+            case 12: XPCS_PF8(2, 12); break;
+            default: return fail(ctx, XPCS_EUNSUPPORTED, "too many basis columns for the fp8 pass");
+        }
 #undef XPCS_PF8
-    XPCS_LAUNCH_CHECK(ctx, "proj_frames_f8");
+        XPCS_LAUNCH_CHECK(ctx, "proj_frames_f8");
+        c0 += ncb;
+    }
     return XPCS_OK;
 }
 

@@ -39,6 +39,9 @@ namespace proj {
 bool dispatch_pf_u8_lo_plain(int ncb, int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
                              const unsigned short *qh, const unsigned short *ql, int64_t ldq, int64_t chunk, int nfb,
                              int ncols, float *part, bool vec);
+bool dispatch_pf_u16_lo_plain(int ncb, int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
+                              const unsigned short *qh, const unsigned short *ql, int64_t ldq, int64_t chunk, int nfb,
+                              int ncols, float *part, bool vec);
 }  // namespace proj
 
 namespace {
@@ -88,7 +91,7 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
     const bool vec = (M % 8 == 0) && ((uintptr_t)frames % (8 * esz) == 0) &&
                      (nib == 0 || (uintptr_t)labels % 16 == 0);
     const int frags = ncb * (lo ? 2 : 1) + nib;
-    if (!lo || frags <= kMaxFragsPerLaunch || dtype != XPCS_U8) {
+    if (ncb <= 12 && (!lo || frags <= kMaxFragsPerLaunch || dtype != XPCS_U8)) {
         const int rb = pf_rb(ncb, nib, lo);
         if (rb * 64 != plan.frames_per_block)
             return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
@@ -106,30 +109,61 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
         XPCS_LAUNCH_CHECK(ctx, "proj_frames");
         return XPCS_OK;
     }
-    // wide residual-term pass: groups of column blocks, the last one with the
-    // indicator columns; each group writes its own columns of the partial sums
-    const int groups = (frags + kMaxFragsPerLaunch - 1) / kMaxFragsPerLaunch;
+    // Several launches over groups of column blocks, each writing its own columns of
+    // the partial sums; the indicator columns ride with the last group.  Up to 12
+    // blocks the residual-term uint8 pass keeps its measured split (frags / 13 groups
+    // of balanced size); otherwise the last group takes at most 6 blocks and as many
+    // as fit 13 operand fragments with the indicators, the rest groups of at most 6
+    // (12 without the residual term).
+    int sizes[64], groups = 0;
+    if (lo && ncb <= 12) {
+        groups = (frags + kMaxFragsPerLaunch - 1) / kMaxFragsPerLaunch;
+        int c = 0;
+        for (int g = 0; g < groups; ++g) {
+            const int last = g == groups - 1;
+            sizes[g] = last ? ncb - c : (ncb - c + (groups - g) - 1) / (groups - g);
+            c += sizes[g];
+        }
+        if (sizes[groups - 1] * 2 + nib > kMaxFragsPerLaunch) groups = 0;     // use the general split
+    }
+    if (groups == 0) {
+        const int per = lo ? 6 : 12;
+        int last = lo ? (kMaxFragsPerLaunch - nib) / 2 : per;
+        if (last > per) last = per;
+        if (last > ncb) last = ncb;
+        if (last < 1) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
+        const int rest = ncb - last, nplain = (rest + per - 1) / per;
+        if (nplain + 1 > 64) return fail(ctx, XPCS_EUNSUPPORTED, "basis too wide for proj_frames");
+        for (int g = 0; g < nplain; ++g) sizes[g] = rest / nplain + (g < rest % nplain ? 1 : 0);
+        sizes[nplain] = last;
+        groups = nplain + 1;
+    }
     int c0 = 0;
     for (int g = 0; g < groups; ++g) {
         const int last = g == groups - 1;
-        const int ncb_g = last ? ncb - c0 : (ncb - c0 + (groups - g) - 1) / (groups - g);
+        const int ncb_g = sizes[g];
         const int nib_g = last ? nib : 0;
-        if (ncb_g < 1 || ncb_g > 6 || 2 * ncb_g + nib_g > kMaxFragsPerLaunch)
-            return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
-        const int rb = pf_rb(ncb_g, nib_g, true);
+        const int rb = pf_rb(ncb_g, nib_g, lo);
         const int64_t fbf = (int64_t)rb * 64;
         const int nfb = (int)((N + fbf - 1) / fbf);
         const int64_t nblocks = (int64_t)nfb * plan.nchunks;
         if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
-        const unsigned short *qh = q_hi + (int64_t)16 * c0 * ldq, *ql = q_lo + (int64_t)16 * c0 * ldq;
+        const unsigned short *qh = q_hi + (int64_t)16 * c0 * ldq;
+        const unsigned short *ql = lo ? q_lo + (int64_t)16 * c0 * ldq : nullptr;
         float *pg = part + 16 * c0;
         bool ok;
-        if (nib_g)
-            ok = proj::dispatch_pf_u8(ncb_g, nib_g, true, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
-                                      labels, plan.chunk, nfb, plan.ncols, pg, vec);
+        if (nib_g || !lo)
+            ok = dtype == XPCS_U8
+                     ? proj::dispatch_pf_u8(ncb_g, nib_g, lo, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                            labels, plan.chunk, nfb, plan.ncols, pg, vec)
+                     : proj::dispatch_pf_u16(ncb_g, nib_g, lo, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                             labels, plan.chunk, nfb, plan.ncols, pg, vec);
         else
-            ok = proj::dispatch_pf_u8_lo_plain(ncb_g, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
-                                               plan.chunk, nfb, plan.ncols, pg, vec);
+            ok = dtype == XPCS_U8
+                     ? proj::dispatch_pf_u8_lo_plain(ncb_g, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                                     plan.chunk, nfb, plan.ncols, pg, vec)
+                     : proj::dispatch_pf_u16_lo_plain(ncb_g, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
+                                                      plan.chunk, nfb, plan.ncols, pg, vec);
         if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "unsupported basis width or ROI count for proj_frames");
         XPCS_LAUNCH_CHECK(ctx, "proj_frames");
         c0 += ncb_g;

@@ -275,18 +275,25 @@ xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int
     if (ldb % kstep || ldb < N)
         return fail(ctx, XPCS_EINVAL, "internal: sketch row stride must cover N in whole K steps");
     const int ncb_total = L / 16;
-    // Column groups of at most 12 blocks (grid.y); all groups have the same size.
-    int ngroups = (ncb_total + 11) / 12;
-    while (ncb_total % ngroups) ++ngroups;
-    const int ncb = ncb_total / ngroups;
+    // Column groups of at most 12 blocks (grid.y of one launch per group size): the
+    // sizes differ by at most one, the larger groups first.
+    const int ngroups = (ncb_total + 11) / 12;
+    const int sz = ncb_total / ngroups, nbig = ncb_total % ngroups;
     const size_t esz = dtype == XPCS_U8 ? 1 : 2;
     const bool vec4 = (M % 4 == 0) && ((uintptr_t)frames % (4 * esz) == 0);
     const bool vec2 = (M % 2 == 0) && ((uintptr_t)frames % (2 * esz) == 0);
-    bool ok = dtype == XPCS_U8
-                  ? dispatch_pp<uint8_t>(ncb, (unsigned)ngroups, ctx->stream, frames, M, N, B, ldb, Y, vec4, vec2)
-                  : dispatch_pp<uint16_t>(ncb, (unsigned)ngroups, ctx->stream, frames, M, N, B, ldb, Y, vec4, vec2);
-    if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "too many sketch columns for proj_pixels");
-    XPCS_LAUNCH_CHECK(ctx, "proj_pixels");
+    for (int part = 0; part < 2; ++part) {
+        const int ncb = part == 0 ? sz + 1 : sz, gy = part == 0 ? nbig : ngroups - nbig;
+        if (gy == 0) continue;
+        const int c0 = part == 0 ? 0 : nbig * (sz + 1);
+        const unsigned short *Bp = B + (int64_t)16 * c0 * ldb;
+        float *Yp = Y + (int64_t)16 * c0 * M;
+        bool ok = dtype == XPCS_U8
+                      ? dispatch_pp<uint8_t>(ncb, (unsigned)gy, ctx->stream, frames, M, N, Bp, ldb, Yp, vec4, vec2)
+                      : dispatch_pp<uint16_t>(ncb, (unsigned)gy, ctx->stream, frames, M, N, Bp, ldb, Yp, vec4, vec2);
+        if (!ok) return fail(ctx, XPCS_EUNSUPPORTED, "too many sketch columns for proj_pixels");
+        XPCS_LAUNCH_CHECK(ctx, "proj_pixels");
+    }
     return XPCS_OK;
 }
 

@@ -97,7 +97,7 @@ xpcs_status check_desc(xpcs_server *srv, const xpcs_stream_desc *d) {
     if (d->n_roi < 1) return srv_fail(srv, XPCS_EINVAL, "n_roi must be >= 1");
     if (d->n_roi > 64) return srv_fail(srv, XPCS_EUNSUPPORTED, "a stream records at most 64 ROIs");
     if (d->k < 1 || d->k > d->M) return srv_fail(srv, XPCS_EINVAL, "k must be in 1..M");
-    if (d->k > 192) return srv_fail(srv, XPCS_EUNSUPPORTED, "basis wider than 192");
+    if (d->k > xpcs::kMaxRank) return srv_fail(srv, XPCS_EUNSUPPORTED, "basis wider than 1024");
     if (d->window < 1 || d->window > 65536) return srv_fail(srv, XPCS_EINVAL, "window must be in 1..65536");
     if (d->max_block < 1 || d->max_block > 4096) return srv_fail(srv, XPCS_EINVAL, "max_block must be in 1..4096");
     return XPCS_OK;

@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
                                                     int64_t ld32, double *out64, int64_t ld64, unsigned short *hi,
                                                     unsigned short *lo, uint8_t *f8, int64_t ldh, int Lpad,
                                                     int64_t rows_pad) {
-    __shared__ double Ts[kMaxSmall * kTsCols];        // T[i][j0 + jj] at i * kTsCols + jj
+    __shared__ double Ts[kMaxSmall * kTsCols];        // T[k0 + i][j0 + jj] at i * kTsCols + jj
     const int j0 = blockIdx.y * kTsCols;
     const int64_t base = (int64_t)blockIdx.x * (256 * kTsRows) + threadIdx.x;
     int64_t rr[kTsRows];
@@ -567,27 +567,29 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
         live[q] = row < rows;
         rr[q] = live[q] ? row : 0;
     }
-    if (j0 < m) {
-        for (int idx = threadIdx.x; idx < n * kTsCols; idx += 256) {
+    double acc[kTsRows][kTsCols];
+#pragma unroll
+    for (int q = 0; q < kTsRows; ++q)
+#pragma unroll
+        for (int jj = 0; jj < kTsCols; ++jj) acc[q][jj] = 0.0;
+    // the inner dimension in chunks of at most kMaxSmall rows of T (one LDS fill each)
+    for (int k0 = 0; j0 < m && k0 < n; k0 += kMaxSmall) {
+        const int kc = n - k0 < kMaxSmall ? n - k0 : kMaxSmall;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kc * kTsCols; idx += 256) {
             const int i = idx / kTsCols, jj = idx % kTsCols;
-            Ts[idx] = j0 + jj < m ? T[(int64_t)(j0 + jj) * n + i] : 0.0;
+            Ts[idx] = j0 + jj < m ? T[(int64_t)(j0 + jj) * n + k0 + i] : 0.0;
         }
-    }
-    __syncthreads();
-    if (j0 < m) {
-        double acc[kTsRows][kTsCols];
-#pragma unroll
-        for (int q = 0; q < kTsRows; ++q)
-#pragma unroll
-            for (int jj = 0; jj < kTsCols; ++jj) acc[q][jj] = 0.0;
+        __syncthreads();
+        const TA *Ak = A + (int64_t)k0 * lda;
         // A is read kTsAhead columns ahead of its use (the loads of the next group are
         // in flight while the current one is multiplied)
         TA an[kTsAhead][kTsRows];
 #pragma unroll
         for (int u = 0; u < kTsAhead; ++u)
 #pragma unroll
-            for (int q = 0; q < kTsRows; ++q) an[u][q] = u < n ? A[(int64_t)u * lda + rr[q]] : (TA)0;
-        for (int i0 = 0; i0 < n; i0 += kTsAhead) {
+            for (int q = 0; q < kTsRows; ++q) an[u][q] = u < kc ? Ak[(int64_t)u * lda + rr[q]] : (TA)0;
+        for (int i0 = 0; i0 < kc; i0 += kTsAhead) {
             TA a[kTsAhead][kTsRows];
 #pragma unroll
             for (int u = 0; u < kTsAhead; ++u)
@@ -597,12 +599,12 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
             for (int u = 0; u < kTsAhead; ++u) {
                 const int i = i0 + kTsAhead + u;
 #pragma unroll
-                for (int q = 0; q < kTsRows; ++q) an[u][q] = i < n ? A[(int64_t)i * lda + rr[q]] : (TA)0;
+                for (int q = 0; q < kTsRows; ++q) an[u][q] = i < kc ? Ak[(int64_t)i * lda + rr[q]] : (TA)0;
             }
 #pragma unroll
             for (int u = 0; u < kTsAhead; ++u) {
                 const int i = i0 + u;
-                if (i >= n) break;
+                if (i >= kc) break;
 #pragma unroll
                 for (int jj = 0; jj < kTsCols; jj += 2) {
                     const double2 t = *reinterpret_cast<const double2 *>(&Ts[i * kTsCols + jj]);
@@ -614,6 +616,8 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
                 }
             }
         }
+    }
+    if (j0 < m) {
 #pragma unroll
         for (int q = 0; q < kTsRows; ++q) {
             if (!live[q]) continue;
@@ -1362,13 +1366,14 @@ __global__ void identity_kernel(double *T, int n) {
 }  // namespace
 
 size_t jacobi_rot_bytes(int n) {
+    if (n > kMaxSmall) return jacobi_block_work_bytes(n);
     return (size_t)(kMaxSweeps + 1) * (size_t)(n - 1) * (size_t)(n / 2) * sizeof(double2) + 256;
 }
 
 xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
                           const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G) {
     Phase phase_(ctx, "tsgram");
-    if (ncols > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "Gram wider than 192 columns");
+    if (ncols > kMaxSmall) return launch_panel_gram(ctx, A, a_f64, rows, lda, ncols, row_idx, seg_off, nseg, G);
     const int nc4 = (ncols + 3) / 4;
     const int pw = nc4 * 4;
     const int nblk = nc4 * (nc4 + 1) / 2;
@@ -1495,7 +1500,13 @@ xpcs_status launch_tsgram_batched(xpcs_ctx *ctx, const void *A, bool a_f64, int6
 xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol, const double *Rprev,
                            double *Rinv) {
     Phase phase_(ctx, "cholinv");
-    if (n > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "Cholesky larger than 192");
+    if (n > kMaxSmall) {
+        if (Rprev) return fail(ctx, XPCS_EUNSUPPORTED, "internal: product with a previous factor above 192");
+        xpcs_status st;
+        void *work = scratch_get(ctx, cholinv_blocked_work_bytes(n), &st);
+        if (!work) return st;
+        return launch_cholinv_blocked(ctx, G, n, rel_tol, Rinv, work);
+    }
     double *dst = Rinv;
     if (Rprev) {
         xpcs_status st;
@@ -1522,9 +1533,15 @@ xpcs_status launch_cholinv(xpcs_ctx *ctx, const double *G, int n, double rel_tol
     return XPCS_OK;
 }
 
-xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L) {
+size_t chol_batched_work_bytes(int n, int nb) { return n > kMaxSmall ? chol_blocked_work_bytes(n, nb) : 0; }
+
+xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, double *L, void *work) {
     Phase phase_(ctx, "chol_batched");
-    if (n > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "Cholesky larger than 192");
+    if (n > kMaxSmall) {
+        xpcs_status st;
+        if (!work && !(work = scratch_get(ctx, chol_blocked_work_bytes(n, nb), &st))) return st;
+        return launch_chol_blocked(ctx, G, n, nb, 1e-13, L, work);
+    }
     hipLaunchKernelGGL(chol_batched_kernel, dim3(nb), dim3(1024), 0, ctx->stream, G, n, 1e-13, L);
     XPCS_LAUNCH_CHECK(ctx, "chol_batched");
     return XPCS_OK;
@@ -1533,7 +1550,6 @@ xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, d
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
                          const double *T, int m, const double *colscale, const TsOut &out) {
     Phase phase_(ctx, "tsmul");
-    if (n > kMaxSmall || m > kMaxSmall) return fail(ctx, XPCS_EUNSUPPORTED, "tall x small product wider than 192");
     const int64_t span = (out.hi || out.f8) && out.rows_pad > rows ? out.rows_pad : rows;
     dim3 grid((unsigned)((span + 256 * kTsRows - 1) / (256 * kTsRows)), (unsigned)((m + kTsCols - 1) / kTsCols));
     if (a_f64)
@@ -1550,7 +1566,8 @@ xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows,
 
 xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *rot) {
     Phase phase_(ctx, "jacobi");
-    if (n > kMaxSmall || n % 2) return fail(ctx, XPCS_EUNSUPPORTED, "eigen size must be even and <= 192");
+    if (n % 2) return fail(ctx, XPCS_EUNSUPPORTED, "internal: eigen size must be even");
+    if (n > kMaxSmall) return launch_jacobi_block(ctx, B, n, lam, P, rot);
     int *nsteps = static_cast<int *>(rot);
     double2 *log = reinterpret_cast<double2 *>(static_cast<char *>(rot) + 256);
     if (n <= 2 * kSlotMaxH) {

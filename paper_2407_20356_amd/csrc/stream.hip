@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "zrows.hpp"
 
 struct xpcs_stream {
     xpcs_ctx *ctx = nullptr;
@@ -422,7 +423,7 @@ xpcs_status xpcs_stream_open(xpcs_ctx *ctx, const xpcs_stream_desc *d, xpcs_stre
     if (d->n_roi < 1) return fail(ctx, XPCS_EINVAL, "n_roi must be >= 1");
     if (d->n_roi > 64) return fail(ctx, XPCS_EUNSUPPORTED, "a stream records at most 64 ROIs");
     if (d->k < 1 || d->k > d->M) return fail(ctx, XPCS_EINVAL, "k must be in 1..M");
-    if (d->k > kMaxStreamK) return fail(ctx, XPCS_EUNSUPPORTED, "basis wider than 192");
+    if (d->k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "basis wider than 1024");
     if (d->window < 1 || d->window > 65536) return fail(ctx, XPCS_EINVAL, "window must be in 1..65536");
     if (d->max_block < 1 || d->max_block > 4096) return fail(ctx, XPCS_EINVAL, "max_block must be in 1..4096");
     (void)hipSetDevice(ctx->device);
@@ -522,10 +523,17 @@ xpcs_status xpcs_stream_push(xpcs_stream *s, const void *frames, int64_t nb, voi
     // 2. their z rows into the ring
     {
         Phase phase_(ctx, "stream_prep");
-        dim3 grid((unsigned)((nb + kPrepF - 1) / kPrepF), (unsigned)s->n_roi);
-        hipLaunchKernelGGL(stream_prep_kernel, grid, dim3(256), 0, ctx->stream, Zb, nb, Sb, s->roi_npix, s->Lr,
-                           s->k, s->kp, n, s->cap, s->z_hi, s->z_lo, s->valid);
-        XPCS_LAUNCH_CHECK(ctx, "stream_prep");
+        if (s->k > kMaxStreamK) {
+            if ((st = launch_z_rows_wide(ctx, Zb, true, nullptr, nb, 0, Sb, nb, 0, s->roi_npix, 0, s->Lr, s->k,
+                                         s->n_roi, nb, nullptr, s->z_hi, s->z_lo, s->kp, s->valid, s->cap, n,
+                                         s->cap)))
+                return st;
+        } else {
+            dim3 grid((unsigned)((nb + kPrepF - 1) / kPrepF), (unsigned)s->n_roi);
+            hipLaunchKernelGGL(stream_prep_kernel, grid, dim3(256), 0, ctx->stream, Zb, nb, Sb, s->roi_npix, s->Lr,
+                               s->k, s->kp, n, s->cap, s->z_hi, s->z_lo, s->valid);
+            XPCS_LAUNCH_CHECK(ctx, "stream_prep");
+        }
     }
     // 3. band rows and per-tile diagonal sums
     {

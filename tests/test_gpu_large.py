@@ -1,9 +1,9 @@
 """The large workload's shape, through the C ABI: 1536 x 2048 px (3.1 M), uint8 counts
 (mean 0.01, beta 0.2, tau_c 50), 64 annular ROIs, the online strategy (Sec. 2.2).
 
-An offline basis is computed from a 4,096-frame prefix (k = 184 with 8 oversampling
-columns: the widest sketch the FP64 small steps hold, 192) and checked for
-orthonormality.  The stream then runs on an unrelated basis made on the host
+An offline basis is computed from a 4,096-frame prefix at the workload's rank
+(k = 256 with 16 oversampling columns, l = 272: the blocked FP64 small steps) and
+checked for orthonormality.  The stream then runs on an unrelated basis made on the host
 (the ROI indicators plus Gaussian columns, orthonormalised in FP64: Sec. 2.2's
 online strategy with a basis that does not come from the data), so that the oracle's inputs are the frames, the
 labels and that basis only: the frames are pushed in 1,024-frame blocks with a
@@ -49,7 +49,7 @@ def _unrelated_basis(labels, n_roi, k, seed):
         G -= ind @ (ind.T @ G)
         G = G @ np.linalg.inv(np.linalg.cholesky(G.T @ G)).T
     return np.concatenate([ind, G], axis=1)
-N_USED, PREFIX, BLOCK, WINDOW, K, OVERSAMPLE = 8192, 4096, 1024, 8192, 184, 8
+N_USED, PREFIX, BLOCK, WINDOW, K, OVERSAMPLE = 8192, 4096, 1024, 8192, 256, 16
 
 
 def test_large_shape_stream_against_oracle_and_fft_g2():

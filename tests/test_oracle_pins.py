@@ -200,6 +200,19 @@ def test_full_rank_compression_is_lossless():
                                    O.raw_two_time(F, labels, roi), rtol=1e-10, atol=1e-12)
 
 
+def test_full_rank_randomized_basis_on_the_tiny_workload():
+    # Eq. 11 at the tiny workload's shape (4,096 px x 1,000 frames): the randomized
+    # range finder with k = l = N keeps every direction of the data, so the
+    # compressed TTC is the raw TTC.
+    spec = synth.WORKLOADS["tiny_64x64x1000"]
+    F = synth.speckle_frames_numpy(spec.n_pixels, spec.n_frames, spec.mu, spec.beta, spec.tau_c, spec.dtype,
+                                   seed=1001)
+    labels = synth.workload_labels(spec)
+    U, s, V = O.randomized_basis(F, spec.n_frames, oversample=0, power_iters=1, seed=3)
+    np.testing.assert_allclose(O.compressed_two_time(F, U, labels, 0), O.raw_two_time(F, labels, 0),
+                               rtol=1e-10, atol=1e-12)
+
+
 def test_randomized_basis_lossless_on_low_rank_data():
     F = synth.low_rank_frames_numpy(2000, 150, rank=6, seed=4)
     labels = synth.annular_labels(40, 50, 4, r_in=3.0)
