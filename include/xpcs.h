@@ -61,6 +61,8 @@ typedef int32_t xpcs_status;
 /* arithmetic of the compression products (FP32 accumulation in every case) */
 #define XPCS_PREC_BF16 0
 #define XPCS_PREC_FP8 1
+#define XPCS_BASIS_RANDOMIZED 0
+#define XPCS_BASIS_EXACT 1
 
 /* `roi` argument selecting every ROI in one call */
 #define XPCS_ALL_ROIS (-1)
@@ -144,7 +146,20 @@ typedef struct {
  *                (Sec. 2.2, "offline").  Non-NULL: online mode, an M x k
  *                column-major device basis generated beforehand (Sec. 2.2,
  *                "online"); it is copied to out->U and the frames are only
- *                encoded; sigma_j = |W e_j| and V = W diag(1/sigma). */
+ *                encoded; sigma_j = |W e_j| and V = W diag(1/sigma).
+ *   method       offline mode: XPCS_BASIS_RANDOMIZED (above), or XPCS_BASIS_EXACT:
+ *                the paper's own construction (Sec. 2.1, Eqs. 3 and 6) -- the
+ *                exact N x N frame Gram F F^T (FP64 MFMA over the integer counts,
+ *                exact while every sum stays below 2^53: always for uint8, for
+ *                uint16 when M * amax^2 < 2^53), its full FP64 eigendecomposition
+ *                (block Jacobi), the k leading eigenvectors as V (largest-magnitude
+ *                entry positive), sigma = sqrt(eigenvalue) and the basis
+ *                U = X V diag(1/sigma) in FP64.  k = N (with M >= N) is the
+ *                lossless mode of Eq. 11: C~ equals the raw C.  N <= 4096;
+ *                oversample, power_iters, precision and seed are not used.
+ *   spectrum     NULL, or (XPCS_BASIS_EXACT) device, N doubles: every eigenvalue of
+ *                the frame Gram in decreasing order (the input of the rank rule
+ *                of Sec. 3.1, xpcs_rank_rule). */
 typedef struct {
     int32_t k;
     int32_t oversample;
@@ -152,6 +167,9 @@ typedef struct {
     int32_t precision;
     uint64_t seed;
     const float *basis;
+    int32_t method;
+    int32_t reserved;
+    double *spectrum;
 } xpcs_compress_opts;
 
 /* Compress N frames of M pixels (Sec. 2.1, Eqs. 3-7; Sec. 2.2).
@@ -166,8 +184,9 @@ typedef struct {
  * roi_label: device int32[M], values in [-1, n_roi).
  * out: caller-allocated factors with out->M == M, out->N == N, out->k == opts->k,
  *      out->n_roi == n_roi.
- * Errors: EINVAL (null, sizes, k + oversample > min(M, N) offline), EUNSUPPORTED
- * (k + oversample > 192 offline), EBUDGET, ENOMEM. */
+ * Errors: EINVAL (null, sizes, k + oversample > min(M, N) offline, k > min(M, N)
+ * exact), EUNSUPPORTED (k + oversample > 1024 offline, k > 1024, N > 4096 exact),
+ * EBUDGET, ENOMEM. */
 xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M,
                             int64_t N, const int32_t *roi_label, int32_t n_roi,
                             const xpcs_compress_opts *opts, xpcs_factors *out);
@@ -283,6 +302,76 @@ xpcs_status fit_relaxation(xpcs_ctx *ctx, const double *g2, const int64_t *npair
                            int64_t tau_lo, int64_t tau_hi, const double *p0, int32_t max_iter, double *params,
                            int32_t *status);
 
+/* The stretched form of the relaxation law that Sec. 3.1 names after Kohlrausch,
+ * Williams and Watts: g2(tau) = B + beta exp(-2 (Gamma tau)^gamma), the exponent
+ * gamma fitted with (B, beta, Gamma); gamma = 1 is fit_relaxation's form.  Same
+ * arguments with four parameters per ROI: p0 and params are n_roi x 4 doubles
+ * (B, beta, Gamma, gamma); the default start is fit_relaxation's with gamma = 1.
+ * A ROI needs four valid lags (else NaN parameters and status -1).  A trial step
+ * to Gamma <= 0 has no defined model value and is rejected like one that raises
+ * the cost.  Errors as fit_relaxation. */
+xpcs_status fit_relaxation_stretched(xpcs_ctx *ctx, const double *g2, const int64_t *npairs, int64_t n,
+                                     int32_t n_roi, int64_t tau_lo, int64_t tau_hi, const double *p0,
+                                     int32_t max_iter, double *params, int32_t *status);
+
+/* Rank rule of Sec. 3.1: the data is described by the eigenvectors whose
+ * eigenvalues are at least twice the smallest one.  spectrum: device, n doubles
+ * (e.g. compress_frames' spectrum output of the exact basis: the eigenvalues of
+ * the frame Gram, which are those of the pixel Gram).  *rank (device int32) =
+ * the number of entries that are positive and at least factor * min(spectrum)
+ * (factor = 2 in the paper; zero and negative eigenvalues never count).
+ * Errors: EINVAL (NULL, n < 1, factor < 1). */
+xpcs_status xpcs_rank_rule(xpcs_ctx *ctx, const double *spectrum, int64_t n, double factor, int32_t *rank);
+
+/* Peak visibility of g2 (Sec. 3.1: the peak minus the background level of g2)
+ * and its detectability (Sec. 3.2: a correlation peak is observable when it is
+ * stronger than twice the background level of the TTC, its standard deviation).
+ * Per ROI r of g2 (device, n_roi x n, ROI-major; npairs device or NULL: lags
+ * without pairs and non-finite values are skipped):
+ *   visibility[r] = max g2 over the lags [peak_lo, peak_hi)
+ *                   - mean g2 over the lags [bg_lo, bg_hi)   (NaN if a range is empty),
+ *   detectable[r] = visibility[r] > factor * ttc_stdev[r]     (1 / 0).
+ * ttc_stdev: device, n_roi doubles (two_time_stats' stdev), or NULL when
+ * detectable is NULL.  visibility: device, n_roi doubles; detectable: device
+ * int32 or NULL.  Errors: EINVAL (NULL, sizes, empty or out-of-range lag ranges). */
+xpcs_status peak_visibility(xpcs_ctx *ctx, const double *g2, const int64_t *npairs, int32_t n_roi, int64_t n,
+                            int64_t peak_lo, int64_t peak_hi, int64_t bg_lo, int64_t bg_hi, const double *ttc_stdev,
+                            double factor, double *visibility, int32_t *detectable);
+
+/* Frames for an encoding basis that knows nothing of the sample (Sec. 3.2: the
+ * basis is generated from randomly shifted copies of one unrelated image): frame
+ * t is the texture (height x width, row-major, dtype XPCS_U8 or XPCS_U16) shifted
+ * cyclically by (dy_t, dx_t), dy_t = (h mod 2^32) mod height, dx_t = (h >> 32) mod
+ * width, h = SplitMix64(seed XOR t); frames[t][y][x] = texture[(y + dy_t) mod
+ * height][(x + dx_t) mod width].  compress_frames on these frames (offline mode,
+ * randomized or exact) gives the basis, which other series then use in online mode.
+ * texture: device; frames: device, n_frames * height * width elements of dtype.
+ * Errors: EINVAL (NULL, dtype, sizes), EUNSUPPORTED (more than 65535 frames). */
+xpcs_status shifted_texture_frames(xpcs_ctx *ctx, const void *texture, int32_t dtype, int64_t height, int64_t width,
+                                   int64_t n_frames, uint64_t seed, void *frames);
+
+/* ------------------------------------------------------------------ persisted state
+ * The compressed data are what the paper keeps for later calculations (Sec. 3.1;
+ * Sec. 2.2: compressed frames are appended to the compressed series).  The factors
+ * of compress_frames -- with the ROI labels and the sketch seed they came from, if
+ * given -- and an online stream's whole state go to a file and come back to device
+ * memory bit for bit, in this process or another, so that correlations are
+ * recomputed, or a stream resumed, without the raw frames.  Files: an 8-byte magic,
+ * int64 header fields with their FNV-1a 64 hash, then sections of raw little-endian
+ * arrays, each with its length and hash; any mismatch is reported as EINVAL
+ * ("corrupt file").  Calls wait for the context's stream and copy synchronously. */
+xpcs_status xpcs_factors_save(xpcs_ctx *ctx, const xpcs_factors *f, const int32_t *roi_label, uint64_t seed,
+                              const char *path);
+/* Sizes of a factors file (host only, no device work): M, N, k, n_roi, whether it
+ * holds ROI labels, the seed.  Errors: EINVAL (unreadable, not a factors file,
+ * corrupt header). */
+xpcs_status xpcs_factors_info(const char *path, int64_t *M, int64_t *N, int32_t *k, int32_t *n_roi,
+                              int32_t *has_labels, uint64_t *seed);
+/* Loads a factors file into caller-allocated factors of the file's sizes, and the
+ * ROI labels into roi_label (device int32[M]) unless it is NULL.
+ * Errors: EINVAL (NULL, sizes differ, no labels in the file, corrupt file). */
+xpcs_status xpcs_factors_load(xpcs_ctx *ctx, const char *path, xpcs_factors *f, int32_t *roi_label);
+
 /* ------------------------------------------------------------------ online streams
  * The paper's online strategy (Sec. 2.2): the encoding basis is fixed beforehand
  * (e.g. from compress_frames on an earlier measurement or on the first frames of
@@ -336,6 +425,14 @@ xpcs_status xpcs_stream_g2(xpcs_stream *s, double *g2, int64_t *npairs);
 
 /* Frames pushed so far (host value). */
 int64_t xpcs_stream_frames(const xpcs_stream *s);
+
+/* Writes the stream's whole state (labels, basis, ROI factors, the window of
+ * compressed rows, g2 sums, frame count) to `path`; xpcs_stream_load opens a new
+ * stream on ctx from such a file, and pushes to it continue the series exactly
+ * as the saved stream would have (bit-identical bands and g2 sums).
+ * Errors: EINVAL (NULL, unreadable or corrupt file), EBUDGET, ENOMEM. */
+xpcs_status xpcs_stream_save(xpcs_stream *s, const char *path);
+xpcs_status xpcs_stream_load(xpcs_ctx *ctx, const char *path, xpcs_stream **out);
 
 /* Releases the stream's device memory (after the work in flight). NULL is ignored. */
 void xpcs_stream_close(xpcs_stream *s);

@@ -37,6 +37,15 @@ What is computed, and where it comes from:
 * Relaxation fit (Sec. 3.1, Eq. 13): g2(tau) = B + beta * exp(-2 Gamma tau).
 * Background level of a TTC (Sec. 3.2): mean and standard deviation of its
   off-diagonal valid entries.
+* Rank rule (Sec. 3.1): the number of eigenvalues of the data Gram at least
+  twice the smallest one.
+* Peak visibility (Sec. 3.1) and detectability (Sec. 3.2): a g2 peak minus the
+  background level of g2; detectable when above twice the TTC's standard
+  deviation.
+* Stretched relaxation law (Sec. 3.1, named after Kohlrausch, Williams and
+  Watts): g2(tau) = B + beta * exp(-2 (Gamma tau)^gamma).
+* Unrelated encoding basis (Sec. 3.2): frames that are randomly shifted copies
+  of one image.
 """
 
 from __future__ import annotations
@@ -115,6 +124,40 @@ def raw_two_time(F: np.ndarray, labels: np.ndarray, roi: int) -> np.ndarray:
     px = roi_pixels(labels, roi)
     S = np.asarray(F)[:, px].astype(np.int64).sum(axis=1)
     return normalise_two_time(raw_gram(F, labels, roi), S, px.size)
+
+
+def raw_g2_at_lags(F: np.ndarray, labels: np.ndarray, roi: int, lags, chunk: int = 2048
+                   ) -> Tuple[np.ndarray, np.ndarray]:
+    """g2 of the raw two-time correlation (Eqs. 1 and 12) at the given lags only.
+
+    For lag tau every pair (t, t + tau) with photons in both frames contributes
+    C[t, t + tau] = |R| (x_t . x_{t+tau}) / (S_t S_{t+tau}), the dot product of
+    the two frames over the ROI's pixels exact in int64; g2 is their mean.  The
+    frames are taken in chunks so that large series need not be held as int64.
+    Returns (g2, npairs) with one entry per lag.
+    """
+    F = np.asarray(F)
+    px = roi_pixels(labels, roi)
+    n = F.shape[0]
+    S = F[:, px].astype(np.int64).sum(axis=1)
+    g2 = np.full(len(lags), np.nan)
+    npairs = np.zeros(len(lags), dtype=np.int64)
+    for i, tau in enumerate(lags):
+        total, count = 0.0, 0
+        for t0 in range(0, n - tau, chunk):
+            t1 = min(t0 + chunk, n - tau)
+            a = F[t0:t1][:, px].astype(np.int64)
+            b = F[t0 + tau:t1 + tau][:, px].astype(np.int64)
+            dots = (a * b).sum(axis=1)
+            s1, s2 = S[t0:t1], S[t0 + tau:t1 + tau]
+            ok = (s1 > 0) & (s2 > 0)
+            total += float((float(px.size) * dots[ok].astype(np.float64)
+                            / (s1[ok].astype(np.float64) * s2[ok].astype(np.float64))).sum())
+            count += int(ok.sum())
+        npairs[i] = count
+        if count:
+            g2[i] = total / count
+    return g2, npairs
 
 
 # ----------------------------------------------------------------------------
@@ -395,3 +438,92 @@ def siegert_fit(g2: np.ndarray, taus: np.ndarray,
     sol = least_squares(resid, np.asarray(p0, dtype=np.float64), method="lm")
     B, beta, gamma = sol.x
     return float(B), float(beta), float(gamma)
+
+
+def kww_fit(g2: np.ndarray, taus: np.ndarray,
+            p0: Optional[Tuple[float, float, float, float]] = None) -> Tuple[float, float, float, float]:
+    """Least-squares fit of g2(tau) = B + beta * exp(-2 (Gamma tau)^gamma); returns
+    (B, beta, Gamma, gamma).  gamma = 1 is the form of siegert_fit."""
+    from scipy.optimize import least_squares
+
+    taus = np.asarray(taus, dtype=np.float64)
+    y = np.asarray(g2, dtype=np.float64)
+    if p0 is None:
+        p0 = (float(y[-1]), float(max(y[0] - y[-1], 1e-3)), 1.0 / max(taus.mean(), 1.0), 1.0)
+
+    def resid(p):
+        with np.errstate(invalid="ignore"):
+            return p[0] + p[1] * np.exp(-2.0 * np.power(p[2] * taus, p[3])) - y
+
+    sol = least_squares(resid, np.asarray(p0, dtype=np.float64), method="lm", xtol=1e-15, ftol=1e-15,
+                        gtol=1e-15, max_nfev=20000)
+    B, beta, gamma_rate, expo = sol.x
+    return float(B), float(beta), float(gamma_rate), float(expo)
+
+
+# ----------------------------------------------------------------------------
+# Rank rule, peak visibility, detectability (Sec. 3.1, Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+
+def gram_spectrum(F: np.ndarray) -> np.ndarray:
+    """Every eigenvalue of the frame Gram F F^T (equal to the nonzero ones of the
+    pixel Gram), in decreasing order."""
+    Fd = np.asarray(F).astype(np.float64)
+    return np.sort(np.linalg.eigvalsh(Fd @ Fd.T))[::-1]
+
+
+def rank_rule(spectrum: np.ndarray, factor: float = 2.0) -> int:
+    """How many eigenvalues are at least `factor` times the smallest one (Sec. 3.1:
+    the eigenvectors that describe the data); zero or negative ones never count."""
+    lam = np.asarray(spectrum, dtype=np.float64)
+    lo = factor * lam.min()
+    return int(np.count_nonzero((lam > 0.0) & (lam >= lo)))
+
+
+def peak_visibility(g2: np.ndarray, npairs: Optional[np.ndarray], peak: Tuple[int, int],
+                    background: Tuple[int, int]) -> float:
+    """The highest g2 over the lags [peak[0], peak[1]) minus the mean g2 over the lags
+    [background[0], background[1]) (Sec. 3.1), valid lags only; NaN if a range has none."""
+    g2 = np.asarray(g2, dtype=np.float64)
+    ok = np.isfinite(g2) if npairs is None else (np.asarray(npairs) > 0) & np.isfinite(g2)
+    pk = [g2[t] for t in range(peak[0], peak[1]) if ok[t]]
+    bg = [g2[t] for t in range(background[0], background[1]) if ok[t]]
+    if not pk or not bg:
+        return math.nan
+    return max(pk) - sum(bg) / len(bg)
+
+
+def detectable(visibility: float, ttc_stdev: float, factor: float = 2.0) -> bool:
+    """A correlation peak counts as observable when it is stronger than `factor` times
+    the background level of the TTC, its standard deviation (Sec. 3.2)."""
+    return bool(visibility > factor * ttc_stdev)
+
+
+# ----------------------------------------------------------------------------
+# Encoding basis from unrelated images (Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+
+def texture_shifts(n_frames: int, seed: int, height: int, width: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Cyclic shifts (dy_t, dx_t) of frame t: h = SplitMix64(seed XOR t),
+    dy = (h mod 2^32) mod height, dx = (h >> 32) mod width."""
+    h = splitmix64(np.uint64(seed) ^ np.arange(n_frames, dtype=np.uint64))
+    dy = (h & np.uint64(0xFFFFFFFF)) % np.uint64(height)
+    dx = (h >> np.uint64(32)) % np.uint64(width)
+    return dy.astype(np.int64), dx.astype(np.int64)
+
+
+def shifted_texture_frames(texture: np.ndarray, n_frames: int, seed: int) -> np.ndarray:
+    """(n_frames, H*W): frame t is the texture moved cyclically so that its pixel
+    (y, x) holds texture[(y + dy_t) mod H, (x + dx_t) mod W]."""
+    tex = np.asarray(texture)
+    H, W = tex.shape
+    dy, dx = texture_shifts(n_frames, seed, H, W)
+    out = np.empty((n_frames, H * W), dtype=tex.dtype)
+    for t in range(n_frames):
+        rows = (np.arange(H) + dy[t]) % H
+        cols = (np.arange(W) + dx[t]) % W
+        out[t] = tex[np.ix_(rows, cols)].ravel()
+    return out
+

@@ -33,6 +33,8 @@ XPCS_F32 = 10
 XPCS_F64 = 11
 XPCS_PREC_BF16 = 0
 XPCS_PREC_FP8 = 1
+XPCS_BASIS_RANDOMIZED = 0
+XPCS_BASIS_EXACT = 1
 XPCS_ALL_ROIS = -1
 
 
@@ -50,6 +52,7 @@ class XpcsCompressOpts(ctypes.Structure):
         ("k", ctypes.c_int32), ("oversample", ctypes.c_int32),
         ("power_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("basis", ctypes.c_void_p),
+        ("method", ctypes.c_int32), ("reserved", ctypes.c_int32), ("spectrum", ctypes.c_void_p),
     ]
 
 
@@ -86,6 +89,16 @@ SIGNATURES = {
     "g2_from_factors": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _P]),
     "fit_relaxation": (_ST, [_P, _P, _P, _I64, _I32, _I64, _I64, _P, _I32, _P, _P]),
     "two_time_stats": (_ST, [_P, ctypes.POINTER(XpcsFactors), _I32, _I64, _I64, _P, _P, _P]),
+    "fit_relaxation_stretched": (_ST, [_P, _P, _P, _I64, _I32, _I64, _I64, _P, _I32, _P, _P]),
+    "xpcs_rank_rule": (_ST, [_P, _P, _I64, ctypes.c_double, _P]),
+    "peak_visibility": (_ST, [_P, _P, _P, _I32, _I64, _I64, _I64, _I64, _I64, _P, ctypes.c_double, _P, _P]),
+    "shifted_texture_frames": (_ST, [_P, _P, _I32, _I64, _I64, _I64, ctypes.c_uint64, _P]),
+    "xpcs_factors_save": (_ST, [_P, ctypes.POINTER(XpcsFactors), _P, ctypes.c_uint64, ctypes.c_char_p]),
+    "xpcs_factors_info": (_ST, [ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_uint64)]),
+    "xpcs_factors_load": (_ST, [_P, ctypes.c_char_p, ctypes.POINTER(XpcsFactors), _P]),
+    "xpcs_stream_save": (_ST, [_P, ctypes.c_char_p]),
+    "xpcs_stream_load": (_ST, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
     "xpcs_enable_phase_timing": (_ST, [_P, _I32]),
     "xpcs_phase_times": (_ST, [_P, _I32, _P, _P, _P, ctypes.POINTER(_I32)]),
     "xpcs_stream_open": (_ST, [_P, ctypes.POINTER(XpcsStreamDesc), ctypes.POINTER(_P)]),

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import List, Optional, Tuple
 
@@ -139,9 +140,13 @@ class Factors:
 def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int, k: int,
                     oversample: int = 16, power_iters: int = 1, seed: int = 0,
                     basis: Optional[torch.Tensor] = None, out: Optional[Factors] = None,
-                    precision: str = "bf16") -> Factors:
+                    precision: str = "bf16", method: str = "randomized",
+                    spectrum: Optional[torch.Tensor] = None) -> Factors:
     """frames: (N, M) uint8/uint16 device tensor; roi_label: (M,) int32; basis: optional (k, M) float32;
-    precision: "bf16" or "fp8" (the subspace passes on e4m3 operands, uint8 frames)."""
+    precision: "bf16" or "fp8" (the subspace passes on e4m3 operands, uint8 frames);
+    method: "randomized" or "exact" (eigendecomposition of the exact frame Gram, N <= 4096);
+    spectrum: optional (N,) float64 output, the frame Gram's eigenvalues in decreasing order
+    (method "exact")."""
     _check_device(frames, "frames", ctx.device)
     _check_device(roi_label, "roi_label", ctx.device)
     if roi_label.dtype != torch.int32:
@@ -153,8 +158,14 @@ def compress_frames(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor,
             raise ValueError("basis must be a (k, M) float32 tensor")
     f = out if out is not None else Factors.empty(M, N, k, n_roi, ctx.device)
     prec = {"bf16": L.XPCS_PREC_BF16, "fp8": L.XPCS_PREC_FP8}[precision]
+    meth = {"randomized": L.XPCS_BASIS_RANDOMIZED, "exact": L.XPCS_BASIS_EXACT}[method]
+    if spectrum is not None:
+        _check_device(spectrum, "spectrum", ctx.device)
+        if spectrum.dtype != torch.float64 or spectrum.numel() < frames.shape[0]:
+            raise ValueError("spectrum must be a float64 tensor of N elements")
     opts = L.XpcsCompressOpts(k, oversample, power_iters, prec, seed & (2 ** 64 - 1),
-                              basis.data_ptr() if basis is not None else None)
+                              basis.data_ptr() if basis is not None else None, meth, 0,
+                              spectrum.data_ptr() if spectrum is not None else None)
     fs = f.struct()
     ctx.bind_stream()
     ctx.check(ctx.lib.compress_frames(ctx.handle, _ptr(frames), _frame_dtype(frames), M, N, _ptr(roi_label),
@@ -302,6 +313,112 @@ def fit_relaxation(ctx: Context, g2: torch.Tensor, npairs: Optional[torch.Tensor
     return params, status
 
 
+def fit_relaxation_stretched(ctx: Context, g2: torch.Tensor, npairs: Optional[torch.Tensor] = None,
+                             tau_lo: int = 1, tau_hi: Optional[int] = None, p0: Optional[torch.Tensor] = None,
+                             max_iter: int = 200) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Fit g2(tau) = B + beta exp(-2 (Gamma tau)^gamma) per ROI over lags [tau_lo, tau_hi).
+
+    As fit_relaxation with four parameters: p0 optional (n_roi, 4) float64; returns
+    (params (n_roi, 4) = B, beta, Gamma, gamma; status (n_roi,) int32)."""
+    if g2.dim() == 1:
+        g2 = g2[None]
+        npairs = None if npairs is None else npairs[None]
+    if g2.dtype != torch.float64 or not g2.is_contiguous():
+        raise ValueError("g2 must be a contiguous float64 tensor")
+    n_roi, n = g2.shape
+    tau_hi = n if tau_hi is None else tau_hi
+    if npairs is not None and (npairs.dtype != torch.int64 or tuple(npairs.shape) != (n_roi, n)
+                               or not npairs.is_contiguous()):
+        raise ValueError("npairs must be a contiguous int64 tensor shaped like g2")
+    if p0 is not None and (p0.dtype != torch.float64 or tuple(p0.shape) != (n_roi, 4) or not p0.is_contiguous()):
+        raise ValueError("p0 must be a contiguous (n_roi, 4) float64 tensor")
+    params = torch.empty((n_roi, 4), dtype=torch.float64, device=g2.device)
+    status = torch.empty((n_roi,), dtype=torch.int32, device=g2.device)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.fit_relaxation_stretched(ctx.handle, _ptr(g2), _ptr(npairs), n, n_roi, tau_lo, tau_hi,
+                                               _ptr(p0), max_iter, _ptr(params), _ptr(status)))
+    return params, status
+
+
+def rank_rule(ctx: Context, spectrum: torch.Tensor, factor: float = 2.0) -> torch.Tensor:
+    """Number of eigenvalues at least `factor` times the smallest (Sec. 3.1), as a
+    device int32 scalar tensor."""
+    if spectrum.dtype != torch.float64 or spectrum.dim() != 1 or not spectrum.is_contiguous():
+        raise ValueError("spectrum must be a contiguous 1-D float64 tensor")
+    rank = torch.empty((), dtype=torch.int32, device=spectrum.device)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.xpcs_rank_rule(ctx.handle, _ptr(spectrum), spectrum.numel(), float(factor), _ptr(rank)))
+    return rank
+
+
+def peak_visibility(ctx: Context, g2: torch.Tensor, npairs: Optional[torch.Tensor], peak: Tuple[int, int],
+                    background: Tuple[int, int], ttc_stdev: Optional[torch.Tensor] = None,
+                    factor: float = 2.0):
+    """Peak visibility of g2 per ROI (peak lags [peak[0], peak[1]), background lags
+    [background[0], background[1])), and -- with ttc_stdev -- whether the peak is
+    detectable (visibility > factor * stdev).  Returns (visibility, detectable or None)."""
+    if g2.dim() == 1:
+        g2 = g2[None]
+        npairs = None if npairs is None else npairs[None]
+    if g2.dtype != torch.float64 or not g2.is_contiguous():
+        raise ValueError("g2 must be a contiguous float64 tensor")
+    n_roi, n = g2.shape
+    vis = torch.empty((n_roi,), dtype=torch.float64, device=g2.device)
+    det = torch.empty((n_roi,), dtype=torch.int32, device=g2.device) if ttc_stdev is not None else None
+    ctx.bind_stream()
+    ctx.check(ctx.lib.peak_visibility(ctx.handle, _ptr(g2), _ptr(npairs), n_roi, n, peak[0], peak[1],
+                                      background[0], background[1], _ptr(ttc_stdev), float(factor), _ptr(vis),
+                                      _ptr(det)))
+    return vis, det
+
+
+def shifted_texture_frames(ctx: Context, texture: torch.Tensor, n_frames: int, seed: int) -> torch.Tensor:
+    """n_frames cyclically shifted copies of a (H, W) uint8/uint16 texture, flattened
+    to (n_frames, H * W): the frames of an encoding basis made from unrelated data."""
+    _check_device(texture, "texture", ctx.device)
+    if texture.dim() != 2 or not texture.is_contiguous():
+        raise ValueError("texture must be a contiguous (H, W) tensor")
+    H, W = texture.shape
+    frames = torch.empty((n_frames, H * W), dtype=texture.dtype, device=texture.device)
+    ctx.bind_stream()
+    ctx.check(ctx.lib.shifted_texture_frames(ctx.handle, _ptr(texture), _frame_dtype(texture), H, W, n_frames,
+                                             seed & (2 ** 64 - 1), _ptr(frames)))
+    return frames
+
+
+def save_factors(ctx: Context, f: Factors, path: str, roi_label: Optional[torch.Tensor] = None, seed: int = 0):
+    """Write the factors (and the ROI labels, if given) to `path` (xpcs_factors_save)."""
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.xpcs_factors_save(ctx.handle, ctypes.byref(fs), _ptr(roi_label), seed & (2 ** 64 - 1),
+                                        os.fsencode(path)))
+
+
+def factors_info(path: str) -> dict:
+    """Sizes, label presence and seed of a factors file (host only)."""
+    lib = L.load()
+    M, N = ctypes.c_int64(), ctypes.c_int64()
+    k, nr, hl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    seed = ctypes.c_uint64()
+    st = lib.xpcs_factors_info(os.fsencode(path), ctypes.byref(M), ctypes.byref(N), ctypes.byref(k),
+                               ctypes.byref(nr), ctypes.byref(hl), ctypes.byref(seed))
+    if st != L.XPCS_OK:
+        raise XpcsError(st, f"cannot read the factors file {path}")
+    return dict(M=M.value, N=N.value, k=k.value, n_roi=nr.value, has_labels=bool(hl.value), seed=seed.value)
+
+
+def load_factors(ctx: Context, path: str, with_labels: bool = True):
+    """Factors (and ROI labels, when the file has them and with_labels) from `path`."""
+    info = factors_info(path)
+    f = Factors.empty(info["M"], info["N"], info["k"], info["n_roi"], ctx.device)
+    labels = (torch.empty((info["M"],), dtype=torch.int32, device=ctx.device)
+              if with_labels and info["has_labels"] else None)
+    fs = f.struct()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.xpcs_factors_load(ctx.handle, os.fsencode(path), ctypes.byref(fs), _ptr(labels)))
+    return f, labels
+
+
 def correlate_two_time_raw(ctx: Context, frames: torch.Tensor, roi_label: torch.Tensor, n_roi: int,
                            roi: int = L.XPCS_ALL_ROIS, t0: int = 0, t1: Optional[int] = None,
                            want_c: bool = True, c_dtype=torch.float32, want_g2: bool = True,
@@ -387,6 +504,24 @@ class Stream:
     @property
     def frames(self) -> int:
         return int(self.ctx.lib.xpcs_stream_frames(self.handle))
+
+    def save(self, path: str):
+        """Write the stream's whole state to `path` (xpcs_stream_save)."""
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.xpcs_stream_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx: Context, path: str, n_roi: int, window: int, dtype=torch.uint8) -> "Stream":
+        """Open a stream from a file written by save() (xpcs_stream_load); n_roi, window
+        and dtype size the arrays this wrapper returns and must match the file."""
+        s = cls.__new__(cls)
+        s.ctx, s.n_roi, s.window = ctx, n_roi, window
+        s.dtype_code = L.XPCS_U8 if dtype == torch.uint8 else L.XPCS_U16
+        h = ctypes.c_void_p()
+        ctx.bind_stream()
+        ctx.check(ctx.lib.xpcs_stream_load(ctx.handle, os.fsencode(path), ctypes.byref(h)))
+        s.handle = h
+        return s
 
     def close(self):
         if getattr(self, "handle", None):

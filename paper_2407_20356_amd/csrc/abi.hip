@@ -140,6 +140,73 @@ struct Orth {
     }
 };
 
+constexpr int kMaxExactFrames = 4096;
+
+// The paper's construction of the basis (Sec. 2.1, Eqs. 3 and 6): the exact frame Gram
+// F F^T, its full FP64 eigendecomposition, the k leading eigenvectors V and
+// sigma = sqrt(eigenvalue), the pixel basis U = X V diag(1/sigma) in FP64; the exact ROI
+// sums come from the encoding pass over the frames with that basis.
+xpcs_status compress_exact(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M, int64_t N,
+                           const int32_t *roi_label, int32_t n_roi, int k, double *spectrum, xpcs_factors *out) {
+    if (N > kMaxExactFrames) return fail(ctx, XPCS_EUNSUPPORTED, "the exact basis takes at most 4096 frames");
+    if (k > M || k > N) return fail(ctx, XPCS_EINVAL, "k larger than min(M, N)");
+    if (k > kMaxRank) return fail(ctx, XPCS_EUNSUPPORTED, "rank above 1024");
+    (void)hipSetDevice(ctx->device);
+    ws_begin(ctx);
+    const int L = (int)up(k, 16);
+    const int64_t ldq = up(M, 64);
+    const FrameProj plan = plan_proj_frames(M, N, L, n_roi, true);
+    size_t need = 0;
+    auto add = [&](size_t b) { need += align_up(b, 256) + 256; };
+    const size_t b_nn = (size_t)N * N * 8, b_tu = (size_t)N * k * 8, b_q16 = (size_t)L * ldq * 2;
+    const size_t b_part = (size_t)plan.nchunks * plan.ncols * N * 4, b_z = (size_t)L * N * 8;
+    add(b_nn); add(b_nn); add((size_t)N * 8); add(jacobi_block_work_bytes((int)N)); add(b_tu); add((size_t)k * 8);
+    add((size_t)k * k * 8); add(b_q16); add(b_q16); add(b_part); add(b_z);
+    add((size_t)(n_roi + 1) * 8); add((size_t)(M + n_roi) * 4); add((size_t)(M + n_roi) * 4);
+    xpcs_status st;
+    if ((st = ws_reserve(ctx, need))) return st;
+    auto *H = static_cast<double *>(ws_take(ctx, b_nn));
+    auto *P = static_cast<double *>(ws_take(ctx, b_nn));
+    auto *lam = static_cast<double *>(ws_take(ctx, (size_t)N * 8));
+    void *jw = ws_take(ctx, jacobi_block_work_bytes((int)N));
+    auto *Tu = static_cast<double *>(ws_take(ctx, b_tu));
+    auto *scale = static_cast<double *>(ws_take(ctx, (size_t)k * 8));
+    auto *Tid = static_cast<double *>(ws_take(ctx, (size_t)k * k * 8));
+    auto *qhi = static_cast<unsigned short *>(ws_take(ctx, b_q16));
+    auto *qlo = static_cast<unsigned short *>(ws_take(ctx, b_q16));
+    auto *part = static_cast<float *>(ws_take(ctx, b_part));
+    auto *Za = static_cast<double *>(ws_take(ctx, b_z));
+    auto *off = static_cast<int64_t *>(ws_take(ctx, (size_t)(n_roi + 1) * 8));
+    auto *perm = static_cast<int32_t *>(ws_take(ctx, (size_t)(M + n_roi) * 4));
+    auto *qroi = static_cast<int32_t *>(ws_take(ctx, (size_t)(M + n_roi) * 4));
+
+    if ((st = launch_roi_count(ctx, roi_label, M, n_roi, out->roi_npix))) return st;
+    // Eq. 3: the Gram of the data and its eigenvectors, Eq. 6: the K largest
+    if ((st = launch_frame_gram(ctx, frames, dtype, M, N, H))) return st;
+    {
+        Phase phase_(ctx, "jacobi");
+        if ((st = launch_jacobi_block(ctx, H, (int)N, lam, P, jw))) return st;
+    }
+    if ((st = launch_select_exact(ctx, lam, P, (int)N, k, Tu, scale, out->sigma, spectrum))) return st;
+    // U = X V diag(1 / sigma) (the paper's pixel-space encoding vectors), V = the eigenvectors
+    TsOut ou;
+    ou.out32 = out->U;
+    ou.ld32 = M;
+    if ((st = launch_tsmul_counts(ctx, frames, dtype, M, N, Tu, k, scale, ou))) return st;
+    if ((st = launch_identity(ctx, Tid, k))) return st;
+    TsOut ov;
+    ov.out32 = out->V;
+    ov.ld32 = N;
+    if ((st = launch_tsmul(ctx, Tu, true, N, N, k, Tid, k, nullptr, ov))) return st;
+    // the exact ROI sums ride along the encoding pass W = X^T U (Eq. 7)
+    if ((st = launch_basis_to_bf16(ctx, out->U, M, k, ldq, L, qhi, qlo))) return st;
+    if ((st = launch_proj_frames(ctx, frames, dtype, M, N, qhi, qlo, ldq, L, roi_label, n_roi, plan, part))) return st;
+    if ((st = launch_proj_frames_reduce(ctx, part, plan, N, L, n_roi, Za, N, out->roi_sum))) return st;
+    // per-ROI basis Gram G_R = U_R^T U_R
+    if ((st = launch_roi_order(ctx, roi_label, M, n_roi, out->roi_npix, 1, off, perm, qroi, M + n_roi))) return st;
+    return launch_tsgram(ctx, out->U, false, M, M, k, perm, off, n_roi, out->roi_gram);
+}
+
 }  // namespace
 
 extern "C" {
@@ -163,6 +230,10 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     const bool fp8 = opts->precision == XPCS_PREC_FP8 && !opts->basis;
     if (fp8 && dtype != XPCS_U8) return fail(ctx, XPCS_EUNSUPPORTED, "XPCS_PREC_FP8 takes XPCS_U8 frames");
     if (n_roi > 64) return fail(ctx, XPCS_EUNSUPPORTED, "compress_frames records at most 64 ROI sums");
+    if (opts->method != XPCS_BASIS_RANDOMIZED && opts->method != XPCS_BASIS_EXACT)
+        return fail(ctx, XPCS_EINVAL, "method must be XPCS_BASIS_RANDOMIZED or XPCS_BASIS_EXACT");
+    if (!opts->basis && opts->method == XPCS_BASIS_EXACT)
+        return compress_exact(ctx, frames, dtype, M, N, roi_label, n_roi, k, opts->spectrum, out);
     const bool online = opts->basis != nullptr;
     int ell = k + (opts->oversample > 0 ? opts->oversample : 0);
     ell += ell & 1;                                 // the eigensolver pairs columns

@@ -599,7 +599,15 @@ __global__ __launch_bounds__(kPgThreads) void panel_gram_kernel(const TA *__rest
                 const int c = (p == 0 ? I : J) * kT + 16 * cb + cl;
                 const TA *src = A + (int64_t)(c < ncols ? c : 0) * lda;
                 if (v4 && c < ncols) {
-                    if constexpr (sizeof(TA) == 4) {
+                    if constexpr (sizeof(TA) == 1) {
+                        const unsigned v = *reinterpret_cast<const unsigned *>(src + r);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x[p][cb][j] = (TA)((v >> (8 * j)) & 0xffu);
+                    } else if constexpr (sizeof(TA) == 2) {
+                        const uint2 v = *reinterpret_cast<const uint2 *>(src + r);
+                        x[p][cb][0] = (TA)(v.x & 0xffffu); x[p][cb][1] = (TA)(v.x >> 16);
+                        x[p][cb][2] = (TA)(v.y & 0xffffu); x[p][cb][3] = (TA)(v.y >> 16);
+                    } else if constexpr (sizeof(TA) == 4) {
                         const float4 v = *reinterpret_cast<const float4 *>(src + r);
                         x[p][cb][0] = v.x; x[p][cb][1] = v.y; x[p][cb][2] = v.z; x[p][cb][3] = v.w;
                     } else {
@@ -770,8 +778,23 @@ xpcs_status launch_jacobi_block(xpcs_ctx *ctx, const double *Bs, int n, double *
 
 // Gram of a tall matrix (or of each segment of a gathered row list) over 64-column
 // panel pairs, for any number of columns.
+// a_type: XPCS_F32, XPCS_F64, XPCS_U8 / XPCS_U16 counts (the frame Gram F F^T of integer
+// counts is exact in FP64 while every sum stays below 2^53).
+static xpcs_status panel_gram_any(xpcs_ctx *ctx, const void *A, int a_type, int64_t rows, int64_t lda, int ncols,
+                                  const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G);
+
 xpcs_status launch_panel_gram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
                               const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G) {
+    return panel_gram_any(ctx, A, a_f64 ? XPCS_F64 : XPCS_F32, rows, lda, ncols, row_idx, seg_off, nseg, G);
+}
+
+xpcs_status launch_frame_gram(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N, double *G) {
+    Phase phase_(ctx, "frame_gram");
+    return panel_gram_any(ctx, frames, dtype, M, M, (int)N, nullptr, nullptr, 1, G);
+}
+
+static xpcs_status panel_gram_any(xpcs_ctx *ctx, const void *A, int a_type, int64_t rows, int64_t lda, int ncols,
+                                  const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G) {
     const int np = (ncols + kT - 1) / kT, npairs = np * (np + 1) / 2;
     const int64_t seg_rows = seg_off ? rows / (nseg > 0 ? nseg : 1) : rows;
     int nparts = (int)(seg_rows / 256);
@@ -782,15 +805,27 @@ xpcs_status launch_panel_gram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t 
     double *part = static_cast<double *>(
         scratch_get(ctx, (size_t)nseg * npairs * nparts * kT * kT * sizeof(double), &st));
     if (!part) return st;
-    const size_t esz = a_f64 ? 8 : 4;
+    const size_t esz = a_type == XPCS_F64 ? 8 : (a_type == XPCS_F32 ? 4 : (a_type == XPCS_U8 ? 1 : 2));
     const bool vec = !row_idx && !seg_off && lda % 4 == 0 && (uintptr_t)A % (4 * esz) == 0;
     dim3 grid(nparts, npairs, nseg);
-    if (a_f64)
-        hipLaunchKernelGGL(panel_gram_kernel<double>, grid, dim3(kPgThreads), 0, ctx->stream,
-                           static_cast<const double *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
-    else
-        hipLaunchKernelGGL(panel_gram_kernel<float>, grid, dim3(kPgThreads), 0, ctx->stream,
-                           static_cast<const float *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
+    switch (a_type) {
+        case XPCS_F64:
+            hipLaunchKernelGGL(panel_gram_kernel<double>, grid, dim3(kPgThreads), 0, ctx->stream,
+                               static_cast<const double *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
+            break;
+        case XPCS_F32:
+            hipLaunchKernelGGL(panel_gram_kernel<float>, grid, dim3(kPgThreads), 0, ctx->stream,
+                               static_cast<const float *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
+            break;
+        case XPCS_U8:
+            hipLaunchKernelGGL(panel_gram_kernel<uint8_t>, grid, dim3(kPgThreads), 0, ctx->stream,
+                               static_cast<const uint8_t *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
+            break;
+        default:
+            hipLaunchKernelGGL(panel_gram_kernel<uint16_t>, grid, dim3(kPgThreads), 0, ctx->stream,
+                               static_cast<const uint16_t *>(A), rows, lda, ncols, row_idx, seg_off, part, vec);
+            break;
+    }
     XPCS_LAUNCH_CHECK(ctx, "panel_gram");
     const int64_t n2 = (int64_t)ncols * ncols;
     hipLaunchKernelGGL(panel_gram_reduce_kernel, dim3((unsigned)((n2 + 255) / 256), nseg), dim3(256), 0, ctx->stream,

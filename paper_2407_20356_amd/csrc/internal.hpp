@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <stdio.h>
 
 #include <string>
 #include <vector>
@@ -126,6 +127,22 @@ class Phase {
         hipError_t e_ = hipGetLastError();                                    \
         if (e_ != hipSuccess) return ::xpcs::check_hip((ctx), e_, (what));    \
     } while (0)
+
+// ---------------------------------------------------------------- persisted state (persist.hip)
+// FNV-1a 64 hash of n bytes continuing from h.
+uint64_t fnv1a64(const void *p, size_t n, uint64_t h);
+// A checksummed state file: magic, int64 header fields with their hash, then
+// sections of device memory, each with its length and hash.
+struct PersistFile {
+    FILE *fp = nullptr;
+    ~PersistFile();
+    xpcs_status open_write(const char *path);
+    xpcs_status open_read(const char *path);
+    xpcs_status write_header(const char *magic, const int64_t *fields, int nfields);
+    xpcs_status read_header(const char *magic, int64_t *fields, int nfields);
+    xpcs_status write_device(xpcs_ctx *ctx, const void *dev, size_t bytes);
+    xpcs_status read_device(xpcs_ctx *ctx, void *dev, size_t bytes);
+};
 
 // ---------------------------------------------------------------- ROI bookkeeping (ingest.hip)
 // roi_npix[r] (int64) and label validation.
@@ -253,6 +270,10 @@ struct TsOut {
 };
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
                          const double *T, int m, const double *colscale, const TsOut &out);
+// out = X T with X the frames read as the column-major M x N count matrix (FP64
+// accumulation of exact products), T column-major N x m, optional column scale.
+xpcs_status launch_tsmul_counts(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
+                                const double *T, int m, const double *colscale, const TsOut &out);
 // Symmetric eigendecomposition of B (n x n, n even) by cyclic Jacobi (parallel
 // order on chip up to 192, block Jacobi above): eigenvalues lam[n] (unsorted),
 // eigenvectors P (row-major n x n, column j = vector j).  `rot` holds the rotation
@@ -266,6 +287,11 @@ xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, do
 xpcs_status launch_select_basis(xpcs_ctx *ctx, const double *lam, const double *P, int n, int k,
                                 const double *Wl, int64_t N, int64_t ldw, double *T_u,
                                 double *scale_v, double *sigma);
+// The same selection for the exact basis: T_u = the k leading eigenvectors (columns
+// of P, sign: largest-magnitude entry positive), sigma = sqrt(max(lam, 0)),
+// scale_v = 1 / sigma; spectrum (optional) = all n eigenvalues in decreasing order.
+xpcs_status launch_select_exact(xpcs_ctx *ctx, const double *lam, const double *P, int n, int k, double *T_u,
+                                double *scale_v, double *sigma, double *spectrum);
 // Online mode: sigma[j] = |W[:, j]|, scale[j] = 1 / sigma[j] (0 if sigma is 0).
 xpcs_status launch_column_norms(xpcs_ctx *ctx, const double *W, int64_t N, int64_t ldw, int k,
                                 double *sigma, double *scale);
@@ -286,6 +312,9 @@ size_t jacobi_block_work_bytes(int n);
 xpcs_status launch_jacobi_block(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *work);
 xpcs_status launch_panel_gram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int ncols,
                               const int32_t *row_idx, const int64_t *seg_off, int nseg, double *G);
+// The frame Gram F F^T (N x N, FP64) of N frames of M integer counts: exact while
+// every sum stays below 2^53 (always for uint8; M amax^2 < 2^53 for uint16).
+xpcs_status launch_frame_gram(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N, double *G);
 
 // ---------------------------------------------------------------- compressed TTC prep (lowrank.hip)
 // Per ROI r (Lr = Cholesky factor of G_R, row-major lower, nr x k x k) and frame t of

@@ -1319,6 +1319,20 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(const double *__restrict_
     }
 }
 
+// spectrum[rank(j)] = lam[j]: every eigenvalue in decreasing order (ties by index).
+__global__ __launch_bounds__(256) void spectrum_kernel(const double *__restrict__ lam, int n,
+                                                       double *__restrict__ spectrum) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double lj = lam[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+        const double li = lam[i];
+        rank += (li > lj) || (li == lj && i < j);
+    }
+    spectrum[rank] = lj;
+}
+
 __global__ __launch_bounds__(256) void column_norm_kernel(const double *__restrict__ W, int64_t N, int64_t ldw,
                                                           double *__restrict__ sigma, double *__restrict__ scale) {
     const int j = blockIdx.x;
@@ -1564,6 +1578,22 @@ xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows,
     return XPCS_OK;
 }
 
+xpcs_status launch_tsmul_counts(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
+                                const double *T, int m, const double *colscale, const TsOut &out) {
+    Phase phase_(ctx, "tsmul");
+    dim3 grid((unsigned)((M + 256 * kTsRows - 1) / (256 * kTsRows)), (unsigned)((m + kTsCols - 1) / kTsCols));
+    if (dtype == XPCS_U8)
+        hipLaunchKernelGGL(tsmul_kernel<uint8_t>, grid, dim3(256), 0, ctx->stream, static_cast<const uint8_t *>(frames),
+                           M, M, (int)N, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo,
+                           out.f8, out.ldh, out.Lpad, out.rows_pad);
+    else
+        hipLaunchKernelGGL(tsmul_kernel<uint16_t>, grid, dim3(256), 0, ctx->stream,
+                           static_cast<const uint16_t *>(frames), M, M, (int)N, T, m, colscale, out.out32, out.ld32,
+                           out.out64, out.ld64, out.hi, out.lo, out.f8, out.ldh, out.Lpad, out.rows_pad);
+    XPCS_LAUNCH_CHECK(ctx, "tsmul");
+    return XPCS_OK;
+}
+
 xpcs_status launch_jacobi(xpcs_ctx *ctx, const double *B, int n, double *lam, double *P, void *rot) {
     Phase phase_(ctx, "jacobi");
     if (n % 2) return fail(ctx, XPCS_EUNSUPPORTED, "internal: eigen size must be even");
@@ -1605,6 +1635,25 @@ xpcs_status launch_select_basis(xpcs_ctx *ctx, const double *lam, const double *
     if (st != XPCS_OK) return st;
     hipLaunchKernelGGL(sign_fix_kernel, dim3(k), dim3(256), 0, ctx->stream, Wk, N, N, n, T_u, sigma, scale_v);
     XPCS_LAUNCH_CHECK(ctx, "sign_fix");
+    return XPCS_OK;
+}
+
+xpcs_status launch_select_exact(xpcs_ctx *ctx, const double *lam, const double *P, int n, int k, double *T_u,
+                                double *scale_v, double *sigma, double *spectrum) {
+    Phase phase_(ctx, "select_basis");
+    xpcs_status st;
+    int *perm = static_cast<int *>(scratch_get(ctx, (size_t)k * sizeof(int), &st));
+    if (!perm) return st;
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, ctx->stream, lam, P, n, k, T_u, sigma, perm);
+    XPCS_LAUNCH_CHECK(ctx, "select");
+    // the sign of each selected eigenvector from its own largest-magnitude entry
+    hipLaunchKernelGGL(sign_fix_kernel, dim3(k), dim3(256), 0, ctx->stream, T_u, (int64_t)n, (int64_t)n, n, T_u,
+                       sigma, scale_v);
+    XPCS_LAUNCH_CHECK(ctx, "sign_fix");
+    if (spectrum) {
+        hipLaunchKernelGGL(spectrum_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, lam, n, spectrum);
+        XPCS_LAUNCH_CHECK(ctx, "spectrum");
+    }
     return XPCS_OK;
 }
 

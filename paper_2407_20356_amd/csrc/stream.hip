@@ -575,6 +575,91 @@ xpcs_status xpcs_stream_g2(xpcs_stream *s, double *g2, int64_t *npairs) {
 
 int64_t xpcs_stream_frames(const xpcs_stream *s) { return s ? s->n : 0; }
 
+namespace {
+const char kStreamMagic[8] = {'X', 'P', 'C', 'S', 'S', 'T', 'R', 1};
+enum { kSM, kSDtype, kSRoi, kSK, kSWindow, kSMaxBlock, kSN, kSBytes, kSFields };
+}  // namespace
+
+xpcs_status xpcs_stream_save(xpcs_stream *s, const char *path) {
+    if (!s) return XPCS_EINVAL;
+    xpcs_ctx *ctx = s->ctx;
+    if (!path) return fail(ctx, XPCS_EINVAL, "path is NULL");
+    (void)hipSetDevice(ctx->device);
+    PersistFile pf;
+    if (pf.open_write(path)) return fail(ctx, XPCS_EINVAL, std::string("cannot write ") + path);
+    const int64_t hdr[kSFields] = {s->M, s->dtype, s->n_roi, s->k, s->window, s->max_block, s->n,
+                                   (int64_t)s->bytes};
+    if (pf.write_header(kStreamMagic, hdr, kSFields)) return fail(ctx, XPCS_EDEVICE, "write failed");
+    return pf.write_device(ctx, s->mem, s->bytes);
+}
+
+xpcs_status xpcs_stream_load(xpcs_ctx *ctx, const char *path, xpcs_stream **out) {
+    if (!ctx) return XPCS_EINVAL;
+    if (!path || !out) return fail(ctx, XPCS_EINVAL, "path and out must not be NULL");
+    *out = nullptr;
+    (void)hipSetDevice(ctx->device);
+    PersistFile pf;
+    if (pf.open_read(path)) return fail(ctx, XPCS_EINVAL, std::string("cannot read ") + path);
+    int64_t hdr[kSFields];
+    if (pf.read_header(kStreamMagic, hdr, kSFields))
+        return fail(ctx, XPCS_EINVAL, "not a stream file, or a corrupt header");
+    xpcs_stream_desc d{};
+    d.M = hdr[kSM];
+    d.dtype = (int32_t)hdr[kSDtype];
+    d.n_roi = (int32_t)hdr[kSRoi];
+    d.k = (int32_t)hdr[kSK];
+    d.window = hdr[kSWindow];
+    d.max_block = hdr[kSMaxBlock];
+    if (d.M <= 0 || d.n_roi < 1 || d.n_roi > 64 || d.k < 1 || d.k > kMaxRank || d.window < 1 ||
+        d.window > 65536 || d.max_block < 1 || d.max_block > 4096 || (d.dtype != XPCS_U8 && d.dtype != XPCS_U16) ||
+        hdr[kSN] < 0)
+        return fail(ctx, XPCS_EINVAL, "corrupt stream header");
+    const StreamLayout lay = stream_layout(&d);
+    if ((int64_t)lay.total != hdr[kSBytes]) return fail(ctx, XPCS_EINVAL, "the stream file's layout differs");
+    auto *s = new xpcs_stream;
+    s->ctx = ctx;
+    s->M = d.M;
+    s->dtype = d.dtype;
+    s->n_roi = d.n_roi;
+    s->k = d.k;
+    s->kp = lay.kp;
+    s->L16 = lay.L16;
+    s->window = d.window;
+    s->max_block = d.max_block;
+    s->cap = lay.cap;
+    s->ldq = lay.ldq;
+    s->n = hdr[kSN];
+    s->bytes = lay.total;
+    if (ctx->budget && ctx->ws.capacity + ctx->scratch.capacity + ctx->persistent + s->bytes > ctx->budget) {
+        delete s;
+        return fail(ctx, XPCS_EBUDGET, "stream state of " + std::to_string(lay.total) + " bytes exceeds the HBM budget");
+    }
+    hipError_t e = hipMalloc(&s->mem, s->bytes);
+    if (e != hipSuccess) {
+        delete s;
+        return check_hip(ctx, e, "hipMalloc(stream)");
+    }
+    ctx->persistent += s->bytes;
+    char *base = static_cast<char *>(s->mem);
+    s->labels = reinterpret_cast<int32_t *>(base + lay.o_lab);
+    s->u_hi = reinterpret_cast<unsigned short *>(base + lay.o_uh);
+    s->u_lo = reinterpret_cast<unsigned short *>(base + lay.o_ul);
+    s->roi_npix = reinterpret_cast<int64_t *>(base + lay.o_np);
+    s->Lr = reinterpret_cast<double *>(base + lay.o_lr);
+    s->z_hi = reinterpret_cast<unsigned short *>(base + lay.o_zh);
+    s->z_lo = reinterpret_cast<unsigned short *>(base + lay.o_zl);
+    s->valid = reinterpret_cast<unsigned char *>(base + lay.o_va);
+    s->g2_sum = reinterpret_cast<double *>(base + lay.o_gs);
+    s->g2_cnt = reinterpret_cast<int64_t *>(base + lay.o_gc);
+    const xpcs_status st = pf.read_device(ctx, s->mem, s->bytes);
+    if (st) {
+        xpcs_stream_close(s);
+        return st;
+    }
+    *out = s;
+    return XPCS_OK;
+}
+
 void xpcs_stream_close(xpcs_stream *s) {
     if (!s) return;
     if (s->mem) {

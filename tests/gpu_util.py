@@ -43,6 +43,25 @@ def assert_two_time_close(C, Cref, rtol=1e-3, small=0.1, what="C"):
     return worst
 
 
+def assert_g2_close(g2, gref, ok=None, rtol=1e-3, small=0.1, what="g2"):
+    """The compressed path's tolerance applied to g2: lags with |g2*| >= small within
+    rtol relative, the remaining valid lags within rtol in relative Frobenius norm
+    (near-zero correlations, e.g. a basis unrelated to the data)."""
+    g2 = np.asarray(g2, dtype=np.float64)
+    gref = np.asarray(gref, dtype=np.float64)
+    ok = np.isfinite(gref) if ok is None else (np.asarray(ok) & np.isfinite(gref))
+    big = ok & (np.abs(gref) >= small)
+    if big.any():
+        rel = np.abs(g2[big] - gref[big]) / np.abs(gref[big])
+        assert rel.max() <= rtol, f"{what}: max rel err {rel.max():.3e} > {rtol:.1e}"
+    rest = ok & ~big
+    if rest.any():
+        den = np.linalg.norm(gref[rest])
+        if den > 0:
+            num = np.linalg.norm(g2[rest] - gref[rest])
+            assert num / den <= rtol, f"{what}: small-lag Frobenius rel err {num / den:.3e}"
+
+
 def check_homomorphic_identity(C, F, labels, n_roi, U):
     """C~ of a basis U (M x k, orthonormal columns) equals the two-time correlation
     of the decompressed data U U^T X (Eqs. 8-10), formed here with plain NumPy: the

@@ -22,7 +22,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import assert_two_time_close, say, to_np
+from tests.gpu_util import assert_g2_close, assert_two_time_close, say, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -111,8 +111,8 @@ def test_fullsize_online_basis_against_oracle(setup):
         np.testing.assert_array_equal(npg[r], nref)
         np.testing.assert_array_equal(npf[r], nref)
         ok = nref > 0
-        np.testing.assert_allclose(g2g[r][ok], gref[ok], rtol=1e-3, err_msg=f"g2 roi {r}")
-        np.testing.assert_allclose(g2f[r][ok], gref[ok], rtol=1e-3, err_msg=f"FFT g2 roi {r}")
+        assert_g2_close(g2g[r], gref, ok, what=f"g2 roi {r}")
+        assert_g2_close(g2f[r], gref, ok, what=f"FFT g2 roi {r}")
 
 
 @pytest.mark.parametrize("k", [64, 128])

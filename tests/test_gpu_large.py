@@ -25,7 +25,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import assert_two_time_close, say, to_np
+from tests.gpu_util import assert_g2_close, assert_two_time_close, say, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -89,7 +89,7 @@ def test_large_shape_stream_against_oracle_and_fft_g2():
     g2s, nps, g2f, npf = to_np(g2s), to_np(nps), to_np(g2f), to_np(npf)
     np.testing.assert_array_equal(nps, npf)
     ok = npf > 0
-    np.testing.assert_allclose(g2s[ok], g2f[ok], rtol=1e-3)
+    assert_g2_close(g2s, g2f, ok, what="stream g2 vs FFT g2")
     # sampled band entries against the oracle
     rng = np.random.default_rng(17)
     t_last = np.sort(rng.choice(np.arange(N_USED - BLOCK, N_USED), size=8, replace=False))

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import assert_two_time_close, say, to_dev, to_np
+from tests.gpu_util import assert_g2_close, assert_two_time_close, say, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -78,7 +78,7 @@ def test_stream_matches_oracle(ctx, dtype, big):
     gref, nref = O.stream_g2(ref)
     np.testing.assert_array_equal(npairs, nref)
     ok = nref > 0
-    np.testing.assert_allclose(g2[ok], gref[ok], rtol=1e-3)
+    assert_g2_close(g2, gref, ok, what="stream g2")
     assert np.all(np.isnan(g2[~ok]))
 
 

@@ -18,7 +18,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import assert_two_time_close, say, to_dev, to_np
+from tests.gpu_util import assert_g2_close, assert_two_time_close, say, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -45,7 +45,7 @@ def _assert_parity(C, g2, npairs, Crefs):
         gref, nref = O.g2_from_two_time(Cref)
         np.testing.assert_array_equal(npairs[r], nref)
         ok = nref > 0
-        np.testing.assert_allclose(g2[r][ok], gref[ok], rtol=1e-3)
+        assert_g2_close(g2[r], gref, ok, what=f"g2 roi {r}")
 
 
 def test_online_basis_rank_260(ctx):
@@ -199,4 +199,4 @@ def test_stream_rank_200_ring_wraps(ctx):
     gref, nref = O.stream_g2(ref)
     np.testing.assert_array_equal(npairs, nref)
     ok = nref > 0
-    np.testing.assert_allclose(g2[ok], gref[ok], rtol=1e-3)
+    assert_g2_close(g2, gref, ok, what="stream g2")

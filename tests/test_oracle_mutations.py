@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 from oracle import xpcs_oracle as OX
+from tests import test_oracle_analysis as apins
 from tests import test_oracle_pins as pins
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -171,3 +172,57 @@ def test_relaxation_fit_drops_the_factor_two(monkeypatch):
     monkeypatch.setattr(OX, "siegert_fit", wrong)
     monkeypatch.setattr(O, "siegert_fit", wrong)
     _expect_pin_failure(pins.test_siegert_relation_recovered)
+
+
+def test_rank_rule_strict_inequality(monkeypatch):
+    def wrong(spectrum, factor=2.0):
+        lam = np.asarray(spectrum, dtype=np.float64)
+        return int(np.count_nonzero((lam > 0.0) & (lam > factor * lam.min())))
+    monkeypatch.setattr(O, "rank_rule", wrong)
+    _expect_pin_failure(apins.test_rank_rule_hand_worked)
+
+
+def test_rank_rule_on_singular_values(monkeypatch):
+    def wrong(spectrum, factor=2.0):
+        s = np.sqrt(np.clip(np.asarray(spectrum, dtype=np.float64), 0.0, None))
+        return int(np.count_nonzero((s > 0.0) & (s >= factor * s.min())))
+    monkeypatch.setattr(O, "rank_rule", wrong)
+    _expect_pin_failure(apins.test_rank_rule_hand_worked)
+
+
+def test_peak_visibility_background_minimum(monkeypatch):
+    orig = OX.peak_visibility
+
+    def wrong(g2, npairs, peak, background):
+        g2 = np.asarray(g2, dtype=np.float64)
+        ok = np.isfinite(g2) if npairs is None else (np.asarray(npairs) > 0) & np.isfinite(g2)
+        bg = [g2[t] for t in range(*background) if ok[t]]
+        v = orig(g2, npairs, peak, background)
+        return v + (sum(bg) / len(bg) - min(bg)) if bg else v
+    monkeypatch.setattr(O, "peak_visibility", wrong)
+    _expect_pin_failure(apins.test_peak_visibility_hand_worked)
+
+
+def test_peak_visibility_counts_lags_without_pairs(monkeypatch):
+    orig = OX.peak_visibility
+    monkeypatch.setattr(O, "peak_visibility", lambda g2, npairs, peak, bg: orig(g2, None, peak, bg))
+    _expect_pin_failure(apins.test_peak_visibility_hand_worked)
+
+
+def test_kww_fit_without_the_exponent(monkeypatch):
+    def wrong(g2, taus, p0=None):
+        B, b, gam = OX.siegert_fit(g2, taus, None if p0 is None else p0[:3])
+        return B, b, gam, 1.0
+    monkeypatch.setattr(O, "kww_fit", wrong)
+    _expect_pin_failure(apins.test_kww_fit_recovers_exact_curves, 0.6)
+
+
+def test_texture_shift_axes_swapped(monkeypatch):
+    orig = OX.texture_shifts
+
+    def wrong(n, seed, H, W):
+        dy, dx = orig(n, seed, W, H)
+        return dx, dy
+    monkeypatch.setattr(OX, "texture_shifts", wrong)
+    _expect_pin_failure(apins.test_shifted_texture_frames_are_cyclic_shifts_found_by_search)
+

@@ -105,6 +105,21 @@ def test_empty_frames_are_nan_and_skipped():
     assert g2[2] == pytest.approx(C[0, 2], rel=1e-15)
 
 
+def test_raw_g2_at_lags_equals_the_diagonal_mean_of_the_full_matrix():
+    # the lag-sampled raw g2 (diagonal dot products, chunked) against the full
+    # Gram, its normalisation and the diagonal mean, with empty frames
+    F = synth.speckle_frames_numpy(600, 90, 0.05, 0.2, 8.0, "u8", seed=31)
+    F[5] = 0
+    F[40, :300] = 0
+    labels = synth.annular_labels(20, 30, 2, r_in=1.0)
+    lags = [0, 1, 2, 7, 33, 88, 89]
+    for roi in range(2):
+        g_full, n_full = O.g2_from_two_time(O.raw_two_time(F, labels, roi))
+        g, n = O.raw_g2_at_lags(F, labels, roi, lags, chunk=17)
+        np.testing.assert_array_equal(n, n_full[lags])
+        np.testing.assert_allclose(g, g_full[lags], rtol=1e-13)
+
+
 def test_g2_brute_force_loops():
     rng = np.random.default_rng(11)
     C = rng.random((9, 9))
