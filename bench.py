@@ -44,13 +44,47 @@ def percentile(xs, q):
     return xs[i]
 
 
+def roi_counts_and_sums(labels, n_roi, F=None):
+    """|R| per ROI and, for host frames F (n x M), the exact per-frame ROI photon sums
+    (plain NumPy bookkeeping for the spot checks and operation counts)."""
+    import numpy as np
+    lab = np.asarray(labels)
+    npix = np.bincount(lab[lab >= 0], minlength=n_roi)[:n_roi].astype(np.int64)
+    if F is None:
+        return npix, None
+    S = np.stack([np.asarray(F)[:, lab == r].astype(np.int64).sum(axis=1) for r in range(n_roi)])
+    return npix, S
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(frames_host, labels, n_roi, k, seed, n_sample):
     """Time the FP64 oracle on the first n_sample frames: basis + C~ + g2 for every ROI."""
     import numpy as np
     import oracle as O
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+        info = [p for p in threadpool_info() if p.get("user_api") == "blas"] or threadpool_info()
+        threads = max([int(p.get("num_threads", 1)) for p in info] or [1])
+        blas = ", ".join(sorted({f"{p.get('internal_api', '?')} {p.get('version', '')}".strip() for p in info}))
     except Exception:
         threads = os.cpu_count() or 1
     F = np.ascontiguousarray(frames_host[:n_sample])
@@ -64,6 +98,7 @@ def cpu_baseline(frames_host, labels, n_roi, k, seed, n_sample):
         O.g2_from_two_time(C)
     dt = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "blas": blas, "host_cpus": os.cpu_count(),
             "sample": f"first {n_sample} frames of the same series ({F.shape[1]} px, {n_roi} ROIs, k={k}): "
                       f"FP64 randomized basis + compressed C and g2 for every ROI, {dt:.1f} s",
             "seconds": dt}
@@ -111,7 +146,7 @@ def stream_latency(api, torch, dev, n_blocks):
             "frames_pushed": int(n_blocks * nb), "g2_finite": ok}
 
 
-def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, seed=4000):
+def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, budget_bytes=0, seed=4000):
     """Many online streams served at once (the serving workload): detectors drawn
     from {256x256, 512x512, 1024x512} px, 8..36 annular ROIs, uint8 counts
     (mean 0.05, beta 0.2, tau_c 50), k = 64 with each stream's basis compressed
@@ -150,10 +185,30 @@ def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, seed=4000):
             events.append((starts[i] + phase + b * period, i, b))
     events.sort()
 
-    def run(paced):
-        srv = api.Server(0, lanes=lanes, max_streams=n_streams)
+    def run(paced, budget=0):
+        """Push every block at its arrival time (paced) or back to back.  A stream
+        closes once its last block is reported, which frees its memory for waiting
+        requests; a request that does not fit the budget waits, and its blocks are
+        pushed once it is admitted (their latency then includes the wait)."""
+        from collections import deque
+        srv = api.Server(0, hbm_budget_bytes=budget, lanes=lanes, max_streams=n_streams)
         ids, lat, lag, opens, arrival_to_done = {}, [], {}, [], []
         seen = {i: 0 for i in range(n_streams)}
+        held = {i: deque() for i in range(n_streams)}       # blocks of a waiting stream
+        admitted, closing, closed = set(), set(), set()
+        max_admitted, queued_opens, admit_wait = 0, 0, []
+        t_open = {}
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        def push(i, ta, b):
+            st = streams[i]
+            lag[(i, b)] = max(0.0, (now() - ta) * 1e3) if paced else 0.0
+            srv.push(ids[i], st["pool"][(b % 4) * nb:(b % 4 + 1) * nb], band=st["band"])
+            if b == st["life"] - 1:
+                closing.add(i)
 
         def collect(i):
             for ms, _ in srv.poll(ids[i]):
@@ -161,48 +216,83 @@ def serving_run(api, torch, dev, n_streams, life_lo, life_hi, lanes, seed=4000):
                 arrival_to_done.append(lag[(i, seen[i])] + ms)
                 seen[i] += 1
 
-        t0 = time.perf_counter()
+        def service():
+            nonlocal max_admitted
+            for j in list(admitted):
+                collect(j)
+            for j in list(closing):
+                if seen[j] == streams[j]["life"]:
+                    srv.close(ids[j])
+                    closing.discard(j)
+                    admitted.discard(j)
+                    closed.add(j)
+            for j in list(ids):
+                if j not in admitted and j not in closed and srv.state(ids[j]) == 2:
+                    admitted.add(j)
+                    admit_wait.append((now() - t_open[j]) * 1e3)
+                    while held[j]:
+                        push(j, *held[j].popleft())
+            max_admitted = max(max_admitted, len(admitted))
+
         for (ta, i, b) in events:
-            st = streams[i]
             if paced:
-                while time.perf_counter() - t0 < ta:
+                while now() < ta:
                     pass
             if b == 0:
                 to = time.perf_counter()
-                ids[i], state = srv.open(st["labels"], st["n_roi"], st["basis"], window, nb)
+                ids[i], state = srv.open(streams[i]["labels"], streams[i]["n_roi"], streams[i]["basis"], window, nb)
                 opens.append((time.perf_counter() - to) * 1e3)
-            lag[(i, b)] = max(0.0, (time.perf_counter() - t0 - ta) * 1e3) if paced else 0.0
-            srv.push(ids[i], st["pool"][(b % 4) * nb:(b % 4 + 1) * nb], band=st["band"])
-            for j in ids:
-                collect(j)
-        srv.wait()
-        wall = time.perf_counter() - t0
-        for j in ids:
-            collect(j)
-        g2, _ = srv.g2(ids[0])
-        srv.wait()
-        ok = bool(torch.isfinite(g2[:, :nb]).all().item())
+                t_open[i] = now()
+                if state == 2:
+                    admitted.add(i)
+                    admit_wait.append(0.0)
+                else:
+                    queued_opens += 1
+            if i in admitted:
+                push(i, ta, b)
+            else:
+                held[i].append((ta, b))
+            service()
+        while len(closed) < n_streams:
+            before = (len(closed), len(admitted))
+            srv.wait()
+            service()
+            if (len(closed), len(admitted)) == before and not admitted:
+                raise RuntimeError("a serving request can never be admitted under the budget")
+        wall = now()
         srv.destroy()
-        return lat, arrival_to_done, opens, wall, ok
+        return dict(lat=lat, a2d=arrival_to_done, opens=opens, wall=wall, max_admitted=max_admitted,
+                    queued=queued_opens, admit_wait=admit_wait)
 
     run(False)                                   # loads every kernel; not timed
-    lat_b, _, _, wall_b, ok_b = run(False)
-    lat, a2d, opens, wall_p, ok_p = run(True)
+    sat = run(False)
+    pac = run(True)
     total_frames = sum(st["life"] for st in streams) * nb
-    return {"workload": f"serve_{n_streams}streams_u8_k64_w4096_b256",
-            "streams": [{"px": f"{st['shape'][0]}x{st['shape'][1]}", "n_roi": st["n_roi"], "blocks": st["life"]}
-                        for st in streams],
-            "lanes": lanes, "blocks": len(events), "frames": total_frames,
-            "block_latency_p50_ms": percentile(lat, 50), "block_latency_p99_ms": percentile(lat, 99),
-            "arrival_to_done_p50_ms": percentile(a2d, 50), "arrival_to_done_p99_ms": percentile(a2d, 99),
-            "open_ms_p50": percentile(opens, 50), "open_ms_max": max(opens),
-            "paced_wall_s": wall_p, "arrival_frames_per_s": total_frames / (events[-1][0] + period),
-            "saturated_frames_per_s": total_frames / wall_b, "saturated_wall_s": wall_b,
-            "saturated_block_latency_p50_ms": percentile(lat_b, 50),
-            "g2_finite": ok_p and ok_b}
+    out = {"workload": f"serve_{n_streams}streams_u8_k64_w4096_b256",
+           "streams": [{"px": f"{st['shape'][0]}x{st['shape'][1]}", "n_roi": st["n_roi"], "blocks": st["life"]}
+                       for st in streams],
+           "lanes": lanes, "blocks": len(events), "frames": total_frames,
+           "block_latency_p50_ms": percentile(pac["lat"], 50), "block_latency_p99_ms": percentile(pac["lat"], 99),
+           "arrival_to_done_p50_ms": percentile(pac["a2d"], 50), "arrival_to_done_p99_ms": percentile(pac["a2d"], 99),
+           "open_ms_p50": percentile(pac["opens"], 50), "open_ms_max": max(pac["opens"]),
+           "paced_wall_s": pac["wall"], "arrival_frames_per_s": total_frames / (events[-1][0] + period),
+           "saturated_frames_per_s": total_frames / sat["wall"], "saturated_wall_s": sat["wall"],
+           "saturated_block_latency_p50_ms": percentile(sat["lat"], 50),
+           "max_admitted_at_once": pac["max_admitted"]}
+    if budget_bytes:
+        b = run(True, budget_bytes)
+        out["budget"] = {"hbm_budget_bytes": budget_bytes, "requests_that_waited": b["queued"],
+                         "max_admitted_at_once": b["max_admitted"],
+                         "admission_wait_ms_p50": percentile(b["admit_wait"], 50),
+                         "admission_wait_ms_max": max(b["admit_wait"]),
+                         "block_latency_p50_ms": percentile(b["lat"], 50),
+                         "block_latency_p99_ms": percentile(b["lat"], 99),
+                         "arrival_to_done_p99_ms": percentile(b["a2d"], 99), "wall_s": b["wall"],
+                         "frames_per_s": total_frames / b["wall"]}
+    return out
 
 
-def precision_table(api, torch, dev, steps=3):
+def precision_table(api, torch, dev, steps=3, raw_steps=5):
     """BF16 vs FP8 subspace passes on the precision workload: 1024 x 1024 px x
     20,000 frames, uint8 counts <= 127 (mean 0.02, beta 0.15, tau_c 50), 36 ROIs,
     k = 128 (q = 1).  Per precision: compress time, the basis' orthonormality and
@@ -210,7 +300,6 @@ def precision_table(api, torch, dev, steps=3):
     both); between the two: singular values, the subspaces (cosine of the largest
     principal angle over the top 32 and over all k directions) and g2 (fused)."""
     import numpy as np
-    import oracle as O
     import synth
     spec = synth.WORKLOADS["det1024_20k_precision"]
     M, N, n_roi, k = spec.n_pixels, spec.n_frames, spec.n_roi, spec.ranks[0]
@@ -245,6 +334,23 @@ def precision_table(api, torch, dev, steps=3):
                      "w_rel_err": float(np.linalg.norm(Wg - Ws) / np.linalg.norm(Ws)),
                      "sigma_first": float(sig[prec][0]), "sigma_last": float(sig[prec][-1])}
         del f
+    # the raw path on the same frames: exact int8 Gram of every ROI, C in FP32 (57.6 GB) + fused g2
+    C = api.empty_two_time(dev, n_roi, N)
+    g2r = torch.empty((n_roi, N), dtype=torch.float64, device=dev)
+    npr = torch.empty((n_roi, N), dtype=torch.int64, device=dev)
+    ctx.enable_phase_timing(True)
+    per, wall = timed_steps(torch, ctx, lambda: api.correlate_two_time_raw(ctx, frames, labels_d, n_roi, C=C, g2=g2r,
+                                                                           npairs=npr), raw_steps, 1)
+    ph = ctx.phase_times()
+    ctx.enable_phase_timing(False)
+    tot_ms, cnt = ph.get("raw_gram_tiles", (float("nan"), 1))
+    ops = 2.0 * N * N * float(roi_counts_and_sums(labels, n_roi)[0].sum())
+    raw = {"ms_per_step": 1e3 * wall / raw_steps, "frames_per_s": N / (wall / raw_steps),
+           "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99), "steps": raw_steps, "warmup": 1,
+           "gram_ms": tot_ms / cnt, "gram_int8_TOPs": ops / (tot_ms / cnt / 1e3) / 1e12,
+           "gram_frac_of_int8_peak": ops / (tot_ms / cnt / 1e3) / 1e12 / PEAK_I8_TOPS,
+           "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph.items()}}
+    del C, g2r, npr
     cross = (U["bf16"].double().T @ U["fp8"].double())
     cos_all = float(torch.linalg.svdvals(cross).min().item())
     cos_top = float(torch.linalg.svdvals(cross[:32, :32]).min().item())
@@ -256,7 +362,82 @@ def precision_table(api, torch, dev, steps=3):
             "bf16": res["bf16"], "fp8": res["fp8"],
             "sigma_max_rel_diff": float(np.max(np.abs(sig["fp8"] - sig["bf16"]) / sig["bf16"])),
             "subspace_cos_min_top32": cos_top, "subspace_cos_min_all": cos_all,
-            "g2_max_rel_diff": float(np.max(np.abs(g2["fp8"][ok] - g2["bf16"][ok]) / np.abs(g2["bf16"][ok])))}
+            "g2_max_rel_diff": float(np.max(np.abs(g2["fp8"][ok] - g2["bf16"][ok]) / np.abs(g2["bf16"][ok]))),
+            "raw": raw, "speedup_bf16_vs_raw": raw["ms_per_step"] / res["bf16"]["compress_ms"]}
+
+
+def timed_steps(torch, ctx, fn, steps, warmup):
+    """Device time of each of `steps` calls of fn after `warmup` untimed ones (events
+    on the current stream), and the host wall time of the timed ones."""
+    for _ in range(warmup):
+        fn()
+    ctx.sync()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    w0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ctx.sync()
+    return [a.elapsed_time(b) for a, b in evs], wall
+
+
+def tiny_line(api, torch, dev, steps, warmup):
+    """The tiny workload (64 x 64 px x 1,000 frames, uint8, one ROI, k = 32): the
+    compressed step (basis + C in FP32 + fused g2) and the raw step (exact Gram, C in
+    FP64 + fused g2) in absolute microseconds (launch- and latency-bound sizes)."""
+    import synth
+    spec = synth.WORKLOADS["tiny_64x64x1000"]
+    M, N, k = spec.n_pixels, spec.n_frames, spec.ranks[0]
+    labels = torch.from_numpy(synth.workload_labels(spec)).to(dev)
+    frames = synth.speckle_frames_torch(M, N, spec.mu, spec.beta, spec.tau_c, spec.dtype, seed=1001, device=dev)
+    ctx = api.Context(0)
+    f = api.Factors.empty(M, N, k, 1, dev)
+    C = api.empty_two_time(dev, 1, N)
+    C64 = api.empty_two_time(dev, 1, N, torch.float64)
+    g2 = torch.empty((1, N), dtype=torch.float64, device=dev)
+    npairs = torch.empty((1, N), dtype=torch.int64, device=dev)
+
+    def comp():
+        api.compress_frames(ctx, frames, labels, 1, k=k, seed=7, out=f)
+        api.correlate_two_time(ctx, f, C=C, g2=g2, npairs=npairs)
+
+    def raw():
+        api.correlate_two_time_raw(ctx, frames, labels, 1, C=C64, g2=g2, npairs=npairs)
+
+    pc, wc = timed_steps(torch, ctx, comp, steps, warmup)
+    pr, wr = timed_steps(torch, ctx, raw, steps, warmup)
+    ctx.close()
+    return {"workload": "tiny_64x64x1000 (4096 px x 1000 frames, u8, 1 ROI, k=32)",
+            "compressed_us_p50": 1e3 * percentile(pc, 50), "compressed_us_p99": 1e3 * percentile(pc, 99),
+            "compressed_frames_per_s": N / (wc / steps),
+            "raw_us_p50": 1e3 * percentile(pr, 50), "raw_us_p99": 1e3 * percentile(pr, 99),
+            "raw_frames_per_s": N / (wr / steps), "steps": steps, "warmup": warmup}
+
+
+def k128_line(api, torch, ctx, frames, labels_d, n_roi, steps, warmup):
+    """The benchmark workload's compressed step at k = 128 (same frames, C and g2)."""
+    N, M = frames.shape
+    k = 128
+    f = api.Factors.empty(M, N, k, n_roi, frames.device)
+    C = api.empty_two_time(frames.device, n_roi, N)
+    g2 = torch.empty((n_roi, N), dtype=torch.float64, device=frames.device)
+    npairs = torch.empty((n_roi, N), dtype=torch.int64, device=frames.device)
+
+    def comp():
+        api.compress_frames(ctx, frames, labels_d, n_roi, k=k, seed=7, out=f)
+        api.correlate_two_time(ctx, f, C=C, g2=g2, npairs=npairs)
+
+    per, wall = timed_steps(torch, ctx, comp, steps, warmup)
+    del C
+    torch.cuda.empty_cache()
+    return {"workload": "det512_10k_36roi at k=128", "ms_per_step": 1e3 * wall / steps,
+            "frames_per_s": N / (wall / steps), "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99),
+            "steps": steps, "warmup": warmup}
 
 
 def g2_only(api, torch, ctx, f, reps=5):
@@ -324,7 +505,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="det512_10k_36roi")
     ap.add_argument("--k", type=int, default=64)
-    ap.add_argument("--raw-steps", type=int, default=3)
+    ap.add_argument("--raw-steps", type=int, default=20)
     ap.add_argument("--no-raw", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-frames", type=int, default=3000)
@@ -333,10 +514,14 @@ def main():
     ap.add_argument("--stream-blocks", type=int, default=40)
     ap.add_argument("--no-serve", action="store_true", help="skip the many-stream serving measurement")
     ap.add_argument("--serve-streams", type=int, default=16)
-    ap.add_argument("--serve-life", type=int, nargs=2, default=[16, 48], metavar=("LO", "HI"),
+    ap.add_argument("--serve-life", type=int, nargs=2, default=[64, 512], metavar=("LO", "HI"),
                     help="stream lifetimes in blocks")
+    ap.add_argument("--serve-budget-mib", type=int, default=1024,
+                    help="HBM budget of the extra serving run that exercises admission (0: skip it)")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--no-g2only", action="store_true", help="skip the g2-without-C comparison")
+    ap.add_argument("--no-k128", action="store_true", help="skip the k = 128 line of the benchmark workload")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny workload's microsecond line")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16 vs FP8 table on the 1024 x 1024 x 20,000 uint8 workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -420,7 +605,6 @@ def main():
         f"{kk} {v[0] / v[1]:.3f}x{v[1] // args.steps}" for kk, v in sorted(ph_c.items(), key=lambda kv: -kv[1][0])))
 
     # light parity spot checks on this run (sampled frames; the full checks are in tests/)
-    import oracle as O
     rng = np.random.default_rng(0)
     ts = np.sort(rng.choice(N, size=16, replace=False))
     idx = torch.from_numpy(ts).to(dev)
@@ -431,12 +615,12 @@ def main():
     U = f.U.cpu().numpy().T.astype(np.float64)
     Ws = Fs.astype(np.float64) @ U
     Wg = (f.V.cpu().numpy().T.astype(np.float64) * f.sigma.cpu().numpy())[ts]
-    S_ok = bool(np.array_equal(f.roi_sum.cpu().numpy()[:, ts], O.roi_frame_sums(Fs, labels, n_roi)))
+    npix, S_host = roi_counts_and_sums(labels, n_roi, Fs)
+    S_ok = bool(np.array_equal(f.roi_sum.cpu().numpy()[:, ts], S_host))
     w_err = float(np.linalg.norm(Wg - Ws) / np.linalg.norm(Ws))
     orth = float(np.abs(U.T @ U - np.eye(k)).max())
     Cs = C[:, torch.from_numpy(ts).to(dev)][:, :, torch.from_numpy(ts).to(dev)].cpu().numpy()
-    npix = O.roi_pixel_counts(labels, n_roi)
-    Sg = O.roi_frame_sums(Fs, labels, n_roi).astype(np.float64)
+    Sg = S_host.astype(np.float64)
     c_err = 0.0
     for r in range(n_roi):
         Ur = U[labels == r]
@@ -450,7 +634,7 @@ def main():
     raw = None
     if not args.no_raw:
         log("raw path: warmup + timed steps")
-        per_r, wall_r, ph_r = timed(step_raw, args.raw_steps, 1, "raw")
+        per_r, wall_r, ph_r = timed(step_raw, args.raw_steps, args.warmup, "raw")
         ms_r = 1e3 * wall_r / args.raw_steps
         log("raw phases (ms per launch x launches per step): " + ", ".join(
             f"{kk} {v[0] / v[1]:.3f}x{v[1] // args.raw_steps}" for kk, v in sorted(ph_r.items(), key=lambda kv: -kv[1][0])))
@@ -483,12 +667,23 @@ def main():
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(dk["achieved_GBs"] / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": dk["bytes_per_launch"]}
+    # the whole step against its bound: four passes over the frames (the sketch, the power
+    # pass's two products and the encoding pass) plus writing C once, at peak HBM bandwidth
+    step_bytes = 4 * x_bytes + n_roi * N * N * 4
+    ideal_ms = step_bytes / (PEAK_HBM_GBS * 1e9) * 1e3
+    step_roofline = {"bound": "hbm", "algorithmic_bytes": step_bytes, "ideal_ms": ideal_ms, "ms_per_step": ms_c,
+                     "frac": ideal_ms / ms_c}
     if raw is not None and "raw_gram_tiles" in ph_r:
         tot_ms, cnt = ph_r["raw_gram_tiles"]
-        npix_all = O.roi_pixel_counts(labels, n_roi)
-        ops = 2.0 * N * N * float(npix_all.sum())
+        ops = 2.0 * N * N * float(npix.sum())
         raw["gram_int8_TOPs"] = ops / (tot_ms / cnt / 1e3) / 1e12
         raw["gram_frac_of_int8_peak"] = raw["gram_int8_TOPs"] / PEAK_I8_TOPS
+
+    k128 = None
+    if not args.no_k128 and args.workload == "det512_10k_36roi" and k != 128:
+        log("compressed step at k = 128 on the same frames")
+        k128 = k128_line(api, torch, ctx, frames, labels_d, n_roi, args.steps, args.warmup)
+        log(f"k = 128: {k128['ms_per_step']:.3f} ms per step, {k128['frames_per_s']:.0f} frames/s")
 
     g2o = None
     if not args.no_g2only:
@@ -506,7 +701,7 @@ def main():
     if not args.no_serve:
         log(f"serving: {args.serve_streams} streams, lifetimes {args.serve_life} blocks, {args.serve_lanes} lanes")
         served = serving_run(api, torch, dev, args.serve_streams, args.serve_life[0], args.serve_life[1],
-                             args.serve_lanes)
+                             args.serve_lanes, budget_bytes=args.serve_budget_mib << 20)
         log(f"serving: block latency p50 {served['block_latency_p50_ms']:.3f} ms, "
             f"p99 {served['block_latency_p99_ms']:.3f} ms; arrival to done p99 "
             f"{served['arrival_to_done_p99_ms']:.3f} ms; open max {served['open_ms_max']:.1f} ms; "
@@ -519,6 +714,12 @@ def main():
         log(f"precision table: compress bf16 {prec_table['bf16']['compress_ms']:.2f} ms, "
             f"fp8 {prec_table['fp8']['compress_ms']:.2f} ms; sigma diff {prec_table['sigma_max_rel_diff']:.2e}; "
             f"g2 diff {prec_table['g2_max_rel_diff']:.2e}")
+
+    tiny = None
+    if not args.no_tiny:
+        log("tiny workload: compressed and raw steps in microseconds")
+        tiny = tiny_line(api, torch, dev, args.steps, args.warmup)
+        log(f"tiny: compressed {tiny['compressed_us_p50']:.1f} us, raw {tiny['raw_us_p50']:.1f} us (p50)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -552,6 +753,9 @@ def main():
         "stream": serving,
         "serving": served,
         "precision": prec_table,
+        "k128": k128,
+        "tiny": tiny,
+        "step_roofline": step_roofline,
         "g2_without_c": g2o,
         "kernels": kernels,
         "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_c.items()},
