@@ -649,6 +649,7 @@ def main():
     nb = (N + 127) // 128
     algo = {
         # bytes each launch must move: the frames it reads / the matrix it writes
+        "sketch": (x_bytes, "hbm"),
         "proj_frames": (x_bytes, "hbm"),
         "proj_pixels": (x_bytes, "hbm"),
         "lowrank_tiles": (n_roi * N * N * 4 + 2 * n_roi * N * kp * 2, "hbm"),

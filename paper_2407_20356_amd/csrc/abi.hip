@@ -266,6 +266,7 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     add(jacobi_rot_bytes(ell > 2 ? ell : 2));
     add((size_t)(n_roi + 1) * 8); add((size_t)(M + n_roi) * 4); add((size_t)(M + n_roi) * 4);
     add((size_t)std::max(ell, k) * 8); add((size_t)std::max(ell, k) * 8);
+    add(sketch_need_bytes(M));
     if ((st = ws_reserve(ctx, need))) return st;
     unsigned short *om = static_cast<unsigned short *>(ws_take(ctx, b_om));
     float *Ya = static_cast<float *>(ws_take(ctx, b_y));
@@ -287,6 +288,7 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
     int32_t *qroi = static_cast<int32_t *>(ws_take(ctx, (size_t)(M + n_roi) * 4));
     double *lam = static_cast<double *>(ws_take(ctx, (size_t)std::max(ell, k) * 8));
     double *scale = static_cast<double *>(ws_take(ctx, (size_t)std::max(ell, k) * 8));
+    int *sk_need = static_cast<int *>(ws_take(ctx, sketch_need_bytes(M)));
 
     if ((st = launch_roi_count(ctx, roi_label, M, n_roi, out->roi_npix))) return st;
 
@@ -305,16 +307,12 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
         ov.ld32 = N;
         if ((st = launch_tsmul(ctx, Za, true, N, N, k, Tid, k, scale, ov))) return st;
     } else {
-        // 1. sketch Y0 = X Omega (exact: +-1 entries, integer counts)
+        // 1. sketch Y0 = X Omega, exact on the int8 MFMA (+-1 signs, integer counts)
         uint8_t *om8 = reinterpret_cast<uint8_t *>(om), *q8 = reinterpret_cast<uint8_t *>(qlo);
         const uint8_t *f8frames = static_cast<const uint8_t *>(frames);
-        if (fp8) {
-            if ((st = launch_sketch_omega_f8(ctx, opts->seed, N, L, ell, ldt, om8))) return st;
-            if ((st = launch_proj_pixels_f8(ctx, f8frames, M, N, om8, ldt, L, Ya))) return st;
-        } else {
-            if ((st = launch_sketch_omega(ctx, opts->seed, N, L, ell, ldt, om))) return st;
-            if ((st = launch_proj_pixels(ctx, frames, dtype, M, N, om, ldt, L, Ya))) return st;
-        }
+        if ((st = launch_sketch_i8(ctx, frames, dtype, M, N, opts->seed, ell, L, ldt, reinterpret_cast<int8_t *>(om),
+                                   Ya, sk_need)))
+            return st;
         if (opts->power_iters == 1 && fp8) {
             // 2. the same with e4m3 operands: Q0 = orth(Y0), Z = X^T Q0, Qz = orth(Z), Y1 = X Qz
             TsOut o;

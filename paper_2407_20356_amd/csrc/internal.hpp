@@ -197,9 +197,13 @@ xpcs_status launch_g2_reduce(xpcs_ctx *ctx, const double *g2_part, const int *g2
                              int nr, double *g2, int64_t *npairs);
 
 // ---------------------------------------------------------------- projections (proj_pixels.hip, proj_frames*.hip)
-// Rademacher sketch as bf16 rows om[j][t] (row stride ldt >= N padded to 32, zero padded).
-xpcs_status launch_sketch_omega(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell,
-                                int64_t ldt, unsigned short *om);
+// Rademacher sketch (sketch.hip): om[j][t] = +-1 (int8) for j < ell, t < N, zero
+// padded (row stride ldt, a multiple of 64 >= N; L rows, L a multiple of 16), then
+// Y[j][p] = sum_t X[t][p] om[j][t] on the int8 MFMA (exact per 7-bit plane of the
+// counts); Y fp32 with row stride M.  `need` is scratch of sketch_need_bytes(M).
+size_t sketch_need_bytes(int64_t M);
+xpcs_status launch_sketch_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N, uint64_t seed,
+                             int ell, int L, int64_t ldt, int8_t *om, float *Y, int *need);
 // Pixel-space product Y[j][p] = sum_t X[p][t] B[j][t] (B bf16 rows of stride ldb, L
 // columns, L multiple of 16); Y fp32 column-major with stride M.
 xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
@@ -215,12 +219,10 @@ struct FrameProj {
 };
 // Plan for a pass with (lo = true) or without the residual term of Q.
 FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo);
-// FP8 (e4m3) versions of the subspace passes for u8 counts (proj_f8.hip): the
-// same +-1 sketch in e4m3, the pixel-space product with an e4m3 B (rows of stride
-// ldb) and the frame-space power pass with an e4m3 Q (no residual term, no
-// indicator columns; `plan` from plan_proj_frames(M, N, L, 0, false)).
-xpcs_status launch_sketch_omega_f8(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell, int64_t ldt,
-                                   uint8_t *om);
+// FP8 (e4m3) versions of the power pass for u8 counts (proj_f8.hip): the
+// pixel-space product with an e4m3 B (rows of stride ldb) and the frame-space
+// product with an e4m3 Q (no residual term, no indicator columns; `plan` from
+// plan_proj_frames(M, N, L, 0, false)).
 xpcs_status launch_proj_pixels_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t M, int64_t N, const uint8_t *B,
                                   int64_t ldb, int L, float *Y);
 xpcs_status launch_proj_frames_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t M, int64_t N, const uint8_t *q8,

@@ -15,7 +15,7 @@
 namespace xpcs {
 namespace proj {
 
-constexpr unsigned short kBfOne = 0x3F80, kBfMinusOne = 0xBF80;
+constexpr unsigned short kBfOne = 0x3F80;
 constexpr int kQp = 40;   // LDS row pitch (u16) of a staged 32-wide K step: 32 + 8 padding
 
 __device__ __forceinline__ unsigned pack_bf16_pair(float a, float b) {

@@ -1,5 +1,5 @@
-// FP8 (OCP e4m3) versions of the three subspace passes over the counts (the
-// range finder's X Omega, and the power pass X^T Q, X Z of Sec. 2.1): these only
+// FP8 (OCP e4m3) versions of the power pass over the counts (X^T Q and X Z of
+// Sec. 2.1; the sketch X Omega is exact on the int8 MFMA in every mode): these only
 // choose the span of the basis, so their B operands may be rounded to e4m3; the
 // encoding pass W = X^T U keeps the split-bf16 basis.  The counts stay exact:
 // a count c < 256 (u8 frames) enters as two nibble planes, c & 15 and
@@ -8,7 +8,7 @@
 // The MFMA is v_mfma_f32_16x16x32_fp8_fp8: the same lane layout as the bf16
 // 16x16x32 (lane l: row l % 16, K group l / 16 of 8 values), 8 bytes per operand.
 //
-// B operands are fp8 rows: the sketch's +-1 (exact), or an orthonormal basis
+// B operands are fp8 rows of an orthonormal basis
 // scaled by 256 (entries of a unit column are at most 1, so the scale keeps them
 // in e4m3's normal range and below its largest finite value 448).  The scale is
 // left in the products: the passes feed orthonormalisations, which remove it.
@@ -49,27 +49,6 @@ __device__ __forceinline__ long f8_plane1(unsigned lo, unsigned hi) {
 }
 __device__ __forceinline__ f32x4 mfma_f8(long a, long b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
-}
-
-// +-1 sketch entries in e4m3 (0x38 = 1, 0xB8 = -1), the same draws as the bf16 sketch.
-__device__ __forceinline__ uint64_t splitmix64_f8(uint64_t x) {
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__global__ void sketch_omega_f8_kernel(uint64_t seed, int64_t N, int L, int ell, int64_t ldt, uint8_t *om) {
-    const int64_t total = (int64_t)L * ldt;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = idx / ldt, t = idx % ldt;
-        uint8_t v = 0;
-        if (j < ell && t < N) {
-            const uint64_t h = splitmix64_f8(seed ^ (((uint64_t)t << 32) | (uint64_t)j));
-            v = (h >> 63) ? 0xB8 : 0x38;
-        }
-        om[idx] = v;
-    }
 }
 
 // One K step (rows j < 16 * NCB of an fp8 row-major operand, KB bytes of K) held in
@@ -349,17 +328,6 @@ void launch_pf_f8(int nblocks, hipStream_t st, const uint8_t *X, int64_t M, int6
 }
 
 }  // namespace
-
-xpcs_status launch_sketch_omega_f8(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell, int64_t ldt,
-                                   uint8_t *om) {
-    Phase phase_(ctx, "sketch_omega");
-    const int64_t total = (int64_t)L * ldt;
-    int grid = (int)((total + 255) / 256);
-    if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(sketch_omega_f8_kernel, dim3(grid), dim3(256), 0, ctx->stream, seed, N, L, ell, ldt, om);
-    XPCS_LAUNCH_CHECK(ctx, "sketch_omega_f8");
-    return XPCS_OK;
-}
 
 xpcs_status launch_proj_pixels_f8(xpcs_ctx *ctx, const uint8_t *frames, int64_t M, int64_t N, const uint8_t *B,
                                   int64_t ldb, int L, float *Y) {

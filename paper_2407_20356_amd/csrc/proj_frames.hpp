@@ -66,12 +66,18 @@ constexpr int pf_kstep(int rb, int ncb, int nib, bool lo) {
     return (rb * (ncb + nib) <= 20 && ncb * (lo ? 2 : 1) <= 12) ? 64 : 32;
 }
 
+// K steps of counts in flight beyond the one being multiplied.
+template <typename T>
+constexpr int pf_depth(int rb, int ncb, int nib, bool lo) {
+    return 1;
+}
+
 // VEC: M is a multiple of 8 and X and the labels are aligned, so each 8-pixel group
 // of a lane is all inside or all outside the chunk; every lane then issues the same
 // vector loads (groups past the chunk end read the chunk's first pixels and meet
 // zero rows of Q and label -1; frames past N read frame N-1 and their outputs are
 // dropped), which keeps the count of loads in flight fixed.
-template <typename T, int RB, int NCB, int NIB, bool LO, bool VEC, int KS>
+template <typename T, int RB, int NCB, int NIB, bool LO, bool VEC, int KS, int D>
 __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ qh,
                                                           const unsigned short *__restrict__ ql,
@@ -222,25 +228,26 @@ __global__ __launch_bounds__(256) void proj_frames_kernel(const T *__restrict__ 
         }
     };
 
-    // One K step in flight beyond the one being multiplied (counts and the staged
-    // operands in registers, the operands written to LDS one step before use).
-    // Loads are issued every step (the last one repeated at the end) so that their
-    // number never varies.
+    // The counts of D K steps beyond the one being multiplied are in flight in
+    // registers; the staged operands are loaded one step ahead and written to the
+    // other LDS buffer after the current step's MFMAs.  Loads are issued every step
+    // (the last step's repeated at the end) so that their number never varies.
     if (nsteps > 0) {
         StageRegs sr;
-        PK xr[2][RB][kKK];
+        PK xr[D + 1][RB][kKK];
+#pragma unroll
+        for (int i = 0; i < D; ++i) load_x(p_begin + KS * (int64_t)(i < nsteps ? i : nsteps - 1), xr[i]);
         stage_load(p_begin, sr);
-        load_x(p_begin, xr[0]);
         stage_store(sr, 0);
         __syncthreads();
-        for (int step0 = 0; step0 < nsteps; step0 += 2) {
+        for (int step0 = 0; step0 < nsteps; step0 += D + 1) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j <= D; ++j) {
                 const int step = step0 + j;
                 if (step >= nsteps) break;
-                const int64_t pn = p_begin + KS * (int64_t)(step + 1 < nsteps ? step + 1 : step);
-                stage_load(pn, sr);
-                load_x(pn, xr[j ^ 1]);
+                const int ahead = step + D < nsteps ? step + D : nsteps - 1;
+                load_x(p_begin + KS * (int64_t)ahead, xr[(j + D) % (D + 1)]);
+                stage_load(p_begin + KS * (int64_t)(step + 1 < nsteps ? step + 1 : step), sr);
                 multiply(xr[j], step & 1);
                 if (step + 1 < nsteps) stage_store(sr, (step + 1) & 1);
                 __syncthreads();
@@ -266,11 +273,12 @@ void launch_pf(int nblocks, hipStream_t st, const void *X, int64_t M, int64_t N,
                const unsigned short *ql, int64_t ldq, const int32_t *labels, int64_t chunk, int nfb,
                int ncols, float *part, bool vec) {
     constexpr int KS = pf_kstep(RB, NCB, NIB, LO);
+    constexpr int D = pf_depth<T>(RB, NCB, NIB, LO);
     if (vec)
-        hipLaunchKernelGGL((proj_frames_kernel<T, RB, NCB, NIB, LO, true, KS>), dim3(nblocks), dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_frames_kernel<T, RB, NCB, NIB, LO, true, KS, D>), dim3(nblocks), dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, qh, ql, ldq, labels, chunk, nfb, ncols, part);
     else
-        hipLaunchKernelGGL((proj_frames_kernel<T, RB, NCB, NIB, LO, false, KS>), dim3(nblocks), dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_frames_kernel<T, RB, NCB, NIB, LO, false, KS, D>), dim3(nblocks), dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, qh, ql, ldq, labels, chunk, nfb, ncols, part);
 }
 

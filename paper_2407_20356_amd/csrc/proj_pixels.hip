@@ -1,5 +1,5 @@
-// Rademacher sketch and the pixel-space product Y = X B (Sec. 2.1: the range
-// finder's X Omega and the power pass X Z).  X is stored frame-contiguous,
+// The pixel-space product Y = X B of the power pass (Sec. 2.1: X Z, Z the
+// orthonormalised frame-space product).  X is stored frame-contiguous,
 // X[t][p] = frames[t*M + p]; the product contracts over frames and is bound by
 // HBM bandwidth (2*l flops per 1- or 2-byte count, well under the BF16 ridge).
 //
@@ -13,29 +13,6 @@ namespace xpcs {
 namespace {
 
 using namespace proj;
-
-// ---------------------------------------------------------------- sketch
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__global__ void sketch_omega_kernel(uint64_t seed, int64_t N, int L, int ell, int64_t ldt,
-                                    unsigned short *om) {
-    const int64_t total = (int64_t)L * ldt;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = idx / ldt, t = idx % ldt;
-        unsigned short v = 0;
-        if (j < ell && t < N) {
-            const uint64_t h = splitmix64(seed ^ (((uint64_t)t << 32) | (uint64_t)j));
-            v = (h >> 63) ? kBfMinusOne : kBfOne;
-        }
-        om[idx] = v;
-    }
-}
 
 // ---------------------------------------------------------------- pixel-space product
 template <typename T, int RB>
@@ -91,7 +68,7 @@ __device__ __forceinline__ typename PixPack<T, RB>::type load_pix_partial(const 
 // or all outside the detector; every lane then issues the same vector loads (lanes
 // past M read pixel 0 and their outputs are dropped; frames past N read frame N-1
 // and meet the zero rows of B), which keeps the count of loads in flight fixed.
-template <typename T, int RB, int NCB, bool VEC, int KG>
+template <typename T, int RB, int NCB, bool VEC, int KG, int D>
 __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ Y) {
@@ -167,35 +144,39 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
         }
     };
 
-    // One K step (KG groups of 32 frames) in flight beyond the one being multiplied
-    // (counts and B's K step in registers, B written to LDS one step before use).
-    // Loads are issued every step (the last one repeated at the end) so that their
-    // number never varies; frames past N meet B's zero columns.
-    Stage16<NCB> st[2][KG];
-    PV xr[2][KG][8];
-    auto load_step = [&](int step, int slot) {
+    // The counts of D K steps (KG groups of 32 frames each) beyond the one being
+    // multiplied are in flight in registers; B's next K step is loaded into
+    // registers and written to the other LDS buffer after the current step's
+    // MFMAs.  Loads are issued every step (the last step's repeated at the end) so
+    // that their number never varies; frames past N meet B's zero columns.
+    Stage16<NCB> st[KG];
+    PV xr[D + 1][KG][8];
+    auto load_x_step = [&](int step, PV (&x)[KG][8]) {
 #pragma unroll
-        for (int g = 0; g < KG; ++g) {
-            const int64_t tk = ((int64_t)step * KG + g) * 32;
-            st[slot][g].load(Bg, ldb, tk);           // tk < ldb: ldb is a multiple of 32 KG
-            load_group(tk, xr[slot][g]);
-        }
+        for (int g = 0; g < KG; ++g) load_group(((int64_t)step * KG + g) * 32, x[g]);
     };
-    load_step(0, 0);
+    auto load_b_step = [&](int step) {
 #pragma unroll
-    for (int g = 0; g < KG; ++g) st[0][g].store(sb[0][g]);
+        for (int g = 0; g < KG; ++g) st[g].load(Bg, ldb, ((int64_t)step * KG + g) * 32);   // < ldb: a multiple of 32 KG
+    };
+#pragma unroll
+    for (int i = 0; i < D; ++i) load_x_step(i < nsteps ? i : nsteps - 1, xr[i]);
+    load_b_step(0);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) st[g].store(sb[0][g]);
     __syncthreads();
-    for (int step0 = 0; step0 < nsteps; step0 += 2) {
+    for (int step0 = 0; step0 < nsteps; step0 += D + 1) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j <= D; ++j) {
             const int step = step0 + j;
             if (step >= nsteps) break;
-            load_step(step + 1 < nsteps ? step + 1 : step, j ^ 1);
+            load_x_step(step + D < nsteps ? step + D : nsteps - 1, xr[(j + D) % (D + 1)]);
+            load_b_step(step + 1 < nsteps ? step + 1 : step);
 #pragma unroll
             for (int g = 0; g < KG; ++g) multiply(xr[j][g], sb[step & 1][g]);
             if (step + 1 < nsteps) {
 #pragma unroll
-                for (int g = 0; g < KG; ++g) st[j ^ 1][g].store(sb[(step + 1) & 1][g]);
+                for (int g = 0; g < KG; ++g) st[g].store(sb[(step + 1) & 1][g]);
             }
             __syncthreads();
         }
@@ -215,17 +196,23 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
     }
 }
 
-// One-byte counts take two groups of 32 frames per K step, so that a step moves as
-// many bytes as a two-byte step does.
+// Groups of 32 frames per K step: one-byte counts take two, so that a step moves
+// as many bytes as a two-byte step does.
+template <typename T>
+constexpr int pp_groups(int rb, int ncb) { return sizeof(T) == 1 ? 2 : 1; }
+// K steps of counts in flight beyond the one being multiplied.
+template <typename T>
+constexpr int pp_depth(int rb, int ncb) { return 1; }
+
 template <typename T, int RB, int NCB>
 void launch_pp(dim3 grid, hipStream_t st, const void *X, int64_t M, int64_t N, const unsigned short *B,
                int64_t ldb, float *Y, bool vec) {
-    constexpr int KG = sizeof(T) == 1 ? 2 : 1;
+    constexpr int KG = pp_groups<T>(RB, NCB), D = pp_depth<T>(RB, NCB);
     if (vec)
-        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, true, KG>), grid, dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, true, KG, D>), grid, dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, B, ldb, Y);
     else
-        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, false, KG>), grid, dim3(256), 0, st,
+        hipLaunchKernelGGL((proj_pixels_kernel<T, RB, NCB, false, KG, D>), grid, dim3(256), 0, st,
                            static_cast<const T *>(X), M, N, B, ldb, Y);
 }
 
@@ -255,17 +242,6 @@ bool dispatch_pp(int ncb, unsigned gy, hipStream_t st, const void *X, int64_t M,
 }
 
 }  // namespace
-
-xpcs_status launch_sketch_omega(xpcs_ctx *ctx, uint64_t seed, int64_t N, int L, int ell, int64_t ldt,
-                                unsigned short *om) {
-    Phase phase_(ctx, "sketch_omega");
-    int64_t total = (int64_t)L * ldt;
-    int grid = (int)((total + 255) / 256);
-    if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(sketch_omega_kernel, dim3(grid), dim3(256), 0, ctx->stream, seed, N, L, ell, ldt, om);
-    XPCS_LAUNCH_CHECK(ctx, "sketch_omega");
-    return XPCS_OK;
-}
 
 xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,
                                const unsigned short *B, int64_t ldb, int L, float *Y) {

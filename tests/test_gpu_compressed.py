@@ -246,6 +246,34 @@ def test_offline_pipeline_parity_wide_sketch(ctx, k, oversample):
     _assert_parity(C, g2, npairs, _oracle_compressed(F, Uo, labels, 3))
 
 
+@pytest.mark.parametrize("dtype,side", [("u8", 45), ("u16", 50)])
+def test_offline_q0_parity_every_count_plane(ctx, dtype, side):
+    """The int8 sketch takes counts as 7-bit planes, the higher planes only in the
+    256-pixel blocks that need them: bright pixels in the first and the last
+    (ragged) block reach every plane (u8 up to 255; u16 up to 65535), the other
+    blocks stay dim.  With q = 0 the pipeline must still match the oracle's FP64
+    randomized basis elementwise (45 x 45 px: M not a multiple of 4, element
+    loads; 50 x 50: vector loads)."""
+    from paper_2407_20356_amd import api
+    labels = synth.annular_labels(side, side, 2, r_in=2.0)
+    M, N = side * side, 300
+    F = synth.speckle_frames_numpy(M, N, 0.3, 0.2, 20.0, dtype, seed=33)
+    rng = np.random.default_rng(34)
+    top = 255 if dtype == "u8" else 65535
+    for px in (3, 200, 257, M - 1):
+        F[:, px] = rng.integers(0, top + 1, size=N)
+    F[7, 5] = top
+    k, seed = 20, 99
+    say(f"offline q=0 parity, {dtype} counts up to {top}, {M} px")
+    f = api.compress_frames(ctx, to_dev(F), to_dev(labels), 2, k=k, seed=seed, power_iters=0)
+    ctx.sync()
+    fn = _factors_np(f)
+    Uo, so, Vo = O.randomized_basis(F, k, 16, 0, seed=seed)
+    np.testing.assert_allclose(fn["sigma"], so, rtol=1e-5)
+    C, g2, npairs = _gpu_correlate(ctx, f)
+    _assert_parity(C, g2, npairs, _oracle_compressed(F, Uo, labels, 2))
+
+
 def test_offline_basis_multi_roi_u16(ctx):
     from paper_2407_20356_amd import api
     H = W = 96
