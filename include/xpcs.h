@@ -423,7 +423,7 @@ xpcs_status xpcs_stream_push(xpcs_stream *s, const void *frames, int64_t nframes
  * 0) and npairs[r*window + tau] (device int64); either may be NULL. */
 xpcs_status xpcs_stream_g2(xpcs_stream *s, double *g2, int64_t *npairs);
 
-/* Frames pushed so far (host value). */
+/* Frames pushed so far (host value; 0 for a NULL stream). */
 int64_t xpcs_stream_frames(const xpcs_stream *s);
 
 /* Writes the stream's whole state (labels, basis, ROI factors, the window of
