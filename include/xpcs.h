@@ -46,7 +46,7 @@ typedef int32_t xpcs_status;
 #define XPCS_OK 0
 #define XPCS_EINVAL (-1)        /* bad argument (null pointer, size, label, dtype)      */
 #define XPCS_ENOMEM (-2)        /* device allocation failed                             */
-#define XPCS_ERANGE (-3)        /* a count exceeds what the exact integer path holds    */
+#define XPCS_ERANGE (-3)        /* reserved: a value outside what an exact path holds   */
 #define XPCS_EBUDGET (-4)       /* the workspace would exceed the context's HBM budget  */
 #define XPCS_EDEVICE (-5)       /* HIP runtime error or a failed device-side step      */
 #define XPCS_EUNSUPPORTED (-6)  /* valid request outside what this build implements    */
@@ -81,7 +81,7 @@ void xpcs_destroy(xpcs_ctx *ctx);
 xpcs_status xpcs_set_stream(xpcs_ctx *ctx, void *hip_stream);
 
 /* Wait for the context's stream, then report and clear device-side flags.
- * Returns XPCS_OK, XPCS_ERANGE, XPCS_EINVAL or XPCS_EDEVICE. */
+ * Returns XPCS_OK, XPCS_EINVAL (a label outside [-1, n_roi)) or XPCS_EDEVICE. */
 xpcs_status xpcs_sync(xpcs_ctx *ctx);
 
 /* Message for the last error on this context ("" if none).  Owned by the context. */
@@ -100,6 +100,10 @@ size_t xpcs_workspace_bytes(const xpcs_ctx *ctx);
  * memory of at least cap entries.  Recording costs a few microseconds of host
  * time per phase; it does not stall the device. */
 xpcs_status xpcs_enable_phase_timing(xpcs_ctx *ctx, int32_t enable);
+/* Restrict the recording to the phases whose names appear in `names` (host
+ * string, comma-separated, e.g. "lowrank_tiles,raw_gram_tiles"); NULL or "" records
+ * every phase again.  Applies from the next recorded phase on. */
+xpcs_status xpcs_phase_filter(xpcs_ctx *ctx, const char *names);
 xpcs_status xpcs_phase_times(xpcs_ctx *ctx, int32_t cap, char *names, double *ms, int64_t *launches,
                              int32_t *n_out);
 
@@ -229,12 +233,12 @@ xpcs_status correlate_two_time_noalloc(xpcs_ctx *ctx, const xpcs_factors *f, int
 /* Two-time correlation from the raw frames (Sec. 2.1, Eqs. 1-2 per ROI), the path
  * the compressed correlation replaces:
  *   C_R[t1][t2] = |R| * G_R[t1][t2] / (S_R[t1] S_R[t2]),  G_R = X_R^T X_R exact.
- * The ROI pixels are gathered once into int8 and G_R runs on int8 MFMA with
- * int32 accumulation (int64 across pixel chunks), so G_R is exact; this needs
- * every count <= 127.  A larger count raises the device flag XPCS_ERANGE
- * (reported by xpcs_sync) and, in the same call, makes every entry of C NaN and
- * every npairs 0 (g2 NaN), so that no inexact value leaves the call looking valid;
- * gram_out then holds the Gram of the counts clamped to 127 and is not exact.
+ * The counts are split into 7-bit planes, count = P0 + 128 P1 + 16384 P2 (P2 for
+ * uint16 only).  Plane 0 of every ROI pixel is gathered once into int8 and its
+ * Gram runs on int8 MFMA with int32 accumulation (int64 across pixel chunks); the
+ * pixels where some count reaches 128 add the other plane pairs,
+ * 2^(7 (a + b)) P_a P_b^T, the same way.  G_R is exact for every count (while it
+ * stays below 2^63; C is its FP64 normalisation).
  * Arguments as correlate_two_time; gram_out (device int64, same layout as C with
  * row stride t1-t0, or NULL) receives the exact G_R. */
 xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dtype, int64_t M,

@@ -100,6 +100,7 @@ SIGNATURES = {
     "xpcs_stream_save": (_ST, [_P, ctypes.c_char_p]),
     "xpcs_stream_load": (_ST, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
     "xpcs_enable_phase_timing": (_ST, [_P, _I32]),
+    "xpcs_phase_filter": (_ST, [_P, ctypes.c_char_p]),
     "xpcs_phase_times": (_ST, [_P, _I32, _P, _P, _P, ctypes.POINTER(_I32)]),
     "xpcs_stream_open": (_ST, [_P, ctypes.POINTER(XpcsStreamDesc), ctypes.POINTER(_P)]),
     "xpcs_stream_push": (_ST, [_P, _P, _I64, _P, _I32]),

@@ -90,6 +90,11 @@ class Context:
         """Record HIP events around every kernel phase (also clears earlier records)."""
         self.check(self.lib.xpcs_enable_phase_timing(self.handle, 1 if enable else 0))
 
+    def phase_filter(self, names=None):
+        """Record only the named phases (an iterable of names; None: every phase)."""
+        arg = None if not names else ",".join(names).encode()
+        self.check(self.lib.xpcs_phase_filter(self.handle, arg))
+
     def phase_times(self, cap: int = 64):
         """{phase: (total_ms, launches)} since timing was enabled (waits for the stream)."""
         names = ctypes.create_string_buffer(32 * cap)

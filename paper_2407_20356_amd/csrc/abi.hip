@@ -450,6 +450,7 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
     auto add = [&](size_t b) { need += align_up(b, 256) + 256; };
     add((size_t)n_roi * 8); add((size_t)(n_roi + 1) * 8); add((size_t)cap * 4); add((size_t)cap * 4);
     add((size_t)nw * ldx); add((size_t)n_roi * nw * 8); add(256);
+    add((size_t)cap * 4); add((size_t)cap * 8); add((size_t)n_roi * 4); add((size_t)n_roi * 4);
     if (g2) { add(g2_part_bytes(nw, nr)); add(g2_cnt_bytes(nw, nr)); }
     if ((st = ws_reserve(ctx, need))) return st;
     auto *npix = static_cast<int64_t *>(ws_take(ctx, (size_t)n_roi * 8));
@@ -459,6 +460,10 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
     auto *xs = static_cast<int8_t *>(ws_take(ctx, (size_t)nw * ldx));
     auto *S = static_cast<int64_t *>(ws_take(ctx, (size_t)n_roi * nw * 8));
     auto *amax = static_cast<int *>(ws_take(ctx, 256));
+    auto *hot = static_cast<int *>(ws_take(ctx, (size_t)cap * 4));
+    auto *hq = static_cast<int64_t *>(ws_take(ctx, (size_t)cap * 8));
+    auto *hcnt = static_cast<int *>(ws_take(ctx, (size_t)n_roi * 4));
+    auto *hbits = static_cast<int *>(ws_take(ctx, (size_t)n_roi * 4));
     TileOut o;
     o.C = C;
     o.c_dtype = c_dtype;
@@ -473,8 +478,19 @@ xpcs_status correlate_two_time_raw(xpcs_ctx *ctx, const void *frames, int32_t dt
     if ((st = launch_roi_count(ctx, roi_label, M, n_roi, npix))) return st;
     if ((st = launch_roi_order(ctx, roi_label, M, n_roi, npix, kRawPad, off, perm, qroi, cap))) return st;
     if ((st = launch_zero(ctx, amax, 256))) return st;
-    if ((st = launch_gather_i8(ctx, frames, dtype, M, t0, nw, perm, qroi, off, n_roi, ldx, xs, S, amax, cap))) return st;
-    if ((st = launch_raw_gram_tiles(ctx, xs, ldx, off, npix, S, nw, r0, nr, amax, M, o))) return st;
+    if ((st = launch_gather_i8(ctx, frames, dtype, M, t0, nw, perm, qroi, off, n_roi, ldx, xs, S, amax, hot, hq, hcnt,
+                               hbits, cap)))
+        return st;
+    RawHot rh;
+    rh.frames = frames;
+    rh.dtype = dtype;
+    rh.M = M;
+    rh.t0 = t0;
+    rh.perm = perm;
+    rh.hq = hq;
+    rh.hcnt = hcnt;
+    rh.hbits = hbits;
+    if ((st = launch_raw_gram_tiles(ctx, xs, ldx, off, npix, S, nw, r0, nr, amax, rh, o))) return st;
     if (g2 && (st = launch_g2_reduce(ctx, o.g2_part, o.g2_cnt, nw, nr, g2, npairs))) return st;
     return XPCS_OK;
 }

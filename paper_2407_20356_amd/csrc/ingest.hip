@@ -226,6 +226,11 @@ __global__ __launch_bounds__(64) void roi_chunk_scatter_kernel(const int32_t *__
 // 4-byte word per frame, so both the gathered loads and the stores are
 // contiguous across the wave.  ROI sums go through LDS (int, exact) and then one
 // exact 64-bit atomic per (frame, ROI) and block.
+//
+// xs holds plane 0 of the counts (count & 127), exact in int8; a position with a
+// count of 128 or more is marked hot[q] (bit 0: plane 1 is needed; bit 1: plane 2,
+// a count of 16384 or more), and the raw Gram adds those pixels' higher planes
+// separately.  amax is the largest plane-0 value, which sets the int32 chunk.
 constexpr int kGatherQ = 4096;
 constexpr int kGatherT = 32;
 constexpr int kGatherSlots = 64;
@@ -236,7 +241,8 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
                                                         const int32_t *__restrict__ qroi,
                                                         const int64_t *__restrict__ off, int n_roi,
                                                         int64_t ldx, int8_t *__restrict__ xs,
-                                                        unsigned long long *__restrict__ S, int *amax, int *flags) {
+                                                        unsigned long long *__restrict__ S, int *amax,
+                                                        int *__restrict__ hot) {
     __shared__ int s_sum[kGatherT][kGatherSlots];
     const int64_t total = off[n_roi];
     const int64_t qb = (int64_t)blockIdx.x * kGatherQ;
@@ -246,18 +252,21 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
     for (int idx = threadIdx.x; idx < kGatherT * kGatherSlots; idx += blockDim.x) (&s_sum[0][0])[idx] = 0;
     __syncthreads();
     int vmax = 0;
-    bool over = false;
     constexpr int kPasses = kGatherQ / (4 * 256);
     int px[kPasses][4];
     int roi[kPasses];
     bool live[kPasses];
+    unsigned hb[kPasses][4];
 #pragma unroll
     for (int ps = 0; ps < kPasses; ++ps) {
         const int64_t q = qb + 4 * (threadIdx.x + 256 * ps);
         live[ps] = q < total;
         roi[ps] = live[ps] ? qroi[q] : -1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) px[ps][e] = live[ps] ? perm[q + e] : -1;
+        for (int e = 0; e < 4; ++e) {
+            px[ps][e] = live[ps] ? perm[q + e] : -1;
+            hb[ps][e] = 0;
+        }
     }
     const int64_t tend = tb + kGatherT < nw ? tb + kGatherT : nw;
 #pragma unroll 4
@@ -272,12 +281,10 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
             int sum = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                vmax = v[e] > vmax ? v[e] : vmax;
-                if (v[e] > 127) {
-                    over = true;
-                    v[e] = 127;
-                }
                 sum += v[e];
+                hb[ps][e] |= (v[e] >= 128 ? 1u : 0u) | (v[e] >= 16384 ? 2u : 0u);
+                v[e] &= 127;
+                vmax = v[e] > vmax ? v[e] : vmax;
             }
             const int word = (v[0] & 0xff) | ((v[1] & 0xff) << 8) | ((v[2] & 0xff) << 16) | ((v[3] & 0xff) << 24);
             const int64_t q = qb + 4 * (threadIdx.x + 256 * ps);
@@ -298,12 +305,55 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
         if (v && r_first + slot < n_roi && tb + tt < nw)
             atomicAdd(&S[(int64_t)(r_first + slot) * nw + tb + tt], (unsigned long long)v);
     }
-    if (over) atomicOr(&flags[kFlagRange], 1);
+#pragma unroll
+    for (int ps = 0; ps < kPasses; ++ps)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (hb[ps][e]) atomicOr(&hot[qb + 4 * (threadIdx.x + 256 * ps) + e], (int)hb[ps][e]);
     for (int o = 32; o > 0; o >>= 1) {
         int v = __shfl_xor(vmax, o);
         vmax = v > vmax ? v : vmax;
     }
     if ((threadIdx.x & 63) == 0) atomicMax(amax, vmax);
+}
+
+// Per ROI (one block): the hot positions of its range in order, hq[off[r] + i]
+// (i < hcnt[r]), and the OR of their plane bits in hbits[r].
+__global__ __launch_bounds__(256) void hot_list_kernel(const int *__restrict__ hot, const int64_t *__restrict__ off,
+                                                       int64_t *__restrict__ hq, int *__restrict__ hcnt,
+                                                       int *__restrict__ hbits) {
+    __shared__ int s_cnt[4];
+    __shared__ int s_base;
+    __shared__ int s_bits;
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q0 = off[r], q1 = off[r + 1];
+    if (threadIdx.x == 0) {
+        s_base = 0;
+        s_bits = 0;
+    }
+    __syncthreads();
+    int bits = 0;
+    for (int64_t c = q0; c < q1; c += 256) {
+        const int64_t q = c + threadIdx.x;
+        const int h = q < q1 ? hot[q] : 0;
+        bits |= h;
+        const unsigned long long m = __ballot(h != 0);
+        if (lane == 0) s_cnt[w] = __popcll(m);
+        __syncthreads();
+        int before = s_base;
+        for (int v = 0; v < w; ++v) before += s_cnt[v];
+        if (h) hq[q0 + before + __popcll(m & ((1ull << lane) - 1ull))] = q;
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
+    }
+    if (bits) atomicOr(&s_bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        hcnt[r] = s_base;
+        hbits[r] = s_bits;
+    }
 }
 
 }  // namespace
@@ -352,22 +402,27 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
 
 xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t t0, int64_t nw,
                              const int32_t *perm, const int32_t *qroi, const int64_t *off, int n_roi, int64_t ldx,
-                             int8_t *xs, int64_t *S, int *amax, int64_t total_cap) {
+                             int8_t *xs, int64_t *S, int *amax, int *hot, int64_t *hq, int *hcnt, int *hbits,
+                             int64_t total_cap) {
     Phase phase_(ctx, "gather_i8");
     if (ldx % 16) return fail(ctx, XPCS_EINVAL, "internal: gather row stride not a multiple of 16");
-    // the sums are accumulated with atomics: start from zero
+    // the sums are accumulated with atomics, the hot marks ORed: start from zero
     hipLaunchKernelGGL(fill_i64_kernel, dim3(256), dim3(256), 0, ctx->stream, S, (int64_t)n_roi * nw, (int64_t)0);
+    xpcs_status st = launch_zero(ctx, hot, (size_t)total_cap * sizeof(int));
+    if (st) return st;
     dim3 grid((unsigned)((total_cap + kGatherQ - 1) / kGatherQ), (unsigned)((nw + kGatherT - 1) / kGatherT));
     auto *Su = reinterpret_cast<unsigned long long *>(S);
     if (dtype == XPCS_U8)
         hipLaunchKernelGGL(gather_i8_kernel<uint8_t>, grid, dim3(256), 0, ctx->stream,
                            static_cast<const uint8_t *>(frames), M, t0, nw, perm, qroi, off, n_roi, ldx, xs, Su,
-                           amax, ctx->flags);
+                           amax, hot);
     else
         hipLaunchKernelGGL(gather_i8_kernel<uint16_t>, grid, dim3(256), 0, ctx->stream,
                            static_cast<const uint16_t *>(frames), M, t0, nw, perm, qroi, off, n_roi, ldx, xs, Su,
-                           amax, ctx->flags);
+                           amax, hot);
     XPCS_LAUNCH_CHECK(ctx, "gather_i8");
+    hipLaunchKernelGGL(hot_list_kernel, dim3((unsigned)n_roi), dim3(256), 0, ctx->stream, hot, off, hq, hcnt, hbits);
+    XPCS_LAUNCH_CHECK(ctx, "hot_list");
     return XPCS_OK;
 }
 

@@ -50,7 +50,7 @@ __device__ __forceinline__ i32x4 mfma_i8(const i32x4 &a, const i32x4 &b, i32x4 c
 
 // ---------------------------------------------------------------- device flags
 enum : int {
-    kFlagRange = 0,     // a count above 127 reached the int8 path
+    kFlagRange = 0,     // reserved (no path raises it: the raw Gram is exact for every count)
     kFlagLabel = 1,     // a label outside [-1, n_roi)
     kFlagNumeric = 2,   // a numerically singular step (all sketch pivots dropped, no convergence)
     kNumFlags = 4,
@@ -80,6 +80,7 @@ struct xpcs_ctx {
     int *flags = nullptr;        // device int[kNumFlags]
     std::string last_error;
     bool timing = false;                         // phase timing enabled
+    std::vector<std::string> phase_only;         // record only these phases (empty: all)
     std::vector<xpcs::PhaseRecord> phases;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;          // reusable events
     void *static_scratch = nullptr;              // this device's copy of the library's static scratch array
@@ -155,11 +156,15 @@ xpcs_status launch_roi_order(xpcs_ctx *ctx, const int32_t *labels, int64_t M, in
                              const int64_t *roi_npix, int pad, int64_t *off, int32_t *perm,
                              int32_t *qroi, int64_t total_cap);
 // Gather the ROI pixels of frames [t0, t0+nw) to int8 rows xs[t][q] (row stride
-// ldx >= total), with exact ROI sums S[r*nw + t] and the int8-range flag.
+// ldx >= total) as plane 0 of the counts (count & 127), with exact ROI sums
+// S[r*nw + t], the largest plane-0 value amax, and the positions whose counts need
+// higher planes: hot[q] (total_cap ints, bit 0: a count >= 128, bit 1: >= 16384),
+// per ROI their list hq[off[r] + i], i < hcnt[r] (hq: total_cap entries), and the
+// OR of their bits hbits[r].
 xpcs_status launch_gather_i8(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M,
                              int64_t t0, int64_t nw, const int32_t *perm, const int32_t *qroi,
                              const int64_t *off, int n_roi, int64_t ldx, int8_t *xs, int64_t *S,
-                             int *amax, int64_t total_cap);
+                             int *amax, int *hot, int64_t *hq, int *hcnt, int *hbits, int64_t total_cap);
 
 // ---------------------------------------------------------------- tile pass (tiles.hip)
 struct TileOut {
@@ -180,10 +185,22 @@ inline int64_t n_tiles_upper(int64_t nw) {
     return nb * (nb + 1) / 2;
 }
 
-// Raw ROI Gram on int8 MFMA + normalisation epilogue, for ROIs [r0, r0+nr).
+// The hot positions of a raw pass (from launch_gather_i8) and the frames they are
+// read back from for their higher count planes.
+struct RawHot {
+    const void *frames = nullptr;
+    int dtype = XPCS_U8;
+    int64_t M = 0, t0 = 0;
+    const int32_t *perm = nullptr;
+    const int64_t *hq = nullptr;
+    const int *hcnt = nullptr;
+    const int *hbits = nullptr;
+};
+// Raw ROI Gram on int8 MFMA + normalisation epilogue, for ROIs [r0, r0+nr); exact
+// for every count (plane 0 from xs, the higher planes of the hot positions).
 xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx,
                                   const int64_t *off, const int64_t *roi_npix, const int64_t *S,
-                                  int64_t nw, int r0, int nr, const int *amax, int64_t max_roi_pixels,
+                                  int64_t nw, int r0, int nr, const int *amax, const RawHot &hot,
                                   const TileOut &out);
 // Low-rank tiles C = Z Z^T for ROIs [0, nr) from split-bf16 rows laid out
 // [r][t][kp] (hi and lo), with the frame validity mask valid[r*nw + t].

@@ -69,7 +69,7 @@ __device__ __forceinline__ typename PixPack<T, RB>::type load_pix_partial(const 
 // past M read pixel 0 and their outputs are dropped; frames past N read frame N-1
 // and meet the zero rows of B), which keeps the count of loads in flight fixed.
 template <typename T, int RB, int NCB, bool VEC, int KG, int D>
-__global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ X, int64_t M, int64_t N,
+__global__ __launch_bounds__(256, sizeof(T) == 1 ? 2 : 1) void proj_pixels_kernel(const T *__restrict__ X, int64_t M, int64_t N,
                                                           const unsigned short *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ Y) {
     typedef typename PixPack<T, RB>::type PV;
@@ -196,10 +196,10 @@ __global__ __launch_bounds__(256) void proj_pixels_kernel(const T *__restrict__ 
     }
 }
 
-// Groups of 32 frames per K step: one-byte counts take two, so that a step moves
-// as many bytes as a two-byte step does.
+// Groups of 32 frames per K step: one (two groups of one-byte counts, with their
+// staged operands, cost the occupancy more than the wider loads gain).
 template <typename T>
-constexpr int pp_groups(int rb, int ncb) { return sizeof(T) == 1 ? 2 : 1; }
+constexpr int pp_groups(int rb, int ncb) { return 1; }
 // K steps of counts in flight beyond the one being multiplied.
 template <typename T>
 constexpr int pp_depth(int rb, int ncb) { return 1; }
@@ -247,7 +247,7 @@ xpcs_status launch_proj_pixels(xpcs_ctx *ctx, const void *frames, int dtype, int
                                const unsigned short *B, int64_t ldb, int L, float *Y) {
     Phase phase_(ctx, "proj_pixels");
     if (L % 16 || L <= 0) return fail(ctx, XPCS_EINVAL, "internal: L must be a positive multiple of 16");
-    const int64_t kstep = dtype == XPCS_U8 ? 64 : 32;      // frames per K step
+    const int64_t kstep = 32;                              // frames per K step
     if (ldb % kstep || ldb < N)
         return fail(ctx, XPCS_EINVAL, "internal: sketch row stride must cover N in whole K steps");
     const int ncb_total = L / 16;

@@ -7,10 +7,12 @@
 // sums of its 255 diagonals t2 - t1 = const in a partial buffer, and a second,
 // fixed-order pass adds them per lag (no float atomics, deterministic).
 //
-// Block shape: 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning a
-// 64 x 64 quarter of the 128 x 128 tile as 4 x 4 MFMA 16 x 16 blocks.  The
-// epilogue stages one 64-row half of the tile in LDS at a time so that both the
-// direct and the mirrored writes go out as contiguous rows.
+// Block shapes: the low-rank tiles and the wide raw variant use 256 threads = 4
+// waves in a 2 x 2 arrangement, each wave owning a 64 x 64 quarter of the
+// 128 x 128 tile as 4 x 4 MFMA 16 x 16 blocks, and an epilogue that stages one
+// 64-row half of the tile in LDS at a time so that both the direct and the
+// mirrored writes go out as contiguous rows; the common raw case uses 256 x 256
+// super-tiles (one 128-tile per wave, below).
 #include <math.h>
 
 #include <type_traits>
@@ -166,12 +168,42 @@ __device__ __forceinline__ int64_t raw_chunk_pixels(const int *__restrict__ amax
     return kc < 64 ? 64 : kc;
 }
 
-template <typename OutT, bool WIDE>
+// The counts of the hot positions (a count of 128 or more somewhere) of a ROI, for
+// the higher planes that the int8 gather leaves out (WIDE path only).
+template <typename T>
+struct HotIn {
+    const T *frames = nullptr;          // the frames of the window start at frames + t0 * M
+    int64_t M = 0, t0 = 0;
+    const int32_t *perm = nullptr;      // pixel of each ROI-sorted position
+    const int64_t *hq = nullptr;        // hot positions of ROI r: hq[off[r] + i], i < hcnt[r]
+    const int *hcnt = nullptr;
+    const int *hbits = nullptr;         // bit 1: some count of the ROI needs plane 2
+};
+constexpr int kHotPitch = 64 + 8;       // LDS row pitch (u16) of 64 staged hot counts
+
+// 16 counts (u16, K order) -> one int8 operand of their 7-bit plane p.
+__device__ __forceinline__ i32x4 hot_plane_frag(const unsigned short *src, int p) {
+    const i32x4 lo = *reinterpret_cast<const i32x4 *>(src), hi = *reinterpret_cast<const i32x4 *>(src + 8);
+    const unsigned m = p == 2 ? 3u : 127u;
+    const int sh = 7 * p;
+    i32x4 out;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const unsigned w0 = (unsigned)(d < 2 ? lo[2 * d] : hi[2 * d - 4]);
+        const unsigned w1 = (unsigned)(d < 2 ? lo[2 * d + 1] : hi[2 * d - 3]);
+        const unsigned b0 = ((w0 & 0xffffu) >> sh) & m, b1 = ((w0 >> 16) >> sh) & m;
+        const unsigned b2 = ((w1 & 0xffffu) >> sh) & m, b3 = ((w1 >> 16) >> sh) & m;
+        out[d] = (int)(b0 | (b1 << 8) | (b2 << 16) | (b3 << 24));
+    }
+    return out;
+}
+
+template <typename OutT, bool WIDE, typename T = uint8_t>
 __device__ __forceinline__ void raw_gram_tile(
     int bi, int bj, int64_t tile_id, const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int slot,
-    int64_t ntiles, int64_t kc, bool over, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
-    int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    int64_t ntiles, int64_t kc, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
+    int64_t gram_roi_stride, double *g2_part, int *g2_cnt, const HotIn<T> &hot = HotIn<T>()) {
     // the operand stages (two buffers of 256 rows x kRawKs bytes) share the LDS of
     // the epilogue's staging buffer
     __shared__ __attribute__((aligned(16))) double stage[kRawLdsDoubles];
@@ -281,6 +313,55 @@ __device__ __forceinline__ void raw_gram_tile(
         if (st + 1 < nstage) put(buf ^ 1);
         __syncthreads();
     }
+    // Higher planes of the hot positions: the Gram of the counts is the sum over
+    // plane pairs (pa, pb) of 2^(7 (pa + pb)) P_pa P_pb^T; plane 0 of every position
+    // is done above, the other pairs only involve the hot positions.  Their counts
+    // are staged in LDS 64 positions at a time (rows as in the main loop), each
+    // pair's products formed in int32 over the 64 positions and added shifted.
+    if constexpr (WIDE) {
+        const int nh = hot.hcnt[roi];
+        if (nh > 0) {
+            const int np = (hot.hbits[roi] & 2) ? 3 : 2;
+            const int64_t *hl = hot.hq + q0;
+            unsigned short *hs = reinterpret_cast<unsigned short *>(stage);
+            for (int h0 = 0; h0 < nh; h0 += 64) {
+                {
+                    const int c = threadIdx.x & 63;
+                    const int px = h0 + c < nh ? hot.perm[hl[h0 + c]] : -1;
+                    for (int i = 0; i < 64; ++i) {
+                        const int row = (threadIdx.x >> 6) + 4 * i;
+                        const int64_t t = row < kTile ? i0 + row : j0 + (row - kTile);
+                        unsigned v = 0;
+                        if (px >= 0 && t < nw && !(diag && row >= kTile)) v = hot.frames[(hot.t0 + t) * hot.M + px];
+                        hs[row * kHotPitch + c] = (unsigned short)v;
+                    }
+                }
+                __syncthreads();
+                if (!skip) {
+                    for (int pa = 0; pa < np; ++pa)
+                        for (int pb = 0; pb < np; ++pb) {
+                            if (pa == 0 && pb == 0) continue;
+                            i32x4 av[4], bv[4];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                av[a] = hot_plane_frag(hs + (64 * wr + 16 * a + lr) * kHotPitch + 16 * lg, pa);
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                bv[b] = hot_plane_frag(hs + (jrow0 + 64 * wc + 16 * b + lr) * kHotPitch + 16 * lg, pb);
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                                for (int b = 0; b < 4; ++b) {
+                                    const i32x4 tp = mfma_i8(av[a], bv[b], (i32x4){0, 0, 0, 0});
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) wide[a][b][e] += (int64_t)tp[e] << (7 * (pa + pb));
+                                }
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    }
     auto gval = [&](int a, int b, int e) -> int64_t {
         if constexpr (WIDE)
             return wide[a][b][e];
@@ -338,13 +419,8 @@ __device__ __forceinline__ void raw_gram_tile(
                     for (int e = 0; e < 4; ++e) {
                         const int rl = 16 * a + 4 * lg + e;
                         const double si = srow[4 * a + e];
-                        double v;
-                        // a count above 127 was clamped on its way to int8: no value of this
-                        // Gram is exact, so C is NaN throughout and g2 has no pairs
-                        if (si > 0.0 && sj > 0.0 && !over)
-                            v = (npix * (double)gval(a, b, e)) / (si * sj);
-                        else
-                            v = __builtin_nan("");
+                        const double v = (si > 0.0 && sj > 0.0) ? (npix * (double)gval(a, b, e)) / (si * sj)
+                                                                : __builtin_nan("");
                         stage[rl * kPitch + c] = v;
                     }
             }
@@ -356,44 +432,281 @@ __device__ __forceinline__ void raw_gram_tile(
     write_diag_partials(g2_part, g2_cnt, (int64_t)slot * ntiles + tile_id, dsum, dcnt);
 }
 
-// One block per tile; ROIs that need more than one int32 chunk are left to the wide kernel.
+// Whether a ROI takes the int32 fast path: its plane-0 sums are exact in one chunk
+// and none of its positions needs a higher plane.
+__device__ __forceinline__ bool raw_fast_roi(const int *__restrict__ amax, int64_t qlen, const int *__restrict__ hcnt,
+                                             int roi) {
+    return qlen <= raw_chunk_pixels(amax, qlen) && hcnt[roi] == 0;
+}
+
+// One block per 128-tile (windows too short to fill the GPU with super-tiles), for
+// the fast-path ROIs.
 template <typename OutT>
 __global__ __launch_bounds__(256, 2) void raw_gram_tile_kernel(
     const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
-    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
+    const int *__restrict__ amax, const int *__restrict__ hcnt, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
     int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
     const int slot = blockIdx.y, roi = r0 + slot;
     const int64_t qlen = off[roi + 1] - off[roi];
-    const int64_t kc = raw_chunk_pixels(amax, qlen);
-    if (qlen > kc) return;
+    if (!raw_fast_roi(amax, qlen, hcnt, roi)) return;
     int bi, bj;
     tile_coords(blockIdx.x, nb, bi, bj);
-    raw_gram_tile<OutT, false>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x, kc, *amax > 127, C, ldc,
-                               c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
+    raw_gram_tile<OutT, false>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x,
+                               raw_chunk_pixels(amax, qlen), C, ldc, c_roi_stride, vec, gram_out, gram_roi_stride,
+                               g2_part, g2_cnt);
 }
 
-// One block per (tile row, ROI), looping over the row's tiles, for the ROIs whose
-// pixel count needs several int32 chunks (int64 between chunks).  Blocks of other
-// ROIs leave at once; the grid is small, so the launch costs little when unused.
-template <typename OutT>
-__global__ __launch_bounds__(256, 2) void raw_gram_wide_kernel(
+// One block per 128-tile for the other ROIs: int32 chunks of plane 0 folded into
+// int64, then the higher planes of the hot positions.  Blocks of fast-path ROIs
+// leave at once.
+template <typename OutT, typename T>
+__global__ __launch_bounds__(256, 2) void raw_gram_slow_kernel(
     const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb,
-    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
-    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    const int *__restrict__ amax, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec, int64_t *gram_out,
+    int64_t gram_roi_stride, double *g2_part, int *g2_cnt, HotIn<T> hot) {
     const int slot = blockIdx.y, roi = r0 + slot;
     const int64_t qlen = off[roi + 1] - off[roi];
-    const int64_t kc = raw_chunk_pixels(amax, qlen);
-    if (qlen <= kc) return;
-    const int bi = blockIdx.x;
-    const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
-    for (int bj = bi; bj < nb; ++bj) {
-        const int64_t D = bj - bi;
-        const int64_t tile_id = D * nb - D * (D - 1) / 2 + bi;
-        raw_gram_tile<OutT, true>(bi, bj, tile_id, xs, ldx, off, roi_npix, S, nw, r0, slot, ntiles, kc, *amax > 127, C, ldc,
-                                  c_roi_stride, vec, gram_out, gram_roi_stride, g2_part, g2_cnt);
+    if (raw_fast_roi(amax, qlen, hot.hcnt, roi)) return;
+    int bi, bj;
+    tile_coords(blockIdx.x, nb, bi, bj);
+    raw_gram_tile<OutT, true, T>(bi, bj, blockIdx.x, xs, ldx, off, roi_npix, S, nw, r0, slot, gridDim.x,
+                                 raw_chunk_pixels(amax, qlen), C, ldc, c_roi_stride, vec, gram_out, gram_roi_stride,
+                                 g2_part, g2_cnt, hot);
+}
+
+// ---------------------------------------------------------------- raw Gram, 256 x 256 super-tiles
+// The common case of the raw path -- a ROI whose int32 sums are exact in one chunk
+// (every count fits int8, pixels * amax^2 < 2^31) -- runs on super-tiles of 256 x 256
+// frames: 4 waves, each owning one 128 x 128 tile of it as 8 x 8 int8 MFMA blocks
+// (256 accumulator registers per lane), so that every 16-byte operand fragment read
+// from LDS feeds 8 MFMAs and every staged row serves two tiles; a super-tile reads
+// half the operand bytes per output of a 128-tile block.  Each wave then writes its
+// own tile (waves whose tile lies below the diagonal or past the window skip it).
+constexpr int kSup = 2 * kTile;
+constexpr int kSupKs = 64;                                  // pixels (bytes) per K step
+constexpr int kSupPitch = kSupKs + 16;                      // LDS row pitch: conflict-free fragment reads
+constexpr int kSupRows = 2 * kSup;                          // staged rows: row block, column block
+constexpr int kSupStage = kSupRows * kSupPitch;             // bytes per staged K step
+constexpr int kSupPer = kSupRows * (kSupKs / 16) / 256;     // 16-byte pieces per thread and K step
+constexpr int kEpiRows = 32;                                // rows of a tile staged at a time
+constexpr int kEpiWave = kEpiRows * kPitch;                 // doubles of one wave's staging area
+constexpr int kSupLds = 2 * kSupStage > 4 * kEpiWave * 8 ? 2 * kSupStage : 4 * kEpiWave * 8;
+
+// Wave-level epilogue of one 128 x 128 tile held in acc[8][8] (rows 16a + 4lg + e,
+// columns 16b + lr of the tile): four passes of 32 rows, each staged as normalised
+// doubles in the wave's own LDS area, then written as direct rows and mirrored
+// columns (contiguous in both), and summed along the tile's 255 diagonals (lane l
+// owns diagonals l - 127 + 64k, k = 0..3).
+template <typename OutT, bool GRAM>
+__device__ __forceinline__ void raw_tile_epilogue_wave(const i32x4 (&acc)[8][8], double *st, int64_t i0,
+                                                       int64_t j0, bool diag, int64_t nw,
+                                                       const int64_t *__restrict__ Sr, double npix,
+                                                       OutT *C, int64_t ldc, bool vec, int64_t *Gr,
+                                                       double *g2p, int *g2c) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    double scol[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t j = j0 + 16 * b + lr;
+        scol[b] = j < nw ? (double)Sr[j] : 0.0;
     }
+    double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+    int dcnt[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int qr = 0; qr < 4; ++qr) {
+        // stage rows [32 qr, 32 qr + 32) of the tile
+#pragma unroll
+        for (int ah = 0; ah < 2; ++ah)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rl = 16 * ah + 4 * lg + e;
+                const int64_t i = i0 + kEpiRows * qr + rl;
+                const double si = i < nw ? (double)Sr[i] : 0.0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int g = acc[2 * qr + ah][b][e];
+                    const double sj = scol[b];
+                    st[rl * kPitch + 16 * b + lr] =
+                        (si > 0.0 && sj > 0.0) ? (npix * (double)g) / (si * sj) : __builtin_nan("");
+                    if constexpr (GRAM) {
+                        // the exact Gram (a verification output), mirrored
+                        const int64_t j = j0 + 16 * b + lr;
+                        if (i < nw && j < nw && j >= i) {
+                            Gr[i * nw + j] = (int64_t)g;
+                            Gr[j * nw + i] = (int64_t)g;
+                        }
+                    }
+                }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int r0 = kEpiRows * qr;
+        if (C) {
+            // direct rows: 32 lanes x 4 columns per row, 2 rows per pass
+#pragma unroll 1
+            for (int pass = 0; pass < kEpiRows / 2; ++pass) {
+                const int rl = 2 * pass + (lane >> 5);
+                const int c = (lane & 31) * 4;
+                const int64_t i = i0 + r0 + rl;
+                if (i < nw) {
+                    OutT v[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        ok[e] = (j0 + c + e < nw) && (!diag || c + e >= r0 + rl);
+                        v[e] = (OutT)st[rl * kPitch + c + e];
+                    }
+                    store4(C + i * ldc + j0 + c, v, ok, vec);
+                }
+            }
+            // mirrored columns: 8 lanes x 4 rows per column, 8 columns per pass
+#pragma unroll 1
+            for (int pass = 0; pass < kTile / 8; ++pass) {
+                const int c = 8 * pass + (lane >> 3);
+                const int rq = (lane & 7) * 4;
+                const int64_t j = j0 + c;
+                if (j < nw) {
+                    OutT v[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + rq + e;
+                        ok[e] = (i0 + r < nw) && (!diag || c > r);
+                        v[e] = (OutT)st[(rq + e) * kPitch + c];
+                    }
+                    store4(C + j * ldc + i0 + r0 + rq, v, ok, vec);
+                }
+            }
+        }
+        if (g2p) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int d = lane - (kTile - 1) + 64 * k;        // c - r
+                if (d > kTile - 1 || (diag && d < 0)) continue;
+                int r_lo = r0, r_hi = r0 + kEpiRows;
+                if (d < 0 && r_lo < -d) r_lo = -d;                     // c = r + d >= 0
+                if (d > 0 && r_hi > kTile - d) r_hi = kTile - d;       // c = r + d < kTile
+                if (i0 + r_hi > nw) r_hi = (int)(nw - i0);             // rows inside the window
+                const int64_t c_lim = nw - j0 - d;                     // and columns
+                if (r_hi > c_lim) r_hi = (int)c_lim;
+                for (int r = r_lo; r < r_hi; ++r) {
+                    const double v = st[(r - r0) * kPitch + r + d];
+                    if (v == v) {
+                        dsum[k] += v;
+                        dcnt[k] += 1;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (g2p) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int slot = lane + 64 * k;
+            if (slot < kDiag) {
+                g2p[slot] = dsum[k];
+                g2c[slot] = dcnt[k];
+            }
+        }
+    }
+}
+
+template <typename OutT, bool GRAM>
+__global__ __launch_bounds__(256, 1) void raw_gram_super_kernel(
+    const int8_t *__restrict__ xs, int64_t ldx, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb, int nb2,
+    const int *__restrict__ amax, const int *__restrict__ hcnt, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
+    int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
+    __shared__ __attribute__((aligned(16))) double lds[kSupLds / 8];
+    const int slot = blockIdx.y, roi = r0 + slot;
+    const int64_t q0 = off[roi], qlen = off[roi + 1] - off[roi];
+    if (!raw_fast_roi(amax, qlen, hcnt, roi)) return;            // the slow kernel's ROI
+    int bi2, bj2;
+    tile_coords(blockIdx.x, nb2, bi2, bj2);
+    const bool dsup = bi2 == bj2;
+    const int64_t I0 = (int64_t)bi2 * kSup, J0 = (int64_t)bj2 * kSup;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    i32x4 acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = (i32x4){0, 0, 0, 0};
+
+    // K steps of 64 pixels: the super-tile's rows (256 of the row block, 256 of the
+    // column block; 256 in all on the diagonal) loaded into registers one step
+    // ahead, written to the other LDS buffer after the current step's MFMAs.
+    int8_t *ops = reinterpret_cast<int8_t *>(lds);
+    const int nsteps = (int)((qlen + kSupKs - 1) / kSupKs);
+    const int jrow0 = dsup ? 0 : kSup;
+    i32x4 nxt[kSupPer];
+    auto fetch = [&](int st) {
+        const int64_t k = q0 + (int64_t)st * kSupKs;
+#pragma unroll
+        for (int q = 0; q < kSupPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            const int row = u >> 2, part = u & 3;
+            const int64_t t = row < kSup ? I0 + row : J0 + (row - kSup);
+            i32x4 v = {0, 0, 0, 0};
+            if (t < nw && !(dsup && row >= kSup)) v = *reinterpret_cast<const i32x4 *>(xs + t * ldx + k + 16 * part);
+            nxt[q] = v;
+        }
+    };
+    auto put = [&](int buf) {
+        int8_t *dst = ops + buf * kSupStage;
+#pragma unroll
+        for (int q = 0; q < kSupPer; ++q) {
+            const int u = threadIdx.x + 256 * q;
+            *reinterpret_cast<i32x4 *>(dst + (u >> 2) * kSupPitch + 16 * (u & 3)) = nxt[q];
+        }
+    };
+    if (nsteps > 0) {
+        fetch(0);
+        put(0);
+        __syncthreads();
+    }
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) fetch(st + 1);
+        {
+            // every wave multiplies (a wave whose tile is below the diagonal or past the
+            // window computes values nobody reads): a branch here would move the
+            // accumulators out of their registers every step
+            const int8_t *src = ops + buf * kSupStage;
+            i32x4 av[8], bv[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                bv[b] = *reinterpret_cast<const i32x4 *>(src + (jrow0 + 128 * wc + 16 * b + lr) * kSupPitch + 16 * lg);
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                av[a] = *reinterpret_cast<const i32x4 *>(src + (128 * wr + 16 * a + lr) * kSupPitch + 16 * lg);
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) acc[a][b] = mfma_i8(av[a], bv[b], acc[a][b]);
+        }
+        if (st + 1 < nsteps) put(buf ^ 1);
+        __syncthreads();
+    }
+
+    // each wave writes its own tile through its own LDS area
+    const int tbi = 2 * bi2 + wr, tbj = 2 * bj2 + wc;
+    if (tbi >= nb || tbj >= nb || tbi > tbj) return;
+    const int64_t i0 = (int64_t)tbi * kTile, j0 = (int64_t)tbj * kTile;
+    const int64_t *Sr = S + (int64_t)roi * nw;
+    const int64_t D = tbj - tbi;
+    const int64_t tile = (int64_t)slot * ((int64_t)nb * (nb + 1) / 2) + D * nb - D * (D - 1) / 2 + tbi;
+    raw_tile_epilogue_wave<OutT, GRAM>(acc, lds + w * kEpiWave, i0, j0, tbi == tbj, nw, Sr, (double)roi_npix[roi],
+                                 C ? C + (int64_t)slot * c_roi_stride : nullptr, ldc, vec,
+                                 gram_out ? gram_out + (int64_t)slot * gram_roi_stride : nullptr,
+                                 g2_part ? g2_part + tile * kDiag : nullptr, g2_part ? g2_cnt + tile * kDiag : nullptr);
 }
 
 // ---------------------------------------------------------------- low-rank tiles (split-bf16 MFMA)
@@ -599,36 +912,72 @@ __global__ __launch_bounds__(256) void g2_reduce_kernel(const double *__restrict
 
 xpcs_status launch_raw_gram_tiles(xpcs_ctx *ctx, const int8_t *xs, int64_t ldx, const int64_t *off,
                                   const int64_t *roi_npix, const int64_t *S, int64_t nw, int r0, int nr,
-                                  const int *amax, int64_t max_roi_pixels, const TileOut &o) {
+                                  const int *amax, const RawHot &h, const TileOut &o) {
     Phase phase_(ctx, "raw_gram_tiles");
     const int nb = (int)((nw + kTile - 1) / kTile);
     const int64_t nt = n_tiles_upper(nw);
     if (nt > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "window too large");
-    dim3 grid((unsigned)nt, (unsigned)nr);
     const bool vec = o.C && o.c_dtype == XPCS_F32 && (o.ldc % 4 == 0) &&
                      ((uintptr_t)o.C % 16 == 0) && (o.c_roi_stride % 4 == 0);
-    // The wide variant is only needed when some ROI can exceed the smallest int32 chunk
-    // (counts <= 127: 133,120 pixels); M bounds every ROI.
-    const bool maybe_wide = max_roi_pixels > 133120;
-    dim3 wgrid((unsigned)nb, (unsigned)nr);
-    if (o.C == nullptr || o.c_dtype == XPCS_F32) {
-        hipLaunchKernelGGL(raw_gram_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, xs, ldx, off,
-                           roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
-                           o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
-        if (maybe_wide)
-            hipLaunchKernelGGL(raw_gram_wide_kernel<float>, wgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
-                               roi_npix, S, nw, r0, nb, amax, static_cast<float *>(o.C), o.ldc,
-                               o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
-    } else {
-        hipLaunchKernelGGL(raw_gram_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, xs, ldx, off,
-                           roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
-                           o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
-        if (maybe_wide)
-            hipLaunchKernelGGL(raw_gram_wide_kernel<double>, wgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
-                               roi_npix, S, nw, r0, nb, amax, static_cast<double *>(o.C), o.ldc,
-                               o.c_roi_stride, false, o.gram_out, o.gram_roi_stride, o.g2_part, o.g2_cnt);
-    }
+    const bool f32 = o.C == nullptr || o.c_dtype == XPCS_F32;
+    float *Cf = static_cast<float *>(o.C);
+    double *Cd = static_cast<double *>(o.C);
+    const int nb2 = (int)((nw + kSup - 1) / kSup);
+    const int64_t nsup = (int64_t)nb2 * (nb2 + 1) / 2;
+    const dim3 sgrid((unsigned)nsup, (unsigned)nr), grid((unsigned)nt, (unsigned)nr);
+    // Fast-path ROIs on super-tiles once there are enough of them to give every CU a
+    // block, else on 128-tiles; the slow kernel takes the other ROIs (which ROI is
+    // which is only known on the device, so both launch).
+    const bool sup = nsup * nr >= 256;
+    if (!sup && f32)
+        hipLaunchKernelGGL(raw_gram_tile_kernel<float>, grid, dim3(256), 0, ctx->stream, xs, ldx, off, roi_npix, S, nw,
+                           r0, nb, amax, h.hcnt, Cf, o.ldc, o.c_roi_stride, vec, o.gram_out, o.gram_roi_stride,
+                           o.g2_part, o.g2_cnt);
+    else if (!sup)
+        hipLaunchKernelGGL(raw_gram_tile_kernel<double>, grid, dim3(256), 0, ctx->stream, xs, ldx, off, roi_npix, S,
+                           nw, r0, nb, amax, h.hcnt, Cd, o.ldc, o.c_roi_stride, false, o.gram_out,
+                           o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    else if (f32 && o.gram_out)
+        hipLaunchKernelGGL((raw_gram_super_kernel<float, true>), sgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, nb2, amax, h.hcnt, Cf, o.ldc, o.c_roi_stride, vec, o.gram_out,
+                           o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    else if (f32)
+        hipLaunchKernelGGL((raw_gram_super_kernel<float, false>), sgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, nb2, amax, h.hcnt, Cf, o.ldc, o.c_roi_stride, vec, o.gram_out,
+                           o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    else if (o.gram_out)
+        hipLaunchKernelGGL((raw_gram_super_kernel<double, true>), sgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, nb2, amax, h.hcnt, Cd, o.ldc, o.c_roi_stride, false, o.gram_out,
+                           o.gram_roi_stride, o.g2_part, o.g2_cnt);
+    else
+        hipLaunchKernelGGL((raw_gram_super_kernel<double, false>), sgrid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                           roi_npix, S, nw, r0, nb, nb2, amax, h.hcnt, Cd, o.ldc, o.c_roi_stride, false, o.gram_out,
+                           o.gram_roi_stride, o.g2_part, o.g2_cnt);
     XPCS_LAUNCH_CHECK(ctx, "raw_gram_tiles");
+    auto slow = [&](auto tag) {
+        typedef decltype(tag) T;
+        HotIn<T> hi;
+        hi.frames = static_cast<const T *>(h.frames);
+        hi.M = h.M;
+        hi.t0 = h.t0;
+        hi.perm = h.perm;
+        hi.hq = h.hq;
+        hi.hcnt = h.hcnt;
+        hi.hbits = h.hbits;
+        if (f32)
+            hipLaunchKernelGGL((raw_gram_slow_kernel<float, T>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                               roi_npix, S, nw, r0, nb, amax, Cf, o.ldc, o.c_roi_stride, vec, o.gram_out,
+                               o.gram_roi_stride, o.g2_part, o.g2_cnt, hi);
+        else
+            hipLaunchKernelGGL((raw_gram_slow_kernel<double, T>), grid, dim3(256), 0, ctx->stream, xs, ldx, off,
+                               roi_npix, S, nw, r0, nb, amax, Cd, o.ldc, o.c_roi_stride, false, o.gram_out,
+                               o.gram_roi_stride, o.g2_part, o.g2_cnt, hi);
+    };
+    if (h.dtype == XPCS_U8)
+        slow(uint8_t{});
+    else
+        slow(uint16_t{});
+    XPCS_LAUNCH_CHECK(ctx, "raw_gram_slow");
     return XPCS_OK;
 }
 

@@ -58,6 +58,7 @@ static void null_arguments(void) {
     EXPECT(xpcs_last_error(NULL) != NULL);
     EXPECT(xpcs_workspace_bytes(NULL) == 0);
     EXPECT(xpcs_enable_phase_timing(NULL, 1) == XPCS_EINVAL);
+    EXPECT(xpcs_phase_filter(NULL, "lowrank_tiles") == XPCS_EINVAL);
     EXPECT(xpcs_phase_times(NULL, 1, names, d, i64, i32) == XPCS_EINVAL);
     EXPECT(compress_frames(NULL, d, XPCS_U8, 4, 4, i32, 1, &opts, &f) == XPCS_EINVAL);
     EXPECT(correlate_two_time(NULL, &f, XPCS_ALL_ROIS, 0, 4, d, XPCS_F64, 4, d, i64) == XPCS_EINVAL);

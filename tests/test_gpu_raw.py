@@ -84,20 +84,67 @@ def test_raw_g2_only_matches_with_c(ctx):
     np.testing.assert_array_equal(to_np(na), to_np(nb))
 
 
-def test_raw_rejects_counts_above_127(ctx):
+def _hot_frames(M, N, dtype, top, seed, hot_px):
+    """Dim speckle counts plus bright pixels: hot_px get counts spread over [0, top],
+    one frame of each reaching top."""
+    rng = np.random.default_rng(seed)
+    F = rng.poisson(0.4, size=(N, M)).astype(np.uint8 if dtype == "u8" else np.uint16)
+    for k, px in enumerate(hot_px):
+        F[:, px] = rng.integers(0, top + 1, size=N)
+        F[(7 * k + 3) % N, px] = top
+    return F
+
+
+@pytest.mark.parametrize("dtype,top", [("u8", 255), ("u16", 300), ("u16", 65535)])
+def test_raw_exact_for_every_count(ctx, dtype, top):
+    """Counts of 128 and more (plane 1) and of 16384 and more (plane 2, uint16) in
+    some pixels of ROI 1 only: ROIs 0 and 2 take the fast path, ROI 1 the path that
+    adds the hot pixels' higher planes.  Every Gram is exact (bit-exact int64
+    against the oracle) and C is the oracle's normalisation to FP64 rounding."""
+    import torch
     from paper_2407_20356_amd import api
-    F = np.full((20, 64), 3, dtype=np.uint16)
-    F[7, 5] = 300
-    labels = np.zeros(64, dtype=np.int32)
-    say("raw count > 127 raises ERANGE at sync; C is NaN and g2 has no pairs")
-    C, g2, npairs, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 1)
-    with pytest.raises(api.XpcsError) as ei:
-        ctx.sync()
-    assert ei.value.status == -3
-    ctx.sync()   # the flag is cleared
-    assert np.isnan(to_np(C)).all()
-    assert np.isnan(to_np(g2)).all()
-    assert (to_np(npairs) == 0).all()
+    H = W = 24
+    M, N = H * W, 260
+    labels = synth.annular_labels(H, W, 3, r_in=1.0)
+    ring1 = np.flatnonzero(labels == 1)
+    F = _hot_frames(M, N, dtype, top, seed=top, hot_px=ring1[[0, 5, len(ring1) - 1]])
+    say(f"raw exact with {dtype} counts up to {top}")
+    C, g2, npairs, gram = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), 3, c_dtype=torch.float64,
+                                                     want_gram=True)
+    ctx.sync()
+    gram, C, g2, npairs = to_np(gram), to_np(C), to_np(g2), to_np(npairs)
+    for r in range(3):
+        np.testing.assert_array_equal(gram[r], O.raw_gram(F, labels, r), err_msg=f"Gram roi {r}")
+        Cref = O.raw_two_time(F, labels, r)
+        np.testing.assert_allclose(C[r], Cref, rtol=1e-15, atol=0, equal_nan=True)
+        gref, nref = O.g2_from_two_time(Cref)
+        np.testing.assert_array_equal(npairs[r], nref)
+        np.testing.assert_allclose(g2[r], gref, rtol=1e-12, equal_nan=True)
+
+
+def test_raw_hot_roi_beside_super_tiles(ctx):
+    """A window long enough for the 256 x 256 super-tiles (2,048 frames, 8 ROIs): the
+    seven dim ROIs on super-tiles, the ROI with bright uint16 pixels on the slow
+    path, in one call; C in FP32 with fused g2."""
+    import torch
+    from paper_2407_20356_amd import api
+    H = W = 40
+    M, N, R = H * W, 2048, 8
+    labels = synth.annular_labels(H, W, R, r_in=1.0)
+    ring = np.flatnonzero(labels == 6)
+    F = _hot_frames(M, N, "u16", 40000, seed=8, hot_px=ring[[1, 2, 40]])
+    say("raw super-tiles beside a hot ROI, 2048 frames x 8 ROIs")
+    C, g2, npairs, _ = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), R)
+    ctx.sync()
+    C, g2, npairs = to_np(C), to_np(g2), to_np(npairs)
+    ts = np.unique(np.concatenate([[0, 1, 255, 256, 511, 1023, 1024, 2047], np.arange(3, 2048, 97)]))
+    for r in range(R):
+        Cref = O.raw_two_time(F, labels, r)
+        np.testing.assert_array_equal(np.nan_to_num(C[r][np.ix_(ts, ts)], nan=-7.0),
+                                      np.nan_to_num(Cref[np.ix_(ts, ts)].astype(np.float32), nan=-7.0))
+        gref, nref = O.g2_from_two_time(Cref)
+        np.testing.assert_array_equal(npairs[r], nref)
+        np.testing.assert_allclose(g2[r], gref, rtol=1e-6, equal_nan=True)
 
 
 def test_bad_label_is_reported(ctx):
