@@ -1,6 +1,6 @@
 // Frame-space products X^T Q (Sec. 2.1): planning, launch and the fixed-order
 // reduction of the per-chunk partial sums.
-#include "proj_frames.hpp"
+#include "proj_frames_dma.hpp"
 
 namespace xpcs {
 namespace {
@@ -31,6 +31,25 @@ __global__ __launch_bounds__(256) void proj_frames_reduce_kernel(const float *__
         S[(int64_t)(j - L) * N + t] = (int64_t)__builtin_rint(s);
 }
 
+// ind[r][p] = bf16(1) where labels[p] == r, else 0, for r < nrows and p < ldq
+// (zero past M): the indicator rows of the direct-to-LDS frame pass.
+__global__ __launch_bounds__(256) void indicator_rows_kernel(const int32_t *__restrict__ labels, int64_t M,
+                                                             int64_t ldq, int nrows, unsigned short *__restrict__ ind) {
+    const int64_t p8 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+    if (p8 >= ldq) return;
+    int lab[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lab[e] = p8 + e < M ? labels[p8 + e] : -1;
+    for (int r = 0; r < nrows; ++r) {
+        i32x4 w;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            w[d] = (int)((lab[2 * d] == r ? (unsigned)proj::kBfOne : 0u) |
+                         ((lab[2 * d + 1] == r ? (unsigned)proj::kBfOne : 0u) << 16));
+        *reinterpret_cast<i32x4 *>(ind + (int64_t)r * ldq + p8) = w;
+    }
+}
+
 }  // namespace
 
 using proj::pf_rb;
@@ -52,6 +71,9 @@ namespace {
 // the two launches take 28.9 ms where the single wide one took 31.7 ms.  uint16
 // passes stay single (their count bytes dominate).
 constexpr int kMaxFragsPerLaunch = 13;
+static_assert(kMaxFragsPerLaunch == proj::kDmaMaxBlocks, "column groups of both frame-pass kernels");
+// Fewest frames for the direct-to-LDS frame pass.
+constexpr int64_t kDmaMinFrames = 1024;
 }  // namespace
 
 FrameProj plan_proj_frames(int64_t M, int64_t N, int L, int n_ind, bool lo) {
@@ -91,7 +113,31 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
     const bool vec = (M % 8 == 0) && ((uintptr_t)frames % (8 * esz) == 0) &&
                      (nib == 0 || (uintptr_t)labels % 16 == 0);
     const int frags = ncb * (lo ? 2 : 1) + nib;
-    if (ncb <= 12 && (!lo || frags <= kMaxFragsPerLaunch || dtype != XPCS_U8)) {
+    // Direct-to-LDS loads need 16-byte aligned rows of counts and basis; passes over
+    // few frames (an online push) keep the register-staged kernel, which needs no
+    // indicator matrix.
+    const bool dma = N >= kDmaMinFrames && (uintptr_t)frames % 16 == 0 && ((size_t)M * esz) % 16 == 0 &&
+                     (uintptr_t)q_hi % 16 == 0 && (!lo || (uintptr_t)q_lo % 16 == 0);
+    const unsigned short *ind = nullptr;
+    if (dma && nib > 0) {
+        xpcs_status st;
+        auto *buf = static_cast<unsigned short *>(scratch_get(ctx, (size_t)16 * nib * ldq * 2, &st));
+        if (!buf) return st;
+        hipLaunchKernelGGL(indicator_rows_kernel, dim3((unsigned)((ldq / 8 + 255) / 256)), dim3(256), 0, ctx->stream,
+                           labels, M, ldq, 16 * nib, buf);
+        XPCS_LAUNCH_CHECK(ctx, "indicator_rows");
+        ind = buf;
+    }
+    // the direct-to-LDS kernel picks its own frames per block; the chunks are the plan's
+    auto run = [&](int ncb_g, int nib_g, const unsigned short *qh, const unsigned short *ql,
+                   const unsigned short *ind_g, float *pg) {
+        if (dtype == XPCS_U8)
+            return proj::dispatch_pf_dma_u8(ncb_g, nib_g, lo, plan.nchunks, ctx->stream, frames, M, N, qh, ql, ind_g,
+                                            ldq, plan.chunk, plan.ncols, pg);
+        return proj::dispatch_pf_dma_u16(ncb_g, nib_g, lo, plan.nchunks, ctx->stream, frames, M, N, qh, ql, ind_g,
+                                         ldq, plan.chunk, plan.ncols, pg);
+    };
+    if (ncb <= 12 && (!lo || frags <= kMaxFragsPerLaunch || (dtype != XPCS_U8 && !dma))) {
         const int rb = pf_rb(ncb, nib, lo);
         if (rb * 64 != plan.frames_per_block)
             return fail(ctx, XPCS_EINVAL, "internal: projection plan made for another variant");
@@ -100,7 +146,8 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
         const int64_t nblocks = (int64_t)nfb * plan.nchunks;
         if (nblocks > 2147483647LL) return fail(ctx, XPCS_EUNSUPPORTED, "projection grid too large");
         const bool ok =
-            dtype == XPCS_U8
+            dma ? run(ncb, nib, q_hi, q_lo, ind, part)
+            : dtype == XPCS_U8
                 ? proj::dispatch_pf_u8(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq, labels,
                                        plan.chunk, nfb, plan.ncols, part, vec)
                 : proj::dispatch_pf_u16(ncb, nib, lo, (int)nblocks, ctx->stream, frames, M, N, q_hi, q_lo, ldq,
@@ -152,7 +199,9 @@ xpcs_status launch_proj_frames(xpcs_ctx *ctx, const void *frames, int dtype, int
         const unsigned short *ql = lo ? q_lo + (int64_t)16 * c0 * ldq : nullptr;
         float *pg = part + 16 * c0;
         bool ok;
-        if (nib_g || !lo)
+        if (dma)
+            ok = run(ncb_g, nib_g, qh, ql, last ? ind : nullptr, pg);
+        else if (nib_g || !lo)
             ok = dtype == XPCS_U8
                      ? proj::dispatch_pf_u8(ncb_g, nib_g, lo, (int)nblocks, ctx->stream, frames, M, N, qh, ql, ldq,
                                             labels, plan.chunk, nfb, plan.ncols, pg, vec)
