@@ -302,6 +302,147 @@ __global__ __launch_bounds__(kGramMfmaThreads) void tsgram_mfma_kernel(const TA 
     }
 }
 
+// Wider Grams (80 < columns <= 192) on the same FP64 MFMA.  The column blocks are
+// split into ng groups of G blocks (blocks past the last column read as zeros and
+// their tiles are not multiplied) and a launch takes the pairs of groups (P, Q):
+// DIAG, P = Q = blockIdx.z, the upper G(G+1)/2 tiles of the group; otherwise the
+// z-th pair P < Q and all G x G tiles.  Four waves per block (one per SIMD: a pair
+// holds up to 25 tiles, 200 accumulator registers); each wave walks every fourth
+// 16-row group of the block's rows, loading the next group while multiplying the
+// current one, and the waves' tiles are added in LDS in wave order.  Tile layout
+// and the partial's upper-tile format are those of the narrow kernel above.
+constexpr int kGramPairThreads = 256;
+constexpr int kGramPairWaves = kGramPairThreads / 64;
+
+template <typename TA, int NB>
+__device__ __forceinline__ void gram_rows_load(const TA *__restrict__ A, int64_t lda, int ncols, int c0, int64_t r,
+                                               int64_t r_end, bool vec, const int32_t *__restrict__ row_idx,
+                                               int cl, TA (&x)[NB][4]) {
+    if (vec && r + 4 <= r_end) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int c = c0 + 16 * cb + cl;
+            if (c < ncols) {
+                load_rows4(A + (int64_t)c * lda + r, x[cb]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[cb][j] = (TA)0;
+            }
+        }
+        return;
+    }
+    int64_t rowj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t pos = r + j;
+        rowj[j] = pos < r_end ? (row_idx ? (int64_t)row_idx[pos] : pos) : -1;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        const int c = c0 + 16 * cb + cl;
+        const TA *src = A + (int64_t)(c < ncols ? c : 0) * lda;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[cb][j] = (c < ncols && rowj[j] >= 0) ? src[rowj[j]] : (TA)0;
+    }
+}
+
+template <typename TA, int G, bool DIAG>
+__global__ __launch_bounds__(kGramPairThreads) void tsgram_pair_kernel(const TA *__restrict__ A, int64_t rows,
+                                                                       int64_t lda, int ncols, int pw, int ng,
+                                                                       double *__restrict__ part,
+                                                                       const int32_t *__restrict__ row_idx,
+                                                                       const int64_t *__restrict__ seg_off, bool vec) {
+    part += (int64_t)blockIdx.y * gridDim.x * pw * pw;
+    const int64_t r_begin = seg_off ? seg_off[blockIdx.y] : 0;
+    const int64_t r_end = seg_off ? seg_off[blockIdx.y + 1] : rows;
+    int P = blockIdx.z, Q = blockIdx.z;
+    if (!DIAG) {
+        int rem = blockIdx.z;
+        P = 0;
+        while (rem >= ng - 1 - P) {
+            rem -= ng - 1 - P;
+            ++P;
+        }
+        Q = P + 1 + rem;
+    }
+    const int p0 = 16 * G * P, q0 = 16 * G * Q;          // first column of each group
+    constexpr int W = 16 * G;
+    __shared__ double red[W * W];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cl = lane & 15, kq = lane >> 4;
+    // blocks of the groups that hold columns (uniform across the block)
+    const int nbp = (ncols - p0 + 15) / 16 < G ? (ncols - p0 + 15) / 16 : G;
+    const int nbq = (ncols - q0 + 15) / 16 < G ? (ncols - q0 + 15) / 16 : G;
+    const int64_t ngroups = (r_end - r_begin + 15) / 16;
+    const int64_t per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per_blk;
+    const int64_t g1 = g0 + per_blk < ngroups ? g0 + per_blk : ngroups;
+    f64x4 acc[G][G];
+#pragma unroll
+    for (int I = 0; I < G; ++I)
+#pragma unroll
+        for (int J = 0; J < G; ++J) acc[I][J] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    constexpr int GJ = DIAG ? 1 : G;                     // the second group's rows (unused when DIAG)
+    TA ci[G][4], ni[G][4], cj[GJ][4], nj[GJ][4];
+    int64_t g = g0 + wv;
+    if (g < g1) {
+        const int64_t r = r_begin + g * 16 + 4 * kq;
+        gram_rows_load<TA, G>(A, lda, ncols, p0, r, r_end, vec, row_idx, cl, ni);
+        if constexpr (!DIAG) gram_rows_load<TA, GJ>(A, lda, ncols, q0, r, r_end, vec, row_idx, cl, nj);
+    }
+    for (; g < g1; g += kGramPairWaves) {
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ci[b][j] = ni[b][j];
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int b = 0; b < GJ; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cj[b][j] = nj[b][j];
+        }
+        if (g + kGramPairWaves < g1) {
+            const int64_t r = r_begin + (g + kGramPairWaves) * 16 + 4 * kq;
+            gram_rows_load<TA, G>(A, lda, ncols, p0, r, r_end, vec, row_idx, cl, ni);
+            if constexpr (!DIAG) gram_rows_load<TA, GJ>(A, lda, ncols, q0, r, r_end, vec, row_idx, cl, nj);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double fi[G], fj[G];
+#pragma unroll
+            for (int b = 0; b < G; ++b) {
+                fi[b] = (double)ci[b][j];
+                fj[b] = DIAG ? fi[b] : (double)cj[DIAG ? 0 : b][j];
+            }
+#pragma unroll
+            for (int I = 0; I < G; ++I)
+#pragma unroll
+                for (int J = DIAG ? I : 0; J < G; ++J)
+                    if (I < nbp && J < nbq) acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[I], fj[J], acc[I][J], 0, 0, 0);
+        }
+    }
+    for (int w = 0; w < kGramPairWaves; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int I = 0; I < G; ++I)
+#pragma unroll
+                for (int J = DIAG ? I : 0; J < G; ++J)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int idx = (16 * I + kq + 4 * v) * W + 16 * J + cl;
+                        red[idx] = (w == 0 ? 0.0 : red[idx]) + acc[I][J][v];
+                    }
+        }
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.x * pw * pw;
+    for (int idx = threadIdx.x; idx < W * W; idx += kGramPairThreads) {
+        const int la = idx / W, lb = idx % W;
+        const int a = p0 + la, b = q0 + lb;
+        if (a < pw && b < pw && (!DIAG || la / 16 <= lb / 16)) out[(int64_t)a * pw + b] = red[idx];
+    }
+}
+
 // G[seg][a][b] = sum over parts of part[.][ra][rb], (ra, rb) the copy in an upper block.
 // 8 threads per entry sum interleaved parts; the 8 sums are added in a fixed order.
 __global__ __launch_bounds__(256) void tsgram_reduce_kernel(const double *__restrict__ part, int nparts, int ncols,
@@ -1407,6 +1548,43 @@ xpcs_status launch_tsgram(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows
     const size_t lds_sums = (size_t)nblk * 16 * sizeof(double);     // one 4x4 block per owned block id
     const size_t lds = lds_tile > lds_sums ? lds_tile : lds_sums;
     dim3 grid(nparts, nseg);
+    // 81..192 columns: the FP64 MFMA kernel over pairs of column groups
+    if (ncols > 80 && (seg_off || (!row_idx && nseg == 1))) {
+        const int nbatch = seg_off ? nseg : 1;
+        const int ncb = (ncols + 15) / 16;
+        const int ng = (ncb + 4) / 5;                  // groups of at most 5 blocks
+        const int gsz = (ncb + ng - 1) / ng;      // blocks per group
+        const bool vec = !row_idx && !seg_off && lda % 4 == 0 && (uintptr_t)A % 16 == 0;
+        const int npairs = ng * (ng - 1) / 2;
+#define XPCS_TSGP(T, GG)                                                                                            \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((tsgram_pair_kernel<T, GG, true>), dim3(nparts, nbatch, ng), dim3(kGramPairThreads), 0,   \
+                           ctx->stream, static_cast<const T *>(A), rows, lda, ncols, pw, ng, part, row_idx, seg_off, \
+                           vec);                                                                                  \
+        if (npairs > 0)                                                                                           \
+            hipLaunchKernelGGL((tsgram_pair_kernel<T, GG, false>), dim3(nparts, nbatch, npairs),                   \
+                               dim3(kGramPairThreads), 0, ctx->stream, static_cast<const T *>(A), rows, lda, ncols, \
+                               pw, ng, part, row_idx, seg_off, vec);                                              \
+    } while (0)
+#define XPCS_TSGP_T(T)                      \
+    switch (gsz) {                          \
+        case 3: XPCS_TSGP(T, 3); break;     \
+        case 4: XPCS_TSGP(T, 4); break;     \
+        default: XPCS_TSGP(T, 5); break;    \
+    }
+        if (a_f64) {
+            XPCS_TSGP_T(double)
+        } else {
+            XPCS_TSGP_T(float)
+        }
+#undef XPCS_TSGP_T
+#undef XPCS_TSGP
+        XPCS_LAUNCH_CHECK(ctx, "tsgram_pair");
+        hipLaunchKernelGGL(tsgram_reduce_kernel, dim3((ncols * ncols + 31) / 32, nseg), dim3(256), 0, ctx->stream,
+                           part, nparts, ncols, pw, G);
+        XPCS_LAUNCH_CHECK(ctx, "tsgram_reduce");
+        return XPCS_OK;
+    }
     // up to 80 columns: the FP64 MFMA kernel (one matrix, or one segment per blockIdx.y)
     if (ncols <= 80 && (seg_off || (!row_idx && nseg == 1))) {
         const int nbatch = seg_off ? nseg : 1;
