@@ -486,13 +486,19 @@ __global__ __launch_bounds__(256, 2) void raw_gram_slow_kernel(
 // own tile (waves whose tile lies below the diagonal or past the window skip it).
 constexpr int kSup = 2 * kTile;
 constexpr int kSupKs = 64;                                  // pixels (bytes) per K step
-constexpr int kSupPitch = kSupKs + 16;                      // LDS row pitch: conflict-free fragment reads
 constexpr int kSupRows = 2 * kSup;                          // staged rows: row block, column block
-constexpr int kSupStage = kSupRows * kSupPitch;             // bytes per staged K step
-constexpr int kSupPer = kSupRows * (kSupKs / 16) / 256;     // 16-byte pieces per thread and K step
+constexpr int kSupStage = kSupRows * kSupKs;                // bytes per staged K step (rows of 64 bytes)
+constexpr int kSupUnits = kSupStage / 1024 / 4;             // 1 KB direct-to-LDS loads per wave and K step
 constexpr int kEpiRows = 32;                                // rows of a tile staged at a time
 constexpr int kEpiWave = kEpiRows * kPitch;                 // doubles of one wave's staging area
-constexpr int kSupLds = 2 * kSupStage > 4 * kEpiWave * 8 ? 2 * kSupStage : 4 * kEpiWave * 8;
+static_assert(kSupStage <= kEpiWave * 8, "a K stage fits one wave's epilogue area");
+
+// s_waitcnt vmcnt(n) with no wait on the other counters (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void sup_wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
 
 // Wave-level epilogue of one 128 x 128 tile held in acc[8][8] (rows 16a + 4lg + e,
 // columns 16b + lr of the tile): four passes of 32 rows, each staged as normalised
@@ -623,7 +629,10 @@ __global__ __launch_bounds__(256, 1) void raw_gram_super_kernel(
     const int64_t *__restrict__ roi_npix, const int64_t *__restrict__ S, int64_t nw, int r0, int nb, int nb2,
     const int *__restrict__ amax, const int *__restrict__ hcnt, OutT *C, int64_t ldc, int64_t c_roi_stride, bool vec,
     int64_t *gram_out, int64_t gram_roi_stride, double *g2_part, int *g2_cnt) {
-    __shared__ __attribute__((aligned(16))) double lds[kSupLds / 8];
+    // four LDS areas, one per wave for the epilogue; the first three are the stage
+    // buffers of the K loop (distinct arrays, so that the compiler sees which buffer a
+    // load fills)
+    __shared__ __attribute__((aligned(1024))) double e0[kEpiWave], e1[kEpiWave], e2[kEpiWave], e3[kEpiWave];
     const int slot = blockIdx.y, roi = r0 + slot;
     const int64_t q0 = off[roi], qlen = off[roi + 1] - off[roi];
     if (!raw_fast_roi(amax, qlen, hcnt, roi)) return;            // the slow kernel's ROI
@@ -640,61 +649,67 @@ __global__ __launch_bounds__(256, 1) void raw_gram_super_kernel(
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = (i32x4){0, 0, 0, 0};
 
-    // K steps of 64 pixels: the super-tile's rows (256 of the row block, 256 of the
-    // column block; 256 in all on the diagonal) loaded into registers one step
-    // ahead, written to the other LDS buffer after the current step's MFMAs.
-    int8_t *ops = reinterpret_cast<int8_t *>(lds);
+    // K steps of 64 pixels: the super-tile's 512 rows (256 of the row block, 256 of the
+    // column block; on the diagonal the row block twice) reach LDS by direct-to-LDS
+    // loads (each lane's 16 bytes land at the wave's LDS address + 16 * lane), rows of
+    // 64 bytes whose four 16-byte pieces are XOR-swizzled (piece p of row r in slot
+    // p ^ ((r >> 1) & 3): the fragment reads of eight consecutive rows fall on distinct
+    // banks).  Two buffers alternate: after the barrier that publishes step st, a wave
+    // reads all its fragments of step st, then starts the loads of step st + 1 into the
+    // other buffer (which every wave finished reading before the barrier) and
+    // multiplies while they fly; no load is pending while LDS is read.  Rows past the
+    // window read the block's first row (their products land in tiles nobody reads).
     const int nsteps = (int)((qlen + kSupKs - 1) / kSupKs);
     const int jrow0 = dsup ? 0 : kSup;
-    i32x4 nxt[kSupPer];
-    auto fetch = [&](int st) {
-        const int64_t k = q0 + (int64_t)st * kSupKs;
+    const int8_t *lsrc[kSupUnits];
 #pragma unroll
-        for (int q = 0; q < kSupPer; ++q) {
-            const int u = threadIdx.x + 256 * q;
-            const int row = u >> 2, part = u & 3;
-            const int64_t t = row < kSup ? I0 + row : J0 + (row - kSup);
-            i32x4 v = {0, 0, 0, 0};
-            if (t < nw && !(dsup && row >= kSup)) v = *reinterpret_cast<const i32x4 *>(xs + t * ldx + k + 16 * part);
-            nxt[q] = v;
-        }
-    };
-    auto put = [&](int buf) {
-        int8_t *dst = ops + buf * kSupStage;
-#pragma unroll
-        for (int q = 0; q < kSupPer; ++q) {
-            const int u = threadIdx.x + 256 * q;
-            *reinterpret_cast<i32x4 *>(dst + (u >> 2) * kSupPitch + 16 * (u & 3)) = nxt[q];
-        }
-    };
-    if (nsteps > 0) {
-        fetch(0);
-        put(0);
-        __syncthreads();
+    for (int j = 0; j < kSupUnits; ++j) {
+        const int u = w + 4 * j;
+        const int row = 16 * u + (lane >> 2);
+        const int piece = (lane & 3) ^ ((row >> 1) & 3);
+        const int64_t base = row < kSup || dsup ? I0 : J0;
+        int64_t t = base + (row & (kSup - 1));
+        if (t >= nw) t = base;
+        lsrc[j] = xs + t * ldx + q0 + 16 * piece;
     }
+    auto issue = [&](int st, double *dst) {
+#pragma unroll
+        for (int j = 0; j < kSupUnits; ++j) {
+            const int u = w + 4 * j;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(lsrc[j] + (int64_t)st * kSupKs),
+                                             (__attribute__((address_space(3))) void *)(
+                                                 reinterpret_cast<char *>(dst) + 1024 * u),
+                                             16, 0, 0);
+        }
+    };
+    // the lane's fragment rows: 16 a + lr of its row block, 16 b + lr of its column block
+    const int arow = 128 * wr + lr, brow = jrow0 + 128 * wc + lr;
+    const int aoff = arow * kSupKs + 16 * (lg ^ ((arow >> 1) & 3));
+    const int boff = brow * kSupKs + 16 * (lg ^ ((brow >> 1) & 3));
+    if (nsteps > 0) issue(0, e0);
     for (int st = 0; st < nsteps; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nsteps) fetch(st + 1);
-        {
-            // every wave multiplies (a wave whose tile is below the diagonal or past the
-            // window computes values nobody reads): a branch here would move the
-            // accumulators out of their registers every step
-            const int8_t *src = ops + buf * kSupStage;
-            i32x4 av[8], bv[8];
+        double *cur = st & 1 ? e1 : e0, *nxt = st & 1 ? e0 : e1;
+        asm volatile("" ::: "memory");
+        sup_wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // every wave multiplies (a wave whose tile is below the diagonal or past the
+        // window computes values nobody reads): a branch here would move the
+        // accumulators out of their registers every step
+        const int8_t *src = reinterpret_cast<const int8_t *>(cur);
+        i32x4 av[8], bv[8];
 #pragma unroll
-            for (int b = 0; b < 8; ++b)
-                bv[b] = *reinterpret_cast<const i32x4 *>(src + (jrow0 + 128 * wc + 16 * b + lr) * kSupPitch + 16 * lg);
+        for (int b = 0; b < 8; ++b) bv[b] = *reinterpret_cast<const i32x4 *>(src + boff + 1024 * b);
 #pragma unroll
-            for (int a = 0; a < 8; ++a)
-                av[a] = *reinterpret_cast<const i32x4 *>(src + (128 * wr + 16 * a + lr) * kSupPitch + 16 * lg);
+        for (int a = 0; a < 8; ++a) av[a] = *reinterpret_cast<const i32x4 *>(src + aoff + 1024 * a);
+        asm volatile("" ::: "memory");
+        if (st + 1 < nsteps) issue(st + 1, nxt);
 #pragma unroll
-            for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < 8; ++a)
 #pragma unroll
-                for (int b = 0; b < 8; ++b) acc[a][b] = mfma_i8(av[a], bv[b], acc[a][b]);
-        }
-        if (st + 1 < nsteps) put(buf ^ 1);
-        __syncthreads();
+            for (int b = 0; b < 8; ++b) acc[a][b] = mfma_i8(av[a], bv[b], acc[a][b]);
     }
+    __syncthreads();
 
     // each wave writes its own tile through its own LDS area
     const int tbi = 2 * bi2 + wr, tbj = 2 * bj2 + wc;
@@ -703,7 +718,8 @@ __global__ __launch_bounds__(256, 1) void raw_gram_super_kernel(
     const int64_t *Sr = S + (int64_t)roi * nw;
     const int64_t D = tbj - tbi;
     const int64_t tile = (int64_t)slot * ((int64_t)nb * (nb + 1) / 2) + D * nb - D * (D - 1) / 2 + tbi;
-    raw_tile_epilogue_wave<OutT, GRAM>(acc, lds + w * kEpiWave, i0, j0, tbi == tbj, nw, Sr, (double)roi_npix[roi],
+    double *const area = w == 0 ? e0 : (w == 1 ? e1 : (w == 2 ? e2 : e3));
+    raw_tile_epilogue_wave<OutT, GRAM>(acc, area, i0, j0, tbi == tbj, nw, Sr, (double)roi_npix[roi],
                                  C ? C + (int64_t)slot * c_roi_stride : nullptr, ldc, vec,
                                  gram_out ? gram_out + (int64_t)slot * gram_roi_stride : nullptr,
                                  g2_part ? g2_part + tile * kDiag : nullptr, g2_part ? g2_cnt + tile * kDiag : nullptr);
