@@ -121,7 +121,7 @@ struct Orth {
         if (st) return st;
         st = launch_cholinv(ctx, G, ell, 1e-13, nullptr, R1);
         if (st) return st;
-        if (passes == 1) return launch_tsmul(ctx, A, a_f64, rows, lda, ell, R1, ell, nullptr, final_out);
+        if (passes == 1) return launch_tsmul(ctx, A, a_f64, rows, lda, ell, R1, ell, nullptr, final_out, true);
         TsOut o1;
         if (tmp_f64) {
             o1.out64 = static_cast<double *>(tmp);
@@ -130,13 +130,13 @@ struct Orth {
             o1.out32 = static_cast<float *>(tmp);
             o1.ld32 = rows;
         }
-        st = launch_tsmul(ctx, A, a_f64, rows, lda, ell, R1, ell, nullptr, o1);
+        st = launch_tsmul(ctx, A, a_f64, rows, lda, ell, R1, ell, nullptr, o1, true);
         if (st) return st;
         st = launch_tsgram(ctx, tmp, tmp_f64, rows, rows, ell, nullptr, nullptr, 1, G);
         if (st) return st;
         st = launch_cholinv(ctx, G, ell, 1e-13, nullptr, R2);
         if (st) return st;
-        return launch_tsmul(ctx, tmp, tmp_f64, rows, rows, ell, R2, ell, nullptr, final_out);
+        return launch_tsmul(ctx, tmp, tmp_f64, rows, rows, ell, R2, ell, nullptr, final_out, true);
     }
 };
 
@@ -197,7 +197,7 @@ xpcs_status compress_exact(xpcs_ctx *ctx, const void *frames, int32_t dtype, int
     TsOut ov;
     ov.out32 = out->V;
     ov.ld32 = N;
-    if ((st = launch_tsmul(ctx, Tu, true, N, N, k, Tid, k, nullptr, ov))) return st;
+    if ((st = launch_tsmul(ctx, Tu, true, N, N, k, Tid, k, nullptr, ov, true))) return st;
     // the exact ROI sums ride along the encoding pass W = X^T U (Eq. 7)
     if ((st = launch_basis_to_bf16(ctx, out->U, M, k, ldq, L, qhi, qlo))) return st;
     if ((st = launch_proj_frames(ctx, frames, dtype, M, N, qhi, qlo, ldq, L, roi_label, n_roi, plan, part))) return st;
@@ -305,7 +305,7 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
         TsOut ov;
         ov.out32 = out->V;
         ov.ld32 = N;
-        if ((st = launch_tsmul(ctx, Za, true, N, N, k, Tid, k, scale, ov))) return st;
+        if ((st = launch_tsmul(ctx, Za, true, N, N, k, Tid, k, scale, ov, true))) return st;
     } else {
         // 1. sketch Y0 = X Omega, exact on the int8 MFMA (+-1 signs, integer counts)
         uint8_t *om8 = reinterpret_cast<uint8_t *>(om), *q8 = reinterpret_cast<uint8_t *>(qlo);
@@ -366,12 +366,12 @@ xpcs_status compress_frames(xpcs_ctx *ctx, const void *frames, int32_t dtype, in
             TsOut o1;
             o1.out32 = Yb;
             o1.ld32 = M;
-            if ((st = launch_tsmul(ctx, Ya, false, M, M, ell, R1, ell, nullptr, o1))) return st;
+            if ((st = launch_tsmul(ctx, Ya, false, M, M, ell, R1, ell, nullptr, o1, true))) return st;
         }
         if ((st = launch_tsgram(ctx, Yb, false, M, M, ell, nullptr, nullptr, 1, G))) return st;
         if ((st = launch_cholinv(ctx, G, ell, 1e-13, nullptr, R2))) return st;
         oq.out32 = Ya;
-        if ((st = launch_tsmul(ctx, Yb, false, M, M, ell, R2, ell, nullptr, oq))) return st;
+        if ((st = launch_tsmul(ctx, Yb, false, M, M, ell, R2, ell, nullptr, oq, true))) return st;
         float *Qf = Ya;
         // 4. W_l = X^T Q with the residual term, and the exact ROI sums
         if ((st = launch_proj_frames(ctx, frames, dtype, M, N, qhi, qlo, ldq, L, roi_label, n_roi, plan, part)))

@@ -279,7 +279,9 @@ xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, d
 // out[:, j] = sum_i A[:, i] T[i][j] (A column-major rows x n, fp32 or fp64; T
 // column-major n x m fp64, optionally scaled per output column by colscale[j]).
 // Writes any of: fp32 out32 (stride ld32), fp64 out64 (stride ld64), bf16 hi/lo
-// rows (stride ldh) padded with zeros up to Lpad columns and rows_pad rows.
+// rows (stride ldh) padded with zeros up to Lpad columns and rows_pad rows.  With
+// t_upper, T is upper triangular (T[i][j] = 0 for i > j) and its zero blocks are
+// skipped.
 struct TsOut {
     float *out32 = nullptr; int64_t ld32 = 0;
     double *out64 = nullptr; int64_t ld64 = 0;
@@ -288,7 +290,7 @@ struct TsOut {
     int Lpad = 0; int64_t rows_pad = 0;
 };
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
-                         const double *T, int m, const double *colscale, const TsOut &out);
+                         const double *T, int m, const double *colscale, const TsOut &out, bool t_upper = false);
 // out = X T with X the frames read as the column-major M x N count matrix (FP64
 // accumulation of exact products), T column-major N x m, optional column scale.
 xpcs_status launch_tsmul_counts(xpcs_ctx *ctx, const void *frames, int dtype, int64_t M, int64_t N,

@@ -5,6 +5,8 @@
 // tall x small products that assemble the basis.
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace xpcs {
@@ -798,6 +800,252 @@ __global__ __launch_bounds__(256) void tsmul_kernel(const TA *__restrict__ A, in
         }
     }
 }
+
+// ---------------------------------------------------------------- tall x small product on the FP64 MFMA
+// out = A T computed as out^T = T^T A^T with v_mfma_f64_16x16x4: the MFMA's rows are
+// 16 output columns (T^T, from LDS), its columns 16 rows of A.  A wave owns strips
+// of 16 SUB rows: lane l reads rows SUB (l % 16) .. SUB (l % 16) + SUB - 1 of inner
+// index k + l / 16 in one load, so the SUB components feed SUB MFMA column sets (rows
+// SUB i + s) that share every T fragment, and the results leave as stores of SUB
+// consecutive rows of one output column.  The loads of the next AH 4-deep inner
+// groups are in flight while a group is multiplied.  A block stages up to kTsmK
+// rows of T for one group of kTsmCols output columns (blockIdx.y), in MFMA fragment
+// order, and its waves walk the strips.  For an upper triangular T (the inverse
+// Cholesky factors) the 4 x 16 blocks below the diagonal are zero: their products
+// and the rows of A that only meet them are skipped.  The products are FP64
+// throughout (A entries are exact in FP64).
+constexpr int kTsmCols = 80;
+constexpr int kTsmTiles = kTsmCols / 16;
+constexpr int kTsmK = 96;
+enum : int { kTsmVecA = 1, kTsmVec32 = 2, kTsmVec64 = 4, kTsmVecH = 8, kTsmVecF8 = 16 };
+
+// SUB consecutive elements at p (vector access when vec; the caller guarantees the
+// alignment of SUB elements)
+template <typename U, int SUB>
+__device__ __forceinline__ void tsm_ld(const U *p, U (&x)[SUB]) {
+    if constexpr (sizeof(U) * SUB <= 16) {
+        using V = U __attribute__((ext_vector_type(SUB)));
+        const V q = *reinterpret_cast<const V *>(p);
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) x[s] = q[s];
+    } else {
+        using V = U __attribute__((ext_vector_type(SUB / 2)));
+        const V q0 = reinterpret_cast<const V *>(p)[0], q1 = reinterpret_cast<const V *>(p)[1];
+#pragma unroll
+        for (int s = 0; s < SUB / 2; ++s) {
+            x[s] = q0[s];
+            x[s + SUB / 2] = q1[s];
+        }
+    }
+}
+template <typename U, int SUB>
+__device__ __forceinline__ void tsm_st(U *p, const U (&x)[SUB], bool vec, int nvalid) {
+    if (vec && nvalid >= SUB) {
+        if constexpr (sizeof(U) * SUB <= 16) {
+            using V = U __attribute__((ext_vector_type(SUB)));
+            V q;
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) q[s] = x[s];
+            *reinterpret_cast<V *>(p) = q;
+        } else {
+            using V = U __attribute__((ext_vector_type(SUB / 2)));
+            V q0, q1;
+#pragma unroll
+            for (int s = 0; s < SUB / 2; ++s) {
+                q0[s] = x[s];
+                q1[s] = x[s + SUB / 2];
+            }
+            reinterpret_cast<V *>(p)[0] = q0;
+            reinterpret_cast<V *>(p)[1] = q1;
+        }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < SUB; ++s)
+        if (s < nvalid) p[s] = x[s];
+}
+
+template <typename TA, bool NARROW, int SUB, int W, int WPE, int AH>
+__global__ __launch_bounds__(64 * W, WPE) void tsmul_mfma_kernel(
+    const TA *__restrict__ A, int64_t rows, int64_t lda, int n, const double *__restrict__ T, int m, int upper,
+    const double *__restrict__ colscale, float *out32, int64_t ld32, double *out64, int64_t ld64,
+    unsigned short *hi, unsigned short *lo, uint8_t *f8, int64_t ldh, int Lpad, int64_t rows_pad, int64_t span,
+    int vflags) {
+    constexpr int RS = 16 * SUB;                      // rows per strip
+    // T in MFMA fragment order: the operand of inner group g and column tile c for
+    // lane l, T[k0 + 4 g + l / 16][j0 + 16 c + l % 16], at (g * kTsmTiles + c) * 64 + l
+    __shared__ double Ts[kTsmK * kTsmCols];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int j0 = blockIdx.y * kTsmCols;
+    const int ncg = m - j0 < kTsmCols ? m - j0 : kTsmCols;
+    const int nct = (ncg + 15) / 16;
+    // inner indices that meet this group: all of them, or (upper) those up to its last column
+    const int kend = upper && j0 + ncg < n ? j0 + ncg : n;
+    const int nchunks = (kend + kTsmK - 1) / kTsmK;
+    const int64_t nstrips = (span + RS - 1) / RS;
+    const bool vec_a = vflags & kTsmVecA;
+    for (int64_t sb = (int64_t)blockIdx.x * W; sb < nstrips; sb += (int64_t)gridDim.x * W) {
+        const int64_t r0 = (sb + wv) * RS;
+        const bool live = sb + wv < nstrips;
+        const int64_t row = r0 + SUB * li;           // this lane's first row
+        const bool full = vec_a && r0 + RS <= rows;
+        f64x4 acc[kTsmTiles][SUB];
+#pragma unroll
+        for (int c = 0; c < kTsmTiles; ++c)
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) acc[c][s] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int k0 = ch * kTsmK;
+            const int kc = kend - k0 < kTsmK ? kend - k0 : kTsmK;
+            if (nchunks > 1 || sb == (int64_t)blockIdx.x * W) {
+                __syncthreads();
+                for (int idx = threadIdx.x; idx < kTsmK * kTsmCols; idx += 64 * W) {
+                    const int l = idx & 63, gc = idx >> 6;
+                    const int i = 4 * (gc / kTsmTiles) + (l >> 4), jj = 16 * (gc % kTsmTiles) + (l & 15);
+                    Ts[idx] = i < kc && jj < ncg ? T[(int64_t)(j0 + jj) * n + k0 + i] : 0.0;
+                }
+                __syncthreads();
+            }
+            if (!live || rows <= 0) continue;         // (rows <= 0: only padding rows, nothing to read)
+            const int ng = (kc + 3) / 4;
+            // the loads are unconditional (indices clamped into the matrix) and the
+            // values outside it are replaced by zeros when used, so no branch splits
+            // the loads in flight
+            int64_t rc[SUB];
+            bool ok[SUB];
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+                ok[s] = row + s < rows;
+                rc[s] = ok[s] ? row + s : rows - 1;
+            }
+            const TA *Ak = A + (int64_t)k0 * lda;
+            auto kloop = [&](auto full_c) {
+                constexpr bool F = decltype(full_c)::value;
+                auto fetch = [&](int g, TA (&x)[SUB]) {
+                    const int kk = 4 * g + lk < kc ? 4 * g + lk : kc - 1;
+                    const TA *p = Ak + (int64_t)kk * lda;
+                    if constexpr (F) {
+                        tsm_ld<TA, SUB>(p + row, x);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < SUB; ++s) x[s] = p[rc[s]];
+                    }
+                };
+                // the chunk's inner groups fully unrolled (static ring slots, so each
+                // group waits for its own loads only)
+                constexpr int kG = kTsmK / 4;
+                TA ring[AH][SUB];
+#pragma unroll
+                for (int u = 0; u < AH; ++u) fetch(u, ring[u]);
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    if (g >= ng) break;
+                    const int u = g % AH;
+                    const bool kv = 4 * g + lk < kc;
+                    double a[SUB];
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) a[s] = kv && (F || ok[s]) ? (double)ring[u][s] : 0.0;
+                    if (g + AH < kG) fetch(g + AH, ring[u]);
+                    const int kg = k0 + 4 * g;
+                    const int cmin = upper && kg > j0 ? (kg - j0) / 16 : 0;
+                    const double *tf = Ts + g * (kTsmTiles * 64) + lane;
+                    double t[kTsmTiles];
+#pragma unroll
+                    for (int c = 0; c < kTsmTiles; ++c) t[c] = tf[64 * c];
+#pragma unroll
+                    for (int c = 0; c < kTsmTiles; ++c) {
+                        if (c < cmin || c >= nct) continue;
+#pragma unroll
+                        for (int s = 0; s < SUB; ++s)
+                            acc[c][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(t[c], a[s], acc[c][s], 0, 0, 0);
+                    }
+                }
+            };
+            if (full) kloop(std::true_type{});
+            else kloop(std::false_type{});
+        }
+        if (!live) continue;
+        // acc[c][s][v]: column j0 + 16 c + lk + 4 v, row r0 + SUB li + s.  The column
+        // offsets are recomputed per strip (kept out of registers across the loop).
+        int64_t l32 = ld32, l64 = ld64, lh = ldh;
+        const double *cs = colscale;
+        int lkx = lk;
+        asm volatile("" : "+s"(l32), "+s"(l64), "+s"(lh), "+s"(cs), "+v"(lkx));
+        const int nv = rows - row < SUB ? (int)(rows - row) : SUB;          // valid rows of this lane
+        const int nvp = rows_pad - row < SUB ? (int)(rows_pad - row) : SUB; // valid padded rows
+#pragma unroll
+        for (int c = 0; c < kTsmTiles; ++c) {
+            if (c >= nct) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int jl = 16 * c + lkx + 4 * v;
+                if (jl >= ncg) continue;
+                const int j = j0 + jl;
+                const double sc = cs ? cs[j] : 1.0;
+                double x[SUB];
+#pragma unroll
+                for (int s = 0; s < SUB; ++s) x[s] = acc[c][s][v] * sc;
+                if (out32 && nv > 0) {
+                    float y[SUB];
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) y[s] = (float)x[s];
+                    tsm_st<float, SUB>(out32 + (int64_t)j * l32 + row, y, vflags & kTsmVec32, nv);
+                }
+                if (out64 && nv > 0) tsm_st<double, SUB>(out64 + (int64_t)j * l64 + row, x, vflags & kTsmVec64, nv);
+                if (NARROW && nvp > 0) {
+                    const int64_t off = (int64_t)j * lh + row;
+                    if (hi) {
+                        unsigned short h[SUB], l[SUB];
+#pragma unroll
+                        for (int s = 0; s < SUB; ++s) {
+                            h[s] = f32_to_bf16_bits((float)x[s]);
+                            l[s] = f32_to_bf16_bits((float)(x[s] - (double)bf16_bits_to_f32(h[s])));
+                        }
+                        tsm_st<unsigned short, SUB>(hi + off, h, vflags & kTsmVecH, nvp);
+                        if (lo) tsm_st<unsigned short, SUB>(lo + off, l, vflags & kTsmVecH, nvp);
+                    }
+                    if (f8) {
+                        uint8_t e[SUB];
+#pragma unroll
+                        for (int s = 0; s < SUB; s += 2) {
+                            const uint32_t q =
+                                __builtin_amdgcn_cvt_pk_fp8_f32((float)x[s] * 256.f, (float)x[s + 1] * 256.f, 0, false);
+                            e[s] = (uint8_t)(q & 0xff);
+                            e[s + 1] = (uint8_t)((q >> 8) & 0xff);
+                        }
+                        tsm_st<uint8_t, SUB>(f8 + off, e, vflags & kTsmVecF8, nvp);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // zero columns [m, Lpad) of the padded bf16 / e4m3 rows (last column group)
+        if (NARROW && blockIdx.y == gridDim.y - 1 && nvp > 0) {
+            for (int j = m + lkx; j < Lpad; j += 4) {
+                const int64_t off = (int64_t)j * lh + row;
+#pragma unroll
+                for (int s = 0; s < SUB; ++s)
+                    if (s < nvp) {
+                        if (hi) hi[off + s] = 0;
+                        if (lo) lo[off + s] = 0;
+                        if (f8) f8[off + s] = 0;
+                    }
+            }
+        }
+    }
+}
+
+// launch shapes (measured at 262,144 x 80 fp32 rows): rows per strip 16 SUB, waves
+// per block W, waves per SIMD WPE, inner groups loaded ahead AH, blocks per CU BPC
+template <typename TA>
+struct TsmShape {
+    static constexpr int SUB = 4, W = 8, WPE = 2, AH = 2, BPC = 1;
+};
+template <>
+struct TsmShape<double> {       // the FP64 rows (the frame side): fewer rows, more strips
+    static constexpr int SUB = 2, W = 4, WPE = 2, AH = 4, BPC = 2;
+};
 
 // ---------------------------------------------------------------- Jacobi eigensolver
 // Parallel-order (round-robin) cyclic Jacobi on a symmetric n x n matrix, n even.
@@ -1740,18 +1988,36 @@ xpcs_status launch_chol_batched(xpcs_ctx *ctx, const double *G, int n, int nb, d
 }
 
 xpcs_status launch_tsmul(xpcs_ctx *ctx, const void *A, bool a_f64, int64_t rows, int64_t lda, int n,
-                         const double *T, int m, const double *colscale, const TsOut &out) {
+                         const double *T, int m, const double *colscale, const TsOut &out, bool t_upper) {
     Phase phase_(ctx, "tsmul");
     const int64_t span = (out.hi || out.f8) && out.rows_pad > rows ? out.rows_pad : rows;
-    dim3 grid((unsigned)((span + 256 * kTsRows - 1) / (256 * kTsRows)), (unsigned)((m + kTsCols - 1) / kTsCols));
+    if (span <= 0 || m <= 0) return XPCS_OK;
+    auto al = [](const void *p, size_t b) { return (reinterpret_cast<uintptr_t>(p) & (b - 1)) == 0; };
+    auto go = [&](auto ta, auto narrow_c) {
+        using TA = decltype(ta);
+        using S = TsmShape<TA>;
+        constexpr int SUB = S::SUB;
+        int vf = 0;
+        if (al(A, SUB * sizeof(TA) < 16 ? SUB * sizeof(TA) : 16) && lda % SUB == 0) vf |= kTsmVecA;
+        if (out.out32 && al(out.out32, SUB * 4 < 16 ? SUB * 4 : 16) && out.ld32 % SUB == 0) vf |= kTsmVec32;
+        if (out.out64 && al(out.out64, 16) && out.ld64 % SUB == 0) vf |= kTsmVec64;
+        if ((!out.hi || al(out.hi, SUB * 2)) && (!out.lo || al(out.lo, SUB * 2)) && out.ldh % SUB == 0) vf |= kTsmVecH;
+        if (out.f8 && al(out.f8, SUB) && out.ldh % SUB == 0) vf |= kTsmVecF8;
+        const int gy = (m + kTsmCols - 1) / kTsmCols;
+        const int64_t nstrips = (span + 16 * SUB - 1) / (16 * SUB);
+        const int64_t want = (nstrips + S::W - 1) / S::W;
+        const int64_t cap = (S::BPC * 256 + gy - 1) / gy;
+        dim3 grid((unsigned)(want < cap ? want : cap), (unsigned)gy);
+        hipLaunchKernelGGL((tsmul_mfma_kernel<TA, decltype(narrow_c)::value, SUB, S::W, S::WPE, S::AH>), grid,
+                           dim3(64 * S::W), 0, ctx->stream, static_cast<const TA *>(A), rows, lda, n, T, m,
+                           (int)t_upper, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.f8,
+                           out.ldh, out.Lpad, out.rows_pad, span, vf);
+    };
+    const bool narrow = out.hi || out.f8;
     if (a_f64)
-        hipLaunchKernelGGL(tsmul_kernel<double>, grid, dim3(256), 0, ctx->stream, static_cast<const double *>(A), rows,
-                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.f8,
-                           out.ldh, out.Lpad, out.rows_pad);
+        narrow ? go(double(), std::true_type{}) : go(double(), std::false_type{});
     else
-        hipLaunchKernelGGL(tsmul_kernel<float>, grid, dim3(256), 0, ctx->stream, static_cast<const float *>(A), rows,
-                           lda, n, T, m, colscale, out.out32, out.ld32, out.out64, out.ld64, out.hi, out.lo, out.f8,
-                           out.ldh, out.Lpad, out.rows_pad);
+        narrow ? go(float(), std::true_type{}) : go(float(), std::false_type{});
     XPCS_LAUNCH_CHECK(ctx, "tsmul");
     return XPCS_OK;
 }
