@@ -212,3 +212,31 @@ def test_raw_wide_accumulation_path(ctx):
     for r in range(2):
         np.testing.assert_array_equal(gram[r], O.raw_gram(F, labels, r))
         np.testing.assert_allclose(C[r], O.raw_two_time(F, labels, r), rtol=1e-15, atol=0, equal_nan=True)
+
+
+@pytest.mark.parametrize("H,W,N,t0,t1,n_roi,dtype,top", [
+    (200, 200, 77, 5, 70, 12, "u16", 40000),    # 5 pixel bands (the last partial), 16-byte band loads
+    (199, 201, 45, 0, 45, 5, "u8", 255),        # rows of an odd byte length: element band loads
+    (120, 120, 40, 3, 40, 70, "u8", 200),       # more ROIs than the band gather keeps in LDS
+])
+def test_raw_gather_shapes(ctx, H, W, N, t0, t1, n_roi, dtype, top):
+    """The gather into ROI order across several 8,192-pixel bands (the last one
+    partial, a ROI's positions split between bands at unaligned places), a window
+    that starts past frame 0 and spans several 32-frame groups, bright pixels in
+    several bands, and the position-order gather for many ROIs: every Gram bit-exact
+    and C the oracle's normalisation."""
+    import torch
+    from paper_2407_20356_amd import api
+    labels = synth.annular_labels(H, W, n_roi, r_in=1.0)
+    rng = np.random.default_rng(H * W + N)
+    hot_px = [int(p) for p in rng.choice(np.flatnonzero(labels >= 0), size=6, replace=False)]
+    F = _hot_frames(H * W, N, dtype, top, seed=N, hot_px=hot_px)
+    say(f"raw gather {H}x{W} px, frames [{t0}, {t1}) of {N}, {n_roi} ROIs, {dtype} up to {top}")
+    C, g2, npairs, gram = api.correlate_two_time_raw(ctx, to_dev(F), to_dev(labels), n_roi, t0=t0, t1=t1,
+                                                     c_dtype=torch.float64, want_gram=True)
+    ctx.sync()
+    gram, C = to_np(gram), to_np(C)
+    Fw = F[t0:t1]
+    for r in range(n_roi):
+        np.testing.assert_array_equal(gram[r], O.raw_gram(Fw, labels, r), err_msg=f"Gram roi {r}")
+        np.testing.assert_allclose(C[r], O.raw_two_time(Fw, labels, r), rtol=1e-15, atol=0, equal_nan=True)
