@@ -512,11 +512,14 @@ __device__ __forceinline__ void raw_tile_epilogue_wave(const i32x4 (&acc)[8][8],
                                                        OutT *C, int64_t ldc, bool vec, int64_t *Gr,
                                                        double *g2p, int *g2c) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    double scol[8];
+    // C = npix G / (S_i S_j) as npix G (1 / S_i) (1 / S_j): one division per row and
+    // per column instead of one per element (a few ulp from the quotient)
+    double rcol[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         const int64_t j = j0 + 16 * b + lr;
-        scol[b] = j < nw ? (double)Sr[j] : 0.0;
+        const double sj = j < nw ? (double)Sr[j] : 0.0;
+        rcol[b] = sj > 0.0 ? 1.0 / sj : __builtin_nan("");
     }
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
     int dcnt[4] = {0, 0, 0, 0};
@@ -530,12 +533,11 @@ __device__ __forceinline__ void raw_tile_epilogue_wave(const i32x4 (&acc)[8][8],
                 const int rl = 16 * ah + 4 * lg + e;
                 const int64_t i = i0 + kEpiRows * qr + rl;
                 const double si = i < nw ? (double)Sr[i] : 0.0;
+                const double ri = si > 0.0 ? npix / si : __builtin_nan("");
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {
                     const int g = acc[2 * qr + ah][b][e];
-                    const double sj = scol[b];
-                    st[rl * kPitch + 16 * b + lr] =
-                        (si > 0.0 && sj > 0.0) ? (npix * (double)g) / (si * sj) : __builtin_nan("");
+                    st[rl * kPitch + 16 * b + lr] = ((double)g * ri) * rcol[b];
                     if constexpr (GRAM) {
                         // the exact Gram (a verification output), mirrored
                         const int64_t j = j0 + 16 * b + lr;

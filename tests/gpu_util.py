@@ -20,6 +20,21 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
+def assert_f32_within_ulp(C, Cref64, what="C", ulp=1):
+    """FP32 C against the oracle's FP64 value rounded to FP32: NaN where the oracle
+    has NaN, else within `ulp` FP32 units (the raw normalisation is evaluated in
+    FP64 to a few FP64 ulp, so its FP32 rounding can land on the neighbouring
+    FP32 number)."""
+    C = np.asarray(C, dtype=np.float32)
+    ref = np.asarray(Cref64).astype(np.float32)
+    nan = np.isnan(ref)
+    np.testing.assert_array_equal(np.isnan(C), nan, err_msg=f"{what}: NaN pattern")
+    d = np.abs(C[~nan].astype(np.float64) - ref[~nan].astype(np.float64))
+    lim = ulp * np.spacing(np.abs(ref[~nan])).astype(np.float64)
+    bad = d > lim
+    assert not bad.any(), f"{what}: {int(bad.sum())} entries beyond {ulp} FP32 ulp, worst {d.max():.3e}"
+
+
 def assert_two_time_close(C, Cref, rtol=1e-3, small=0.1, what="C"):
     """Tolerance of the compressed path: entries with |C*| >= small within rtol
     relative; the remaining entries within rtol in relative Frobenius norm.  NaN

@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import say, to_dev, to_np
+from tests.gpu_util import assert_f32_within_ulp, say, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -140,8 +140,7 @@ def test_raw_hot_roi_beside_super_tiles(ctx):
     ts = np.unique(np.concatenate([[0, 1, 255, 256, 511, 1023, 1024, 2047], np.arange(3, 2048, 97)]))
     for r in range(R):
         Cref = O.raw_two_time(F, labels, r)
-        np.testing.assert_array_equal(np.nan_to_num(C[r][np.ix_(ts, ts)], nan=-7.0),
-                                      np.nan_to_num(Cref[np.ix_(ts, ts)].astype(np.float32), nan=-7.0))
+        assert_f32_within_ulp(C[r][np.ix_(ts, ts)], Cref[np.ix_(ts, ts)], what=f"C roi {r}")
         gref, nref = O.g2_from_two_time(Cref)
         np.testing.assert_array_equal(npairs[r], nref)
         np.testing.assert_allclose(g2[r], gref, rtol=1e-6, equal_nan=True)

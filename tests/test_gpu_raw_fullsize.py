@@ -4,8 +4,9 @@ oracle computes from the frames alone:
 
 * 512 x 512 px x 10,000 frames (uint16 counts, all below 128), 36 ROIs, every
   ROI's C in FP32 with fused g2, written with rows padded to 128 bytes as the
-  benchmark writes them: C among 256 sampled frames of every ROI equal to the
-  oracle's value rounded to FP32, and g2 of four ROIs at twelve lags (first,
+  benchmark writes them: C among 256 sampled frames of every ROI within one FP32
+  ulp of the oracle's value rounded to FP32 (the normalisation is FP64 to a few
+  ulp), and g2 of four ROIs at twelve lags (first,
   tile-edge, middle and last lags) against the oracle's lag-by-lag raw g2;
 * 1024 x 1024 px x 20,000 frames (uint8 counts <= 127), three ROIs (inner,
   middle, outer annulus) one call each with the exact int64 Gram and FP64 C:
@@ -20,7 +21,7 @@ import pytest
 
 import oracle as O
 import synth
-from tests.gpu_util import say, to_np
+from tests.gpu_util import assert_f32_within_ulp, say, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -71,8 +72,7 @@ def test_raw_512_fullsize_sampled_c_and_g2():
     say("oracle: exact Gram of the sampled frames, every ROI")
     Fs = _host_frames(frames, ts)
     for r in range(R):
-        ref = O.raw_two_time(Fs, labels, r).astype(np.float32)
-        np.testing.assert_array_equal(np.nan_to_num(Cs[r], nan=-7.0), np.nan_to_num(ref, nan=-7.0))
+        assert_f32_within_ulp(Cs[r], O.raw_two_time(Fs, labels, r), what=f"C roi {r}")
     say("oracle: raw g2 of four ROIs at sampled lags from all frames")
     lags = [0, 1, 2, 5, 127, 128, 129, 1000, 4999, 5000, N - 2, N - 1]
     Fall = _host_frames(frames, np.arange(N))
