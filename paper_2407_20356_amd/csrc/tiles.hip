@@ -523,6 +523,16 @@ __device__ __forceinline__ void raw_tile_epilogue_wave(const i32x4 (&acc)[8][8],
     }
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
     int dcnt[4] = {0, 0, 0, 0};
+    // no NaN in the tile when every frame of its rows and columns has photons: then the
+    // diagonal sums need no per-entry check (same terms, same order)
+    bool has_ph = true;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t i = i0 + 64 * h + lane, j = j0 + 64 * h + lane;
+        if (i < nw && !(Sr[i] > 0)) has_ph = false;
+        if (j < nw && !(Sr[j] > 0)) has_ph = false;
+    }
+    const bool nan_free = __all(has_ph);
 #pragma unroll
     for (int qr = 0; qr < 4; ++qr) {
         // stage rows [32 qr, 32 qr + 32) of the tile
@@ -600,11 +610,17 @@ __device__ __forceinline__ void raw_tile_epilogue_wave(const i32x4 (&acc)[8][8],
                 if (i0 + r_hi > nw) r_hi = (int)(nw - i0);             // rows inside the window
                 const int64_t c_lim = nw - j0 - d;                     // and columns
                 if (r_hi > c_lim) r_hi = (int)c_lim;
-                for (int r = r_lo; r < r_hi; ++r) {
-                    const double v = st[(r - r0) * kPitch + r + d];
-                    if (v == v) {
-                        dsum[k] += v;
-                        dcnt[k] += 1;
+                if (nan_free) {
+#pragma unroll 8
+                    for (int r = r_lo; r < r_hi; ++r) dsum[k] += st[(r - r0) * kPitch + r + d];
+                    dcnt[k] += r_hi > r_lo ? r_hi - r_lo : 0;
+                } else {
+                    for (int r = r_lo; r < r_hi; ++r) {
+                        const double v = st[(r - r0) * kPitch + r + d];
+                        if (v == v) {
+                            dsum[k] += v;
+                            dcnt[k] += 1;
+                        }
                     }
                 }
             }
