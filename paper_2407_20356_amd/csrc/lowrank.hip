@@ -18,12 +18,12 @@ constexpr int kZChunk = 16;                 // rows of L_R staged at a time
 constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
 constexpr int kZMaxK = 192;                 // widest rank of the on-chip Z-row kernel
 
-// Z[t][j] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] sigma_a L[a][j] in FP64 (zero
-// where S = 0).  W = V diag(sigma) is shared by every ROI, so a block stages a
-// 64-frame slice of it in LDS once and forms Z for kZRois ROIs in turn; lane =
-// frame, wave w owns columns [w CW, (w + 1) CW), rows of L_R are staged kZChunk at
-// a time (prefetched into registers across steps) and read as wave-wide
-// broadcasts.  BF = false stores every column as a contiguous run of 64 frames
+// Z[t][j] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] (sigma_a L[a][j]) in FP64 (zero
+// where S = 0).  V is shared by every ROI, so a block stages a 64-frame slice of it
+// in LDS once (fp32, as stored: the LDS then holds three blocks per CU) and forms Z
+// for kZRois ROIs in turn; lane = frame, wave w owns columns [w CW, (w + 1) CW),
+// rows of L_R are staged kZChunk at a time, scaled by sigma (prefetched into
+// registers across steps) and read as wave-wide broadcasts.  BF = false stores every column as a contiguous run of 64 frames
 // (FP64); BF = true stores each frame's CW columns as 16-byte pieces of bf16 hi
 // and lo.
 template <int CW, bool BF>
@@ -35,9 +35,9 @@ __global__ __launch_bounds__(256) void z_rows_kernel(
     extern __shared__ double zsm[];
     constexpr int kw = 4 * CW;                        // columns covered (>= k)
     constexpr int kPre = kZChunk * kw / 256;          // chunk elements per thread
-    double *wT = zsm;                                 // [k][kZFrames]
-    double *Lc = wT + (size_t)k * kZFrames;           // [kZChunk][kw]
+    double *Lc = zsm;                                 // [kZChunk][kw]
     double *fscale = Lc + (size_t)kZChunk * kw;       // [kZRois][kZFrames]
+    float *vT = reinterpret_cast<float *>(fscale + (size_t)kZRois * kZFrames);   // [k][kZFrames]
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void z_rows_kernel(
     for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
         const int a = idx / kZFrames, f = idx % kZFrames;
         const int64_t tl = f0 + f;
-        wT[idx] = tl < n ? (double)V[(int64_t)a * N + t0 + tl] * sigma[a] : 0.0;
+        vT[idx] = tl < n ? V[(int64_t)a * N + t0 + tl] : 0.0f;
     }
     for (int idx = threadIdx.x; idx < nrb * kZFrames; idx += 256) {
         const int q = idx / kZFrames, f = idx % kZFrames;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void z_rows_kernel(
         for (int i = 0; i < kPre; ++i) {
             const int idx = threadIdx.x + 256 * i;
             const int aa = idx / kw, b = idx % kw;
-            pre[i] = (a0 + aa < k && b < k) ? L[(int64_t)(a0 + aa) * k + b] : 0.0;
+            pre[i] = (a0 + aa < k && b < k) ? sigma[a0 + aa] * L[(int64_t)(a0 + aa) * k + b] : 0.0;
         }
     };
     load(0);
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void z_rows_kernel(
         const int na = min(kZChunk, k - a0);
         const double *lw = Lc + wave * CW;
         for (int aa = 0; aa < na; ++aa) {
-            const double x = wT[(a0 + aa) * kZFrames + lane];
+            const double x = (double)vT[(a0 + aa) * kZFrames + lane];
 #pragma unroll
             for (int m = 0; m < CW; m += 2) {
                 const double2 l = *reinterpret_cast<const double2 *>(lw + aa * kw + m);
@@ -246,7 +246,8 @@ xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr
     if (bf && (!z_hi || !z_lo || !valid || kp != 32 * ((f->k + 31) / 32)))
         return fail(ctx, XPCS_EINVAL, "internal: split-bf16 Z rows need hi, lo, valid and kp = k rounded to 32");
     const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
-    const size_t lds = ((size_t)f->k * kZFrames + (size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double);
+    const size_t lds = ((size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double) +
+                       (size_t)f->k * kZFrames * sizeof(float);
     dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)((nb + kZRois - 1) / kZRois));
 #define XPCS_Z(c)                                                                                                \
     case c:                                                                                                      \
