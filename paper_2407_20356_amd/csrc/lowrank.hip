@@ -17,123 +17,10 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bool ok_frame(int64_t t, int64_t n) { return t < n; }
+constexpr int kZFrames = 64;                // frames per block of the wide kernel
+constexpr int kZMaxK = 192;                 // widest rank of the on-chip (MFMA) Z-row kernel
 
-constexpr int kZFrames = 64;                // frames per block
-constexpr int kZChunk = 16;                 // rows of L_R staged at a time
-constexpr int kZRois = 6;                   // ROIs formed per block from one slice of W
-constexpr int kZMaxK = 192;                 // widest rank of the on-chip Z-row kernel
-
-// Z[t][j] = sqrt(|R|) / S[t0+t] * sum_a V[t0+t][a] (sigma_a L[a][j]) in FP64 (zero
-// where S = 0).  V is shared by every ROI, so a block stages a 64-frame slice of it
-// in LDS once (fp32, as stored: the LDS then holds three blocks per CU) and forms Z
-// for kZRois ROIs in turn; lane = frame, wave w owns columns [w CW, (w + 1) CW),
-// rows of L_R are staged kZChunk at a time, scaled by sigma (prefetched into
-// registers across steps) and read as wave-wide broadcasts.  BF = false stores every column as a contiguous run of 64 frames
-// (FP64); BF = true stores each frame's CW columns as 16-byte pieces of bf16 hi
-// and lo.
-template <int CW, bool BF>
-__global__ __launch_bounds__(256) void z_rows_kernel(
-    const float *__restrict__ V, const double *__restrict__ sigma, const int64_t *__restrict__ roi_sum,
-    const int64_t *__restrict__ roi_npix, const double *__restrict__ Lr, int64_t N, int k, int r0, int nb,
-    int64_t t0, int64_t n, double *__restrict__ z, unsigned short *__restrict__ z_hi,
-    unsigned short *__restrict__ z_lo, int kp, unsigned char *__restrict__ valid) {
-    extern __shared__ double zsm[];
-    constexpr int kw = 4 * CW;                        // columns covered (>= k)
-    constexpr int kPre = kZChunk * kw / 256;          // chunk elements per thread
-    double *Lc = zsm;                                 // [kZChunk][kw]
-    double *fscale = Lc + (size_t)kZChunk * kw;       // [kZRois][kZFrames]
-    float *vT = reinterpret_cast<float *>(fscale + (size_t)kZRois * kZFrames);   // [k][kZFrames]
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t f0 = (int64_t)blockIdx.x * kZFrames;
-    const int slot0 = blockIdx.y * kZRois;
-    const int nrb = min(nb - slot0, kZRois);
-    for (int idx = threadIdx.x; idx < k * kZFrames; idx += 256) {
-        const int a = idx / kZFrames, f = idx % kZFrames;
-        const int64_t tl = f0 + f;
-        vT[idx] = tl < n ? V[(int64_t)a * N + t0 + tl] : 0.0f;
-    }
-    for (int idx = threadIdx.x; idx < nrb * kZFrames; idx += 256) {
-        const int q = idx / kZFrames, f = idx % kZFrames;
-        const int roi = r0 + slot0 + q;
-        const int64_t tl = f0 + f;
-        const int64_t sv = tl < n ? roi_sum[(int64_t)roi * N + t0 + tl] : 0;
-        fscale[idx] = sv > 0 ? sqrt((double)roi_npix[roi]) / (double)sv : 0.0;
-    }
-    // steps = (ROI, chunk of L_R rows); the next step's chunk is loaded into
-    // registers while the current one is used
-    const int nch = (k + kZChunk - 1) / kZChunk, steps = nrb * nch;
-    double pre[kPre];
-    auto load = [&](int st) {
-        const int q = st / nch, a0 = (st % nch) * kZChunk;
-        const double *L = Lr + (int64_t)(slot0 + q) * k * k;
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int idx = threadIdx.x + 256 * i;
-            const int aa = idx / kw, b = idx % kw;
-            pre[i] = (a0 + aa < k && b < k) ? sigma[a0 + aa] * L[(int64_t)(a0 + aa) * k + b] : 0.0;
-        }
-    };
-    load(0);
-    double acc[CW];
-    for (int st = 0; st < steps; ++st) {
-        const int q = st / nch, a0 = (st % nch) * kZChunk;
-        __syncthreads();                              // the previous step is done with Lc
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) Lc[threadIdx.x + 256 * i] = pre[i];
-        __syncthreads();
-        if (st + 1 < steps) load(st + 1);
-        if (a0 == 0) {
-#pragma unroll
-            for (int m = 0; m < CW; ++m) acc[m] = 0.0;
-        }
-        const int na = min(kZChunk, k - a0);
-        const double *lw = Lc + wave * CW;
-        for (int aa = 0; aa < na; ++aa) {
-            const double x = (double)vT[(a0 + aa) * kZFrames + lane];
-#pragma unroll
-            for (int m = 0; m < CW; m += 2) {
-                const double2 l = *reinterpret_cast<const double2 *>(lw + aa * kw + m);
-                acc[m] = fma(x, l.x, acc[m]);
-                acc[m + 1] = fma(x, l.y, acc[m + 1]);
-            }
-        }
-        const int64_t t = f0 + lane;
-        if (a0 + kZChunk >= k && t < n) {              // last chunk of this ROI: store its columns
-            const double sc = fscale[q * kZFrames + lane];
-            const int slot = slot0 + q;
-            if constexpr (BF) {
-                // CW consecutive columns of this frame as 16-byte pieces of hi and lo
-                unsigned short *hrow = z_hi + ((int64_t)slot * n + t) * kp + wave * CW;
-                unsigned short *lrow = z_lo + ((int64_t)slot * n + t) * kp + wave * CW;
-#pragma unroll
-                for (int m0 = 0; m0 < CW; m0 += 8) {
-                    u16x8 h, l;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const double zv = sc * acc[m0 + e];
-                        const unsigned short hb = f32_to_bf16_bits((float)zv);
-                        h[e] = hb;
-                        l[e] = f32_to_bf16_bits((float)(zv - (double)bf16_bits_to_f32(hb)));
-                    }
-                    *reinterpret_cast<u16x8 *>(hrow + m0) = h;
-                    *reinterpret_cast<u16x8 *>(lrow + m0) = l;
-                }
-                if (wave == 0) valid[(int64_t)slot * n + t] = sc > 0.0 ? 1 : 0;
-            } else {
-#pragma unroll
-                for (int m = 0; m < CW; ++m) {
-                    const int j = wave * CW + m;
-                    if (j < k) z[((int64_t)slot * k + j) * n + t] = sc * acc[m];
-                }
-            }
-        }
-    }
-}
-
-
-// The same rows on the FP64 MFMA (ranks up to kZmMaxK): Z_R = diag(sqrt|R| / S_R)
+// Z rows on the FP64 MFMA (ranks up to kZMaxK): Z_R = diag(sqrt|R| / S_R)
 // V (diag(sigma) L_R) computed as its transpose, (diag(sigma) L_R)^T V^T, with
 // v_mfma_f64_16x16x4: the MFMA's rows are 16 columns of Z, its columns 16 frames.
 // blockIdx.z = ROI slot, blockIdx.y = group of kZmCols columns, the block's waves walk
@@ -147,7 +34,6 @@ constexpr int kZmCols = 80;
 constexpr int kZmTiles = kZmCols / 16;
 constexpr int kZmK = 96;                      // rows of diag(sigma) L_R per LDS fill
 constexpr int kZmWaves = 8;
-constexpr int kZmMaxK = 192;
 constexpr int kZmPitch = 17;                  // transpose pitch (32-bit words) against bank conflicts
 
 template <bool BF>
@@ -257,7 +143,7 @@ __global__ __launch_bounds__(64 * kZmWaves, 2) void z_rows_mfma_kernel(
         double fs[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int64_t sv = ok_frame(row + s, n) ? Srow[row + s] : 0;
+            const int64_t sv = row + s < n ? Srow[row + s] : 0;
             fs[s] = sv > 0 ? rn / (double)sv : 0.0;
         }
         if constexpr (BF) {
@@ -448,7 +334,7 @@ xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr
     }
     if (bf && (!z_hi || !z_lo || !valid || kp != 32 * ((f->k + 31) / 32)))
         return fail(ctx, XPCS_EINVAL, "internal: split-bf16 Z rows need hi, lo, valid and kp = k rounded to 32");
-    if (f->k <= kZmMaxK) {
+    {
         if (n <= 0 || nb <= 0) return XPCS_OK;
         const int k = f->k;
         const int gy = ((bf ? kp : k) + kZmCols - 1) / kZmCols;
@@ -467,27 +353,6 @@ xpcs_status launch_z_rows(xpcs_ctx *ctx, const xpcs_factors *f, const double *Lr
         XPCS_LAUNCH_CHECK(ctx, "z_rows_mfma");
         return XPCS_OK;
     }
-    const int cw = 8 * ((f->k + 31) / 32);            // columns per wave, a multiple of 8 >= k / 4
-    const size_t lds = ((size_t)kZChunk * 4 * cw + (size_t)kZRois * kZFrames) * sizeof(double) +
-                       (size_t)f->k * kZFrames * sizeof(float);
-    dim3 grid((unsigned)((n + kZFrames - 1) / kZFrames), (unsigned)((nb + kZRois - 1) / kZRois));
-#define XPCS_Z(c)                                                                                                \
-    case c:                                                                                                      \
-        if (bf)                                                                                                  \
-            hipLaunchKernelGGL((z_rows_kernel<c, true>), grid, dim3(256), lds, ctx->stream, f->V, f->sigma,       \
-                               f->roi_sum, f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z64, z_hi, z_lo, kp, valid); \
-        else                                                                                                     \
-            hipLaunchKernelGGL((z_rows_kernel<c, false>), grid, dim3(256), lds, ctx->stream, f->V, f->sigma,      \
-                               f->roi_sum, f->roi_npix, Lr, f->N, f->k, r0, nb, t0, n, z64, z_hi, z_lo, kp, valid); \
-        break;
-    switch (cw) {
-        XPCS_Z(8) XPCS_Z(16) XPCS_Z(24) XPCS_Z(32) XPCS_Z(40) XPCS_Z(48)
-        default:
-            return fail(ctx, XPCS_EINVAL, "internal: no Z-row kernel for this rank");
-    }
-#undef XPCS_Z
-    XPCS_LAUNCH_CHECK(ctx, "z_rows");
-    return XPCS_OK;
 }
 
 
