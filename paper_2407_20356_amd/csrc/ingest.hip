@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void gather_i8_kernel(const T *__restrict__ fr
 // registers, then once (exact 64-bit atomic) when the ROI changes; hot marks and
 // amax as in the position-order gather.
 constexpr int kBandPx = 8192;
-constexpr int kBandFrames = 64;
+constexpr int kBandFrames = 256;
 constexpr int kBandMaxRoi = 64;
 constexpr int kBandMaxPos = kBandPx + (64 - 1) * kBandMaxRoi;    // pixels plus the last band's padding
 constexpr int kBandMaxUnits = kBandPx / 256 + 2 * kBandMaxRoi + 8;
