@@ -356,6 +356,9 @@ def precision_table(api, torch, dev, steps=3, raw_steps=5):
            "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99), "steps": raw_steps, "warmup": 1,
            "gram_ms": tot_ms / cnt, "gram_int8_TOPs": ops / (tot_ms / cnt / 1e3) / 1e12,
            "gram_frac_of_int8_peak": ops / (tot_ms / cnt / 1e3) / 1e12 / PEAK_I8_TOPS,
+           # the Gram is symmetric and the kernel forms one triangle: on the symmetric
+           # product's count N (N + 1) sum|R| the same time is this fraction of peak
+           "gram_symmetric_frac_of_int8_peak": ops * (N + 1) / (2.0 * N) / (tot_ms / cnt / 1e3) / 1e12 / PEAK_I8_TOPS,
            "phases_ms": {kk: round(v[0] / v[1], 4) for kk, v in ph_all.items()}}
     del C, g2r, npr
     cross = (U["bf16"].double().T @ U["fp8"].double())
@@ -698,6 +701,8 @@ def main():
         ops = 2.0 * N * N * float(npix.sum())
         raw["gram_int8_TOPs"] = ops / (tot_ms / cnt / 1e3) / 1e12
         raw["gram_frac_of_int8_peak"] = raw["gram_int8_TOPs"] / PEAK_I8_TOPS
+        # on the symmetric product's op count N (N + 1) sum|R| (the kernel forms one triangle)
+        raw["gram_symmetric_frac_of_int8_peak"] = raw["gram_frac_of_int8_peak"] * (N + 1) / (2.0 * N)
 
     k128 = None
     if not args.no_k128 and args.workload == "det512_10k_36roi" and k != 128:
