@@ -327,7 +327,12 @@ def precision_table(api, torch, dev, steps=3, raw_steps=5):
         Un = Uh.double().cpu().numpy()
         Ws = Fs @ Un
         Wg = (f.V.T.double().cpu().numpy() * sig[prec])[ts]
+        # compression's bound: four passes over the frames (the sketch, the power pass's two
+        # products and the encoding pass) at peak HBM bandwidth
+        x4 = 4 * M * N * frames.element_size()
         res[prec] = {"compress_ms": ms, "frames_per_s": N / (ms / 1e3),
+                     "compress_algorithmic_bytes": x4,
+                     "compress_hbm_frac": x4 / (PEAK_HBM_GBS * 1e9) * 1e3 / ms,
                      "u_orthonormality": float((Uh.double().T @ Uh.double() - torch.eye(k, device=dev,
                                                                                           dtype=torch.float64))
                                                .abs().max().item()),
@@ -445,9 +450,13 @@ def k128_line(api, torch, ctx, frames, labels_d, n_roi, steps, warmup):
     per, wall = timed_steps(torch, ctx, comp, steps, warmup)
     del C
     torch.cuda.empty_cache()
-    return {"workload": "det512_10k_36roi at k=128", "ms_per_step": 1e3 * wall / steps,
+    ms = 1e3 * wall / steps
+    # the step's bound as for the benchmark step: four passes over the frames and C once
+    step_bytes = 4 * M * N * frames.element_size() + n_roi * N * N * 4
+    return {"workload": "det512_10k_36roi at k=128", "ms_per_step": ms,
             "frames_per_s": N / (wall / steps), "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99),
-            "steps": steps, "warmup": warmup}
+            "steps": steps, "warmup": warmup, "step_algorithmic_bytes": step_bytes,
+            "step_hbm_frac": step_bytes / (PEAK_HBM_GBS * 1e9) * 1e3 / ms}
 
 
 def g2_only(api, torch, ctx, f, reps=5):
