@@ -39,6 +39,44 @@ __device__ __forceinline__ void tile_coords(int64_t id, int nb, int &bi, int &bj
     bj = bi + (int)D;
 }
 
+// The tile a block of the low-rank tile pass takes.  The hardware deals the linear
+// block ids round-robin over the 8 XCDs; here XCD v's blocks take consecutive
+// positions of one range of the (ROI, tile) sequence, and each ROI's tiles go in
+// bands of kOrderRows tile rows, column by column, so that the blocks an XCD runs
+// at once read the Z rows of a few tile rows and columns through its own L2.  tid is
+// the tile's diagonal-major index (as tile_coords), which places its partial sums.
+constexpr int kOrderRows = 8;
+__device__ __forceinline__ void xcd_tile_order(int64_t bx, int64_t by, int64_t nt, int64_t nr, int nb, int &slot,
+                                               int &bi, int &bj, int64_t &tid) {
+    const int64_t T = nt * nr, L = bx + nt * by;
+    const int64_t q = T / 8, r = T % 8, v = L % 8, s = L / 8;
+    const int64_t g = v * q + (v < r ? v : r) + s;       // a bijection of [0, T)
+    slot = (int)(g / nt);
+    int64_t rem = g % nt;
+    int i0 = 0, h = 0;
+    for (;;) {
+        h = nb - i0 < kOrderRows ? nb - i0 : kOrderRows;
+        const int64_t band = (int64_t)h * (h + 1) / 2 + (int64_t)h * (nb - i0 - h);
+        if (rem < band || i0 + h >= nb) break;
+        rem -= band;
+        i0 += h;
+    }
+    const int64_t tri = (int64_t)h * (h + 1) / 2;        // the band's diagonal block, column c holds c + 1 tiles
+    if (rem < tri) {
+        int c = (int)((sqrt(8.0 * (double)rem + 1.0) - 1.0) * 0.5);
+        while (c > 0 && (int64_t)c * (c + 1) / 2 > rem) --c;
+        while ((int64_t)(c + 1) * (c + 2) / 2 <= rem) ++c;
+        bi = i0 + (int)(rem - (int64_t)c * (c + 1) / 2);
+        bj = i0 + c;
+    } else {                                             // then h tiles per column
+        const int64_t r2 = rem - tri;
+        bi = i0 + (int)(r2 % h);
+        bj = i0 + h + (int)(r2 / h);
+    }
+    const int64_t D = bj - bi;
+    tid = D * nb - D * (D - 1) / 2 + bi;
+}
+
 template <typename OutT>
 __device__ __forceinline__ void nt_store(OutT *p, OutT v) {
     __builtin_nontemporal_store(v, p);
@@ -765,9 +803,9 @@ __global__ __launch_bounds__(256, 3) void lowrank_tile_kernel(
     __shared__ __attribute__((aligned(16))) unsigned char smem[kLowrankLds];
     unsigned short *zs = reinterpret_cast<unsigned short *>(smem);   // [array][row 0..255][kZp]
     float *stage = reinterpret_cast<float *>(smem);
-    const int slot = blockIdx.y;
-    int bi, bj;
-    tile_coords(blockIdx.x, nb, bi, bj);
+    int slot, bi, bj;
+    int64_t tile;
+    xcd_tile_order(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, nb, slot, bi, bj, tile);
     const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
     const bool diag = bi == bj;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -887,7 +925,7 @@ __global__ __launch_bounds__(256, 3) void lowrank_tile_kernel(
         epilogue_half<float, OutT, float>(stage, h, i0, j0, diag, nw, Cr, ldc, vec, any_nan, dsum, dcnt);
         __syncthreads();
     }
-    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + blockIdx.x, dsum, dcnt);
+    write_diag_partials(g2_part, g2_cnt, (int64_t)slot * gridDim.x + tile, dsum, dcnt);
 }
 
 // ---------------------------------------------------------------- diagonals of a given matrix
